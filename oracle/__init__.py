@@ -59,7 +59,7 @@ def _load():
     P = C.POINTER
     vp = C.c_void_p
     lib.oracle_analyze.argtypes = [C.c_int64, P(C.c_int64), P(C.c_int32), P(C.c_int32),
-                                   C.c_int32, C.c_int32, C.c_int32, P(vp)]
+                                   C.c_int32, C.c_int32, C.c_int32, C.c_int32, P(vp)]
     lib.oracle_analyze.restype = C.c_int
     lib.oracle_factor.argtypes = [vp, P(C.c_double)]
     lib.oracle_factor.restype = C.c_int
@@ -116,10 +116,12 @@ class Oracle:
     """One matrix: analyze -> factor -> selinv -> get / get_selected / export.
 
     mode 0: symbolic on pattern(PAP^T + (PAP^T)^T) with relaxed, capped
-    supernodes; mode 1: exact non-symmetric structure (small n, no relaxation).
+    supernodes (relaxed subtrees of <= relax columns, chains merged while the
+    padding estimate stays <= pad_pct percent); mode 1: exact non-symmetric
+    structure (small n, no relaxation).
     """
 
-    def __init__(self, n, colptr, rowind, perm=None, max_super=0, relax=0, mode=0):
+    def __init__(self, n, colptr, rowind, perm=None, max_super=0, relax=0, mode=0, pad_pct=0):
         self._lib = _load()
         self._h = C.c_void_p()
         self.n = int(n)
@@ -132,7 +134,7 @@ class Oracle:
             pp = _ptr(self._perm, C.c_int32)
         rc = self._lib.oracle_analyze(self.n, _ptr(self._colptr, C.c_int64),
                                       _ptr(self._rowind, C.c_int32), pp, int(max_super),
-                                      int(relax), int(mode), C.byref(self._h))
+                                      int(relax), int(pad_pct), int(mode), C.byref(self._h))
         if rc:
             raise OracleError(rc, "analyze")
 
@@ -231,8 +233,8 @@ class Oracle:
             pass
 
 
-def selected_inverse(n, colptr, rowind, values, perm=None, max_super=0, relax=0, mode=0):
+def selected_inverse(n, colptr, rowind, values, perm=None, max_super=0, relax=0, mode=0, pad_pct=0):
     """Convenience: returns (Oracle, out) with out[p] = A^{-1}(col p, row p)."""
-    o = Oracle(n, colptr, rowind, perm, max_super, relax, mode)
+    o = Oracle(n, colptr, rowind, perm, max_super, relax, mode, pad_pct)
     o.factor(values).selinv()
     return o, o.get_selected()

@@ -38,9 +38,11 @@
  *       - relaxed: every maximal subtree with at most `relax` nodes (a node v
  *         with size(v) <= relax whose parent has size > relax, or is a root)
  *         is one supernode;
- *       - fundamental: otherwise j-1 and j share a supernode when
- *         parent(j-1) = j, j has exactly one child, and
- *         colcount(j-1) = colcount(j) + 1;
+ *       - chains: otherwise j joins the supernode [f, j-1] when
+ *         parent(j-1) = j, j has exactly one child, and the columns are nearly
+ *         identical: the padding estimate Z of [f, j] (see partition_sym) is at
+ *         most pad_pct percent of its stored entries (pad_pct = 0 gives the
+ *         fundamental supernodes, colcount(j-1) = colcount(j) + 1);
  *       - cap: each supernode is cut into consecutive pieces of at most
  *         `max_super` columns.
  *   mode 1 ("exact"): exact non-symmetric elimination structure from a dense
@@ -395,7 +397,7 @@ static int make_xsup(oracle_t *o, const char *start, int32_t max_super) {
 }
 
 static int partition_sym(oracle_t *o, ilist *cols, const int32_t *parent, int32_t max_super,
-                         int32_t relax) {
+                         int32_t relax, int32_t pad_pct) {
     int64_t n = o->n;
     int32_t *nkids = (int32_t *)calloc((size_t)n + 1, sizeof(int32_t));
     int64_t *size = (int64_t *)malloc(sizeof(int64_t) * (n + 1));
@@ -415,18 +417,31 @@ static int partition_sym(oracle_t *o, ilist *cols, const int32_t *parent, int32_
             for (int64_t u = v - size[v] + 1; u <= v; u++) relroot[u] = (int32_t)v;
         }
     }
+    /* chain merge: j joins the supernode [f, j-1] when j-1's parent is j, j has
+     * no other child, and the padding estimate of [f, j] stays within pad_pct
+     * percent of its stored entries:  with s = j - f + 1 and cnt(t) the number
+     * of off-diagonal entries of column t,
+     *     Z = s cnt(j) - sum_{t=f..j} cnt(t) + s (s - 1) / 2,
+     *     join  iff  100 Z <= pad_pct s (cnt(j) + s).
+     * For identical structures (cnt(t) = cnt(j) + j - t) Z = 0. */
+    int64_t f = 0, sumcnt = 0;
     for (int64_t j = 0; j < n; j++) {
-        if (j == 0) {
-            start[j] = 1;
-            continue;
-        }
-        int join;
-        if (relroot[j] >= 0 || relroot[j - 1] >= 0) {
-            join = relroot[j] >= 0 && relroot[j] == relroot[j - 1];
-        } else {
-            join = parent[j - 1] == j && nkids[j] == 1 && cols[j - 1].n == cols[j].n + 1;
+        int join = 0;
+        if (j > 0) {
+            if (relroot[j] >= 0 || relroot[j - 1] >= 0) {
+                join = relroot[j] >= 0 && relroot[j] == relroot[j - 1];
+            } else if (parent[j - 1] == j && nkids[j] == 1) {
+                int64_t sz = j - f + 1, cj = cols[j].n;
+                int64_t Z = sz * cj - (sumcnt + cj) + sz * (sz - 1) / 2;
+                join = 100 * Z <= (int64_t)pad_pct * sz * (cj + sz);
+            }
         }
         start[j] = !join;
+        if (!join) {
+            f = j;
+            sumcnt = 0;
+        }
+        sumcnt += cols[j].n;
     }
     int rc = make_xsup(o, start, max_super);
     free(nkids);
@@ -590,7 +605,7 @@ static int64_t slot(const oracle_t *o, int64_t r, int64_t c) { return hmap_find(
 /* analyze                                                                  */
 /* ------------------------------------------------------------------------ */
 int oracle_analyze(int64_t n, const int64_t *colptr, const int32_t *rowind, const int32_t *perm,
-                   int32_t max_super, int32_t relax, int32_t mode, oracle_t **out) {
+                   int32_t max_super, int32_t relax, int32_t pad_pct, int32_t mode, oracle_t **out) {
     if (!out) return OR_E_INVALID_ARG;
     *out = NULL;
     oracle_t *o = (oracle_t *)calloc(1, sizeof(oracle_t));
@@ -646,7 +661,7 @@ int oracle_analyze(int64_t n, const int64_t *colptr, const int32_t *rowind, cons
             free_cols(cols, n);
             cols = NULL;
         }
-        if (!rc) rc = partition_sym(o, cols, parent, max_super, relax);
+        if (!rc) rc = partition_sym(o, cols, parent, max_super, relax, pad_pct);
         free_cols(cols, n);
         free(parent);
         free(post);

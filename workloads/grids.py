@@ -36,6 +36,7 @@ class Workload:
     max_super: int
     relax: int
     dims: tuple = ()
+    pad_pct: int = 5
     desc: str = ""
     extra: dict = field(default_factory=dict)
 
