@@ -1,0 +1,203 @@
+/*
+ * selinv.h -- C ABI of the MI355X (gfx950) selected-inversion library.
+ *
+ * Method: supernodal selected inversion of a non-symmetric sparse matrix from
+ * its LU factors (Jacquelin, Lin, Yang, arXiv:1708.04539), Algorithm 1
+ * ("Selected inversion algorithm for a general sparse matrix").  Given a
+ * sparse A and a fill-reducing ordering P, the library factors
+ * At = P A P^T = L U (unpivoted; eq. permuteLU with Q = P^T) and computes every
+ * entry of A^{-1} whose transposed position lies in the block pattern of L+U
+ * (Theorems 1 and 2).  This superset contains the selected set
+ * { A^{-1}(i,j) : A(j,i) != 0 } (eq. sel_entries).
+ *
+ * Call order: selinv_analyze -> selinv_factor -> selinv_run (repeatable) ->
+ * selinv_get / selinv_get_selected / selinv_export.  Out-of-order calls
+ * return SELINV_E_STATE.  No call aborts or exits; every failure is a status
+ * code, and selinv_last_error() gives a message for the handle.
+ *
+ * Conventions
+ *   * Indices are 0-based.  CSC input: colptr[n+1] (int64), rowind[nnz]
+ *     (int32) sorted and unique inside each column, with every diagonal entry
+ *     structurally present; otherwise SELINV_E_BAD_PATTERN.
+ *   * perm[new] = old (perm = NULL means the natural order); the permuted
+ *     matrix is At[a][b] = A[perm[a]][perm[b]].  Not a permutation:
+ *     SELINV_E_BAD_PERM.  The library may replace perm by a postorder of the
+ *     elimination tree of At + At^T; this changes neither the fill nor any
+ *     result.
+ *   * Every input array is copied; the caller may free it on return.  The
+ *     handle owns all host and device memory until selinv_destroy().
+ *   * Device memory is allocated with hipMalloc on the device that is current
+ *     when selinv_factor() is called; later calls must use the same device.
+ *   * Streams: `stream` is a hipStream_t passed as void* (NULL = the null
+ *     stream).  selinv_run() is asynchronous on that stream; the get/export
+ *     calls synchronise it.
+ */
+#ifndef SELINV_H
+#define SELINV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct selinv_handle_s *selinv_handle;
+typedef struct selinv_batch_s *selinv_batch;
+
+typedef enum {
+    SELINV_OK = 0,
+    SELINV_E_INVALID_ARG = 1,  /* null pointer, size or index out of range        */
+    SELINV_E_BAD_PATTERN = 2,  /* CSC not sorted/unique, or missing diagonal      */
+    SELINV_E_BAD_PERM = 3,     /* perm is not a permutation of 0..n-1             */
+    SELINV_E_ZERO_PIVOT = 4,   /* exact zero or non-finite pivot (no pivoting)    */
+    SELINV_E_NOT_SELECTED = 5, /* (i,j) outside the computed superset             */
+    SELINV_E_STATE = 6,        /* call out of order                               */
+    SELINV_E_NOMEM = 7,        /* host or device allocation failed                */
+    SELINV_E_DEVICE = 8        /* HIP runtime error                               */
+} selinv_status;
+
+/* Arithmetic of the run.  Every form keeps the factors, the diagonal-block
+ * inversions (L_KK^{-1}, U_KK^{-1}), the normalisation of step 2 and the
+ * accumulation of the diagonal blocks of step 4 in FP64.
+ *   SELINV_FP64         : all of Algorithm 1 in FP64 (FP64 MFMA).
+ *   SELINV_MIXED_FP32   : off-diagonal blocks of A^{-T} stored in FP32; the
+ *                         products of steps 3-5 on FP32 MFMA.
+ *   SELINV_MIXED_BF16X3 : as MIXED_FP32, but each product is formed from a
+ *                         two-term bfloat16 split of both operands
+ *                         (hi*hi + hi*lo + lo*hi) on BF16 MFMA with FP32
+ *                         accumulation.                                       */
+typedef enum {
+    SELINV_FP64 = 0,
+    SELINV_MIXED_FP32 = 1,
+    SELINV_MIXED_BF16X3 = 2
+} selinv_precision;
+
+/* Supernode partition rules (paper section 2, paragraph on supernodes:
+ * relaxed supernodes with a maximal width).
+ *   max_super : widest supernode; wider ones are cut into consecutive pieces
+ *               of max_super columns (<= 0 or above 1024: 1024, the widest
+ *               block the diagonal-inversion kernel handles).
+ *   relax     : every maximal elimination subtree with at most `relax`
+ *               columns becomes one supernode.
+ *   pad_pct   : outside those subtrees, column j joins the supernode [f, j-1]
+ *               of its only child j-1 while the padding estimate
+ *               Z = s cnt(j) - sum_{t=f..j} cnt(t) + s(s-1)/2  (s = j-f+1,
+ *               cnt = off-diagonal count of a column of L) stays at most
+ *               pad_pct percent of s (cnt(j) + s).  0 gives fundamental
+ *               supernodes; values are clamped to [0, 100].
+ * Padded entries are stored explicitly; their values are still exact entries
+ * of A^{-1}. */
+typedef struct {
+    int32_t max_super;
+    int32_t relax;
+    int32_t pad_pct;
+} selinv_analyze_opts;
+
+typedef struct {
+    int64_t n;          /* matrix order                                          */
+    int64_t nnz_a;      /* stored entries of A                                    */
+    int64_t nnz_lu;     /* entries of the block pattern of L+U (= computed set)  */
+    int32_t nsuper;     /* supernodes                                            */
+    int32_t nlevels;    /* depth of the supernodal elimination tree (+1)         */
+    int32_t max_s;      /* widest supernode                                      */
+    int32_t max_c;      /* largest |R_L(K)| or |R_U(K)|                          */
+    double flops;       /* algorithmic flops of steps 2-5        */
+    double flops_gemm;  /* of which in the products of steps 3-5                 */
+    double bytes_min_fp64; /* algorithmic HBM bytes of one run, FP64 form        */
+    double bytes_min_fp32; /* same with FP32 off-diagonal blocks                 */
+    double max_gemm_flops;  /* flops of the largest single supernode product    */
+    int32_t max_gemm_m, max_gemm_n, max_gemm_k; /* its shape                    */
+} selinv_info;
+
+/* Symbolic analysis (host only).  Builds the elimination tree of At + At^T,
+ * the supernode partition, the block row/column sets R_L(K), R_U(K) of
+ * Algorithm 1, the level sets of the supernodal tree (root at level 0) and
+ * the relative-index maps used by the gather. */
+selinv_status selinv_analyze(int64_t n, const int64_t *colptr, const int32_t *rowind,
+                             const int32_t *perm, const selinv_analyze_opts *opts,
+                             selinv_handle *out);
+
+/* Numerical factorization At = L U without pivoting, FP64, on the host
+ * (setup; OpenMP).  values[] is aligned with rowind[] of selinv_analyze.
+ * The factors are then copied to the current device (one host->device copy).
+ * An exact zero or non-finite pivot gives SELINV_E_ZERO_PIVOT. */
+selinv_status selinv_factor(selinv_handle h, const double *values);
+
+/* Steps 2-5 of Algorithm 1 on the device, asynchronous on `stream`:
+ * diagonal-block inversion and normalisation of every supernode, then one
+ * level of the supernodal tree after another (root first): gather of
+ * A^{-T}(R_L, R_U), the products of steps 3 and 5, and the diagonal block of
+ * step 4.  The factors are left intact, so the call may be repeated. */
+selinv_status selinv_run(selinv_handle h, selinv_precision prec, void *stream);
+
+/* Same as selinv_run for the last completed run, but the sweep is recorded
+ * once into a HIP graph per (handle, precision) and replayed. */
+selinv_status selinv_run_graph(selinv_handle h, selinv_precision prec, void *stream);
+
+/* Batches: several factored handles processed by one level sweep, levels
+ * aligned at the roots (section on inter-supernode parallelism: supernodes
+ * with the same priority run together).  The batch keeps pointers to the
+ * handles; destroy the batch before its handles. */
+selinv_status selinv_batch_create(selinv_handle *hs, int32_t count, selinv_batch *out);
+selinv_status selinv_batch_run(selinv_batch b, selinv_precision prec, void *stream);
+void selinv_batch_destroy(selinv_batch b);
+
+/* A^{-1}(i, j) = At^{-T}(q[j], q[i]), q = perm^{-1} (step 6; eq. unpermute).
+ * Synchronises the run's stream; SELINV_E_NOT_SELECTED when (i, j) is
+ * outside the computed set. */
+selinv_status selinv_get(selinv_handle h, int64_t i, int64_t j, double *out);
+
+/* out[p] = A^{-1}(j, i) for the p-th stored entry (i, j) of A (host buffer of
+ * nnz(A) doubles).  Tr[B A^{-1}] = sum_p B_p out[p] for any B on A's pattern. */
+selinv_status selinv_get_selected(selinv_handle h, double *out);
+
+/* Device version: `out` is a device buffer of nnz(A) doubles; the extraction
+ * kernel runs asynchronously on `stream`. */
+selinv_status selinv_get_selected_device(selinv_handle h, double *out, void *stream);
+
+/* Every computed entry: row[k], col[k], val[k] = A^{-1}(row, col), for k <
+ * info.nnz_lu, in storage order (host buffers). */
+selinv_status selinv_export(selinv_handle h, int32_t *row, int32_t *col, double *val);
+
+/* Structure of the analysis (host buffers; any pointer may be NULL):
+ * perm_out[n] (final ordering, new -> old), xsup[nsuper+1], rl_ptr/ru_ptr
+ * [nsuper+1] (int64), rl/ru (block rows/columns, permuted indices),
+ * level[nsuper]. */
+selinv_status selinv_structure(selinv_handle h, int32_t *perm_out, int32_t *xsup, int64_t *rl_ptr,
+                               int32_t *rl, int64_t *ru_ptr, int32_t *ru, int32_t *level);
+
+selinv_status selinv_query(selinv_handle h, selinv_info *info);
+
+/* Host-only consistency check of the analysis: recomputes the source location
+ * of every entry of every G_K from the relative-index maps (as the gather
+ * kernel does) and compares it with a direct search of the block pattern, and
+ * checks every storage location of A's entries against its array.
+ * *mismatches = 0 when all agree.  Costs O(sum_K |R_L(K)| |R_U(K)|). */
+selinv_status selinv_check_plan(selinv_handle h, int64_t *mismatches);
+
+/* Device-side timing of the last selinv_run, from HIP events recorded on the
+ * run's stream while profiling is on (selinv_set_profiling; not recorded by
+ * selinv_run_graph or batches).  ms[0] diagonal-block inversion, ms[1]
+ * normalisation, ms[2] diagonal initialisation, then for every level d
+ * ms[3+3d] gather, ms[4+3d] products of steps 3 and 5, ms[5+3d] product of
+ * step 4.  count = number of doubles the caller provides. */
+selinv_status selinv_set_profiling(selinv_handle h, int32_t on);
+selinv_status selinv_timings(selinv_handle h, double *ms, int32_t count);
+
+/* Work of one level of the last run's sweep: stats[0] supernodes, [1] widest
+ * supernode, [2] flops of steps 3+5, [3] flops of step 4, [4] entries of G
+ * gathered, [5] gather tiles, [6] product tiles of steps 3+5, [7] of step 4. */
+selinv_status selinv_level_stats(selinv_handle h, int32_t level, double *stats);
+
+/* Message of the last failure on handle h; with h == NULL, of the last failed
+ * selinv_analyze on the calling thread (which then returns *out = NULL). */
+const char *selinv_last_error(selinv_handle h);
+const char *selinv_status_string(selinv_status s);
+void selinv_destroy(selinv_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SELINV_H */

@@ -1,0 +1,465 @@
+// analyze.cpp -- symbolic analysis for supernodal selected inversion.
+//
+// Steps (all on the host, O(|L|) time):
+//   1. validate the CSC pattern and the ordering;
+//   2. adjacency of At + At^T (At = P A P^T);
+//   3. elimination tree by Liu's path-compressed ancestor walk;
+//   4. postorder of that tree (children in increasing order) folded into
+//      the ordering, so that every subtree is a contiguous column range;
+//   5. column counts of L from row subtrees;
+//   6. supernode partition (paper, section 2: relaxed supernodes of nearly
+//      identical columns, capped at a maximal width): maximal subtrees of at
+//      most `relax` columns; chains (parent(j-1) = j, j has one child) whose
+//      padding estimate stays within `pad_pct` percent; cuts every
+//      `max_super` columns;
+//   7. supernodal symbolic factorisation: R(K) = adjacency of K's columns
+//      beyond K, merged with R(C) of every child supernode C;  R_L = R_U = R
+//      for the structurally symmetric pattern used here;
+//   8. levels of the supernodal tree (root at level 0: Algorithm 1 walks
+//      K = N..1, and every supernode on one level depends only on
+//      shallower ones -- section on inter-supernode parallelism);
+//   9. storage offsets, relative-index maps of the gather (Theorem 1: every
+//      entry of A^{-T}(R_L(K), R_U(K)) lies in an ancestor's block), storage
+//      location of every entry of A, and the flop / byte accounting.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "plan.hpp"
+
+namespace selinv {
+
+int64_t Plan::locate(int32_t r, int32_t c) const {
+    int32_t I = supof[r], J = supof[c];
+    if (I == J) {
+        int32_t f = xsup[I], s = width(I);
+        return (LOC_DIAG << LOC_SHIFT) | (off_d[I] + (r - f) + int64_t(c - f) * s);
+    }
+    if (I > J) {
+        const int32_t *b = rl.data() + rl_ptr[J], *e = rl.data() + rl_ptr[J + 1];
+        const int32_t *it = std::lower_bound(b, e, r);
+        if (it == e || *it != r) return -1;
+        return (LOC_L << LOC_SHIFT) | (off_l[J] + (it - b) + int64_t(c - xsup[J]) * cl(J));
+    }
+    const int32_t *b = ru.data() + ru_ptr[I], *e = ru.data() + ru_ptr[I + 1];
+    const int32_t *it = std::lower_bound(b, e, c);
+    if (it == e || *it != c) return -1;
+    return (LOC_U << LOC_SHIFT) | (off_u[I] + (it - b) + int64_t(r - xsup[I]) * cu(I));
+}
+
+namespace {
+
+// adjacency of the symmetric pattern, both triangles, diagonal removed
+void symmetric_adjacency(int64_t n, const int64_t *colptr, const int32_t *rowind,
+                         const std::vector<int32_t> &q, std::vector<int64_t> &ptr,
+                         std::vector<int32_t> &adj) {
+    std::vector<int64_t> cnt(n + 1, 0);
+    for (int64_t j = 0; j < n; j++)
+        for (int64_t k = colptr[j]; k < colptr[j + 1]; k++) {
+            int32_t a = q[rowind[k]], b = q[j];
+            if (a == b) continue;
+            cnt[a + 1]++;
+            cnt[b + 1]++;
+        }
+    for (int64_t i = 0; i < n; i++) cnt[i + 1] += cnt[i];
+    std::vector<int32_t> tmp(cnt[n]);
+    std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
+    for (int64_t j = 0; j < n; j++)
+        for (int64_t k = colptr[j]; k < colptr[j + 1]; k++) {
+            int32_t a = q[rowind[k]], b = q[j];
+            if (a == b) continue;
+            tmp[pos[a]++] = b;
+            tmp[pos[b]++] = a;
+        }
+    ptr.assign(n + 1, 0);
+    adj.clear();
+    adj.reserve(tmp.size());
+    for (int64_t i = 0; i < n; i++) {
+        int32_t *b = tmp.data() + cnt[i], *e = tmp.data() + cnt[i + 1];
+        std::sort(b, e);
+        e = std::unique(b, e);
+        adj.insert(adj.end(), b, e);
+        ptr[i + 1] = adj.size();
+    }
+}
+
+// Liu's algorithm: for each column k, every i < k adjacent to k is walked up
+// (with path compression) to its current root r, which gets parent k.
+void etree(int64_t n, const std::vector<int64_t> &ptr, const std::vector<int32_t> &adj,
+           std::vector<int32_t> &parent) {
+    parent.assign(n, -1);
+    std::vector<int32_t> anc(n, -1);
+    for (int64_t k = 0; k < n; k++) {
+        for (int64_t t = ptr[k]; t < ptr[k + 1]; t++) {
+            int32_t i = adj[t];
+            if (i >= k) continue;
+            while (i != -1 && i != k) {
+                int32_t next = anc[i];
+                anc[i] = (int32_t)k;
+                if (next == -1) parent[i] = (int32_t)k;
+                i = next;
+            }
+        }
+    }
+}
+
+void tree_postorder(int64_t n, const std::vector<int32_t> &parent, std::vector<int32_t> &post) {
+    std::vector<int32_t> head(n, -1), next(n, -1), stack, cur(n);
+    for (int64_t j = n - 1; j >= 0; j--)
+        if (parent[j] >= 0) {
+            next[j] = head[parent[j]];
+            head[parent[j]] = (int32_t)j;
+        }
+    post.clear();
+    post.reserve(n);
+    stack.reserve(n);
+    for (int64_t r = 0; r < n; r++) {
+        if (parent[r] >= 0) continue;
+        stack.push_back((int32_t)r);
+        cur[r] = head[r];
+        while (!stack.empty()) {
+            int32_t v = stack.back();
+            int32_t c = cur[v];
+            if (c >= 0) {
+                cur[v] = next[c];
+                cur[c] = head[c];
+                stack.push_back(c);
+            } else {
+                post.push_back(v);
+                stack.pop_back();
+            }
+        }
+    }
+}
+
+// number of off-diagonal entries in each column of L, from row subtrees
+void column_counts(int64_t n, const std::vector<int64_t> &ptr, const std::vector<int32_t> &adj,
+                   const std::vector<int32_t> &parent, std::vector<int64_t> &count) {
+    count.assign(n, 0);
+    std::vector<int32_t> mark(n, -1);
+    for (int64_t i = 0; i < n; i++) {
+        mark[i] = (int32_t)i;
+        for (int64_t t = ptr[i]; t < ptr[i + 1]; t++) {
+            int32_t k = adj[t];
+            if (k >= i) continue;
+            while (k != -1 && mark[k] != i) {
+                count[k]++;
+                mark[k] = (int32_t)i;
+                k = parent[k];
+            }
+        }
+    }
+}
+
+}  // namespace
+
+selinv_status analyze(Plan &P, int64_t n, const int64_t *colptr, const int32_t *rowind,
+                      const int32_t *perm, int32_t max_super, int32_t relax, int32_t pad_pct,
+                      std::string &err) {
+    if (n < 1 || !colptr || !rowind) {
+        err = "n must be >= 1 and colptr/rowind non-null";
+        return SELINV_E_INVALID_ARG;
+    }
+    if (n >= (int64_t(1) << 31) - 1) {
+        err = "n exceeds the int32 index range";
+        return SELINV_E_INVALID_ARG;
+    }
+    if (colptr[0] != 0) {
+        err = "colptr[0] != 0";
+        return SELINV_E_BAD_PATTERN;
+    }
+    for (int64_t j = 0; j < n; j++) {
+        if (colptr[j + 1] < colptr[j]) {
+            err = "colptr decreases";
+            return SELINV_E_BAD_PATTERN;
+        }
+        bool diag = false;
+        for (int64_t k = colptr[j]; k < colptr[j + 1]; k++) {
+            int32_t r = rowind[k];
+            if (r < 0 || r >= n || (k > colptr[j] && rowind[k - 1] >= r)) {
+                err = "row indices out of range, unsorted or duplicated in column " + std::to_string(j);
+                return SELINV_E_BAD_PATTERN;
+            }
+            diag |= r == j;
+        }
+        if (!diag) {
+            err = "missing diagonal entry in column " + std::to_string(j);
+            return SELINV_E_BAD_PATTERN;
+        }
+    }
+    P.n = n;
+    P.nnz_a = colptr[n];
+    P.a_colptr.assign(colptr, colptr + n + 1);
+    P.a_rowind.assign(rowind, rowind + P.nnz_a);
+    P.p.resize(n);
+    P.q.assign(n, -1);
+    for (int64_t i = 0; i < n; i++) {
+        int32_t v = perm ? perm[i] : (int32_t)i;
+        if (v < 0 || v >= n || P.q[v] >= 0) {
+            err = "perm is not a permutation";
+            return SELINV_E_BAD_PERM;
+        }
+        P.p[i] = v;
+        P.q[v] = (int32_t)i;
+    }
+
+    std::vector<int64_t> aptr;
+    std::vector<int32_t> adj, parent, post;
+    symmetric_adjacency(n, colptr, rowind, P.q, aptr, adj);
+    etree(n, aptr, adj, parent);
+    tree_postorder(n, parent, post);
+    bool ident = true;
+    for (int64_t k = 0; k < n; k++) ident &= post[k] == k;
+    if (!ident) {
+        std::vector<int32_t> np(n);
+        for (int64_t k = 0; k < n; k++) np[k] = P.p[post[k]];
+        P.p = np;
+        for (int64_t k = 0; k < n; k++) P.q[P.p[k]] = (int32_t)k;
+        symmetric_adjacency(n, colptr, rowind, P.q, aptr, adj);
+        etree(n, aptr, adj, parent);
+    }
+
+    // ---- partition -------------------------------------------------------
+    std::vector<int64_t> cnt;
+    column_counts(n, aptr, adj, parent, cnt);
+    std::vector<int32_t> nkids(n, 0), relroot(n, -1);
+    std::vector<int64_t> size(n, 1);
+    for (int64_t j = 0; j < n; j++)
+        if (parent[j] >= 0) {
+            nkids[parent[j]]++;
+            size[parent[j]] += size[j];
+        }
+    for (int64_t v = 0; v < n; v++)
+        if (size[v] <= relax && (parent[v] < 0 || size[parent[v]] > relax))
+            for (int64_t u = v - size[v] + 1; u <= v; u++) relroot[u] = (int32_t)v;
+    // chains of nearly identical columns: j joins [f, j-1] while the padding
+    // estimate Z = s cnt(j) - sum_t cnt(t) + s(s-1)/2 of [f, j] (s = j-f+1) is
+    // at most pad_pct percent of the s (cnt(j) + s) stored entries
+    std::vector<int32_t> starts;
+    int64_t run_first = 0, run_sum = 0;
+    for (int64_t j = 0; j < n; j++) {
+        bool join = false;
+        if (j > 0) {
+            if (relroot[j] >= 0 || relroot[j - 1] >= 0) {
+                join = relroot[j] >= 0 && relroot[j] == relroot[j - 1];
+            } else if (parent[j - 1] == j && nkids[j] == 1) {
+                const int64_t sz = j - run_first + 1;
+                const int64_t Z = sz * cnt[j] - (run_sum + cnt[j]) + sz * (sz - 1) / 2;
+                join = 100 * Z <= int64_t(pad_pct) * sz * (cnt[j] + sz);
+            }
+        }
+        if (!join) {
+            starts.push_back((int32_t)j);
+            run_first = j;
+            run_sum = 0;
+        }
+        run_sum += cnt[j];
+    }
+    starts.push_back((int32_t)n);
+    P.xsup.clear();
+    for (size_t t = 0; t + 1 < starts.size(); t++) {
+        int32_t f = starts[t], e = starts[t + 1];
+        int32_t step = max_super > 0 ? max_super : (e - f);
+        for (int32_t c = f; c < e; c += step) P.xsup.push_back(c);
+    }
+    P.xsup.push_back((int32_t)n);
+    P.ns = (int32_t)P.xsup.size() - 1;
+    P.supof.resize(n);
+    for (int32_t K = 0; K < P.ns; K++)
+        for (int32_t c = P.xsup[K]; c < P.xsup[K + 1]; c++) P.supof[c] = K;
+
+    // ---- supernodal symbolic ------------------------------------------
+    const int32_t ns = P.ns;
+    P.rl_ptr.assign(ns + 1, 0);
+    P.rl.clear();
+    P.sparent.assign(ns, -1);
+    std::vector<std::vector<int32_t>> kids(ns);
+    std::vector<int32_t> mark(n, -1), R;
+    for (int32_t K = 0; K < ns; K++) {
+        int32_t f = P.xsup[K], l = P.xsup[K + 1] - 1;
+        R.clear();
+        for (int32_t j = f; j <= l; j++)
+            for (int64_t t = aptr[j]; t < aptr[j + 1]; t++) {
+                int32_t i = adj[t];
+                if (i > l && mark[i] != K) {
+                    mark[i] = K;
+                    R.push_back(i);
+                }
+            }
+        for (int32_t C : kids[K])
+            for (int64_t t = P.rl_ptr[C]; t < P.rl_ptr[C + 1]; t++) {
+                int32_t i = P.rl[t];
+                if (i > l && mark[i] != K) {
+                    mark[i] = K;
+                    R.push_back(i);
+                }
+            }
+        std::sort(R.begin(), R.end());
+        P.rl.insert(P.rl.end(), R.begin(), R.end());
+        P.rl_ptr[K + 1] = P.rl.size();
+        if (!R.empty()) {
+            P.sparent[K] = P.supof[R[0]];
+            kids[P.sparent[K]].push_back(K);
+        }
+    }
+    P.ru_ptr = P.rl_ptr;
+    P.ru = P.rl;
+
+    // ---- levels ---------------------------------------------------------
+    P.level.assign(ns, 0);
+    P.nlevels = 0;
+    for (int32_t K = ns - 1; K >= 0; K--) {
+        P.level[K] = P.sparent[K] < 0 ? 0 : P.level[P.sparent[K]] + 1;
+        P.nlevels = std::max(P.nlevels, P.level[K] + 1);
+    }
+    P.levels.assign(P.nlevels, {});
+    for (int32_t K = 0; K < ns; K++) P.levels[P.level[K]].push_back(K);
+
+    // ---- storage and accounting -----------------------------------------
+    P.off_d.assign(ns + 1, 0);
+    P.off_l.assign(ns + 1, 0);
+    P.off_u.assign(ns + 1, 0);
+    P.flops = P.flops_gemm = P.bytes64 = P.bytes32 = P.max_gemm_flops = 0;
+    P.max_s = P.max_c = 0;
+    for (int32_t K = 0; K < ns; K++) {
+        double s = P.width(K), cl = (double)P.cl(K), cu = (double)P.cu(K);
+        P.off_d[K + 1] = P.off_d[K] + int64_t(s * s);
+        P.off_l[K + 1] = P.off_l[K] + int64_t(cl * s);
+        P.off_u[K + 1] = P.off_u[K] + int64_t(cu * s);
+        double g = 4 * s * cl * cu + 2 * s * s * cu;
+        P.flops_gemm += g;
+        P.flops += g + s * s * (cl + cu) + 4.0 / 3.0 * s * s * s;
+        double in_out = 8 * s * s + 8 * s * (cl + cu) + 8 * s * s;
+        P.bytes64 += in_out + 8 * s * (cl + cu) + 8 * cl * cu;
+        P.bytes32 += in_out + 4 * s * (cl + cu) + 4 * cl * cu;
+        double big = 2 * s * cl * cu;
+        if (big > P.max_gemm_flops) {
+            P.max_gemm_flops = big;
+            P.max_gemm_m = (int32_t)cl;
+            P.max_gemm_n = (int32_t)s;
+            P.max_gemm_k = (int32_t)cu;
+        }
+        P.max_s = std::max<int32_t>(P.max_s, (int32_t)s);
+        P.max_c = std::max<int32_t>(P.max_c, (int32_t)std::max(cl, cu));
+    }
+    P.tot_d = P.off_d[ns];
+    P.tot_l = P.off_l[ns];
+    P.tot_u = P.off_u[ns];
+
+    // ---- gather maps ------------------------------------------------------
+    P.l_coloff.assign(P.ru.size(), -1);
+    P.u_rowoff.assign(P.rl.size(), -1);
+    P.mapL.clear();
+    P.mapU.clear();
+    for (int32_t K = 0; K < ns; K++) {
+        const int32_t *RL = P.rl.data() + P.rl_ptr[K], *RU = P.ru.data() + P.ru_ptr[K];
+        int64_t cl = P.cl(K), cu = P.cu(K);
+        // L side: for each block J of R_U(K)
+        for (int64_t b = 0; b < cu;) {
+            int32_t J = P.supof[RU[b]];
+            int64_t be = b;
+            while (be < cu && P.supof[RU[be]] == J) be++;
+            int32_t lastJ = P.xsup[J + 1] - 1;
+            int64_t a0 = std::upper_bound(RL, RL + cl, lastJ) - RL;
+            int64_t seg = (int64_t)P.mapL.size();
+            const int32_t *RJ = P.rl.data() + P.rl_ptr[J];
+            int64_t clJ = P.cl(J), t = 0;
+            for (int64_t a = a0; a < cl; a++) {
+                while (t < clJ && RJ[t] < RL[a]) t++;
+                if (t == clJ || RJ[t] != RL[a]) {
+                    err = "closure violated (L side)";
+                    return SELINV_E_BAD_PATTERN;
+                }
+                P.mapL.push_back((int32_t)t);
+            }
+            for (int64_t x = b; x < be; x++) P.l_coloff[P.ru_ptr[K] + x] = seg - a0;
+            b = be;
+        }
+        // U side: for each block I of R_L(K)
+        for (int64_t a = 0; a < cl;) {
+            int32_t I = P.supof[RL[a]];
+            int64_t ae = a;
+            while (ae < cl && P.supof[RL[ae]] == I) ae++;
+            int32_t lastI = P.xsup[I + 1] - 1;
+            int64_t b0 = std::upper_bound(RU, RU + cu, lastI) - RU;
+            int64_t seg = (int64_t)P.mapU.size();
+            const int32_t *RI = P.ru.data() + P.ru_ptr[I];
+            int64_t cuI = P.cu(I), t = 0;
+            for (int64_t b = b0; b < cu; b++) {
+                while (t < cuI && RI[t] < RU[b]) t++;
+                if (t == cuI || RI[t] != RU[b]) {
+                    err = "closure violated (U side)";
+                    return SELINV_E_BAD_PATTERN;
+                }
+                P.mapU.push_back((int32_t)t);
+            }
+            for (int64_t x = a; x < ae; x++) P.u_rowoff[P.rl_ptr[K] + x] = seg - b0;
+            a = ae;
+        }
+    }
+
+    // ---- where the entries of A live --------------------------------------
+    P.a_loc.resize(P.nnz_a);
+    for (int64_t j = 0; j < n; j++)
+        for (int64_t k = colptr[j]; k < colptr[j + 1]; k++) {
+            int64_t loc = P.locate(P.q[rowind[k]], P.q[j]);
+            if (loc < 0) {
+                err = "entry of A outside the symbolic pattern";
+                return SELINV_E_BAD_PATTERN;
+            }
+            P.a_loc[k] = loc;
+        }
+    return SELINV_OK;
+}
+
+// Recompute every source index of the gather exactly as the kernel does (from
+// the relative-index maps) and compare it with an independent binary-search
+// location of the same entry.  Also checks that every location is inside its
+// array.  Returns the number of mismatches (0 = consistent).
+int64_t check_gather_maps(const Plan &P, std::string &err) {
+    int64_t bad = 0;
+    for (int32_t K = 0; K < P.ns; K++) {
+        const int64_t cl = P.cl(K), cu = P.cu(K);
+        const int32_t *RL = P.rl.data() + P.rl_ptr[K], *RU = P.ru.data() + P.ru_ptr[K];
+        for (int64_t b = 0; b < cu; b++) {
+            const int32_t c = RU[b], J = P.supof[c];
+            for (int64_t a = 0; a < cl; a++) {
+                const int32_t r = RL[a], I = P.supof[r];
+                int64_t kind, off;
+                if (I == J) {
+                    kind = LOC_DIAG;
+                    off = P.off_d[J] + int64_t(c - P.xsup[J]) * P.width(J) - P.xsup[J] + r;
+                } else if (I > J) {
+                    const int64_t m = P.l_coloff[P.ru_ptr[K] + b] + a;
+                    if (m < 0 || m >= (int64_t)P.mapL.size()) {
+                        bad++;
+                        continue;
+                    }
+                    kind = LOC_L;
+                    off = P.off_l[J] + int64_t(c - P.xsup[J]) * P.cl(J) + P.mapL[m];
+                } else {
+                    const int64_t m = P.u_rowoff[P.rl_ptr[K] + a] + b;
+                    if (m < 0 || m >= (int64_t)P.mapU.size()) {
+                        bad++;
+                        continue;
+                    }
+                    kind = LOC_U;
+                    off = P.off_u[I] + int64_t(r - P.xsup[I]) * P.cu(I) + P.mapU[m];
+                }
+                const int64_t limit = kind == LOC_DIAG ? P.tot_d : kind == LOC_L ? P.tot_l : P.tot_u;
+                const int64_t want = P.locate(r, c);
+                if (off < 0 || off >= limit || want != ((kind << LOC_SHIFT) | off)) bad++;
+            }
+        }
+    }
+    for (int64_t k = 0; k < P.nnz_a; k++) {
+        const int64_t kind = P.a_loc[k] >> LOC_SHIFT, off = P.a_loc[k] & LOC_MASK;
+        const int64_t limit = kind == LOC_DIAG ? P.tot_d : kind == LOC_L ? P.tot_l : P.tot_u;
+        if (off < 0 || off >= limit) bad++;
+    }
+    if (bad) err = std::to_string(bad) + " inconsistent gather or extraction indices";
+    return bad;
+}
+
+}  // namespace selinv

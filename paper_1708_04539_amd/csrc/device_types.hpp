@@ -1,0 +1,70 @@
+// device_types.hpp -- records shared by the host runtime and the HIP kernels.
+#pragma once
+
+#include <cstdint>
+
+namespace selinv {
+
+// One supernode, as the kernels see it.  Offsets are in elements of the
+// owning array (diag/Zd: off_d; lpan/ZL/Lh: off_l; upan/ZU/Uh: off_u).
+struct SnRec {
+    int32_t f, s, cl, cu;
+    int64_t off_d, off_l, off_u;
+    int64_t rl_off, ru_off;  // into rl / u_rowoff and ru / l_coloff
+    int64_t g_off;           // G_K inside the gather workspace of its level
+};
+
+// One matrix (handle) on the device; every pointer is a device address.
+struct MatDev {
+    const SnRec *sn;
+    const int32_t *supof;
+    const int32_t *rl, *ru;
+    const int64_t *l_coloff, *u_rowoff;
+    const int32_t *mapL, *mapU;
+    const double *Zd;  // A^{-T} diagonal blocks (FP64 in every form)
+    const void *ZL;    // A^{-T}(R_L, K) panels, FP64 or FP32
+    const void *ZU;    // A^{-T}(K, R_U)^T panels, FP64 or FP32
+    void *G;           // gather workspace, FP64 or FP32
+};
+
+// gather: tile of G_K rows [a0, a0+64) x columns [b0, b0+64)
+struct GatherTile {
+    int32_t mat, K, a0, b0;
+};
+
+// C = alpha * op(A) op(B) + beta * Cin, column-major, op = N (0) or T (1)
+struct GemmProb {
+    const void *A;
+    const void *B;
+    void *C;
+    const void *Cin;
+    int32_t M, N, K;
+    int32_t lda, ldb, ldc, ldcin;
+    int32_t opA, opB;
+    int32_t pad;
+    double alpha, beta;
+};
+
+struct GemmTile {
+    int32_t prob, m0, n0, pad;
+};
+
+// triangular inversion of one diagonal block: 4 columns (one per wave)
+struct TriItem {
+    const double *D;  // packed L\U, s x s column-major
+    double *Linv, *Uinv;
+    int32_t s, j0;
+};
+
+// extraction of the selected entries
+struct ExtractArgs {
+    const int64_t *loc;  // kind << 60 | offset per entry of A
+    const double *Zd;
+    const void *ZL, *ZU;
+    double *out;
+    int64_t nnz;
+};
+
+enum Compute : int { CMP_F64 = 0, CMP_F32 = 1, CMP_BF16X3 = 2 };
+
+}  // namespace selinv

@@ -1,0 +1,815 @@
+// runtime.hip -- C ABI of the selected-inversion library (include/selinv.h):
+// handle life cycle, device buffers, per-level work lists and the level sweep.
+//
+// One run (selinv_run) is
+//   tri_inv              (L_KK)^{-1}, (U_KK)^{-1} for every supernode
+//   gemm [F64]           Lhat = L(R_L,K) (L_KK)^{-1},  Uhat^T = U(K,R_U)^T (U_KK)^{-T}
+//   gemm [F64]           A^{-T}(K,K) := (L_KK)^{-T} (U_KK)^{-T}
+//   for level = 0 .. depth-1 (root first; Algorithm 1 walks K = N..1 and a
+//   level depends only on shallower levels):
+//     gather             G_K = A^{-T}(R_L(K), R_U(K))           (all K of the level)
+//     gemm               step 3: A^{-T}(K,R_U)^T = -G_K^T Lhat;  step 5: A^{-T}(R_L,K) = -G_K Uhat^T
+//     gemm               step 4: A^{-T}(K,K) -= A^{-T}(K,R_U) Uhat^T   (FP64 accumulation)
+// All supernodes of a level (and of every matrix of a batch) share one launch
+// per kernel; the work lists are built once per (handle set, precision).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "device_types.hpp"
+#include "kernels.hpp"
+#include "plan.hpp"
+
+using namespace selinv;
+
+namespace {
+
+struct PrecBufs {
+    bool ready = false;
+    double *Zd = nullptr;
+    void *ZL = nullptr, *ZU = nullptr, *Lh = nullptr, *Uh = nullptr, *G = nullptr;
+};
+
+struct Range {
+    int64_t off = 0;
+    int count = 0;
+};
+
+struct Sweep {
+    int prec = 0;
+    MatDev *d_mats = nullptr;
+    TriItem *d_tri = nullptr;
+    GemmProb *d_probs = nullptr;
+    GemmTile *d_tiles = nullptr;
+    GatherTile *d_gt = nullptr;
+    Range tri, norm, dt;
+    std::vector<Range> gat, g35, g4;
+    std::vector<double> lev_flops35, lev_flops4, lev_gather_elems;
+    std::vector<int> lev_nsup, lev_maxs;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    hipStream_t graph_stream = nullptr;
+    ~Sweep() {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipFree(d_mats);
+        (void)hipFree(d_tri);
+        (void)hipFree(d_probs);
+        (void)hipFree(d_tiles);
+        (void)hipFree(d_gt);
+    }
+};
+
+constexpr int NPREC = 3;
+
+inline int elem_bytes(int prec) { return prec == SELINV_FP64 ? 8 : 4; }
+inline int mode_of(int prec) {
+    return prec == SELINV_FP64 ? CMP_F64 : prec == SELINV_MIXED_FP32 ? CMP_F32 : CMP_BF16X3;
+}
+
+}  // namespace
+
+struct selinv_handle_s {
+    Plan P;
+    std::string err;
+    int state = 0;  // 0 analyzed, 1 factored, 2 ran
+    int device = -1;
+    std::vector<SnRec> sn;
+    int64_t g_elems = 0;
+    double *d_diag = nullptr, *d_lpan = nullptr, *d_upan = nullptr, *d_Linv = nullptr, *d_Uinv = nullptr;
+    SnRec *d_sn = nullptr;
+    int32_t *d_supof = nullptr, *d_rl = nullptr, *d_ru = nullptr, *d_mapL = nullptr, *d_mapU = nullptr;
+    int64_t *d_lcol = nullptr, *d_urow = nullptr, *d_aloc = nullptr;
+    PrecBufs pb[NPREC];
+    std::unique_ptr<Sweep> sweep[NPREC];
+    int last_prec = -1;
+    hipStream_t last_stream = nullptr;
+    hipStream_t own_stream = nullptr;
+    bool profiling = false;
+    std::vector<hipEvent_t> events;
+    std::vector<double> times;
+};
+
+struct selinv_batch_s {
+    std::vector<selinv_handle> hs;
+    std::unique_ptr<Sweep> sweep[NPREC];
+    std::string err;
+};
+
+namespace {
+
+selinv_status dev_fail(std::string &err, hipError_t e, const char *what) {
+    err = std::string(what) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? SELINV_E_NOMEM : SELINV_E_DEVICE;
+}
+
+#define HIPCHK(err, call, what)                                   \
+    do {                                                          \
+        hipError_t e_ = (call);                                   \
+        if (e_ != hipSuccess) return dev_fail((err), e_, (what)); \
+    } while (0)
+
+template <class T>
+hipError_t upload(T **dptr, const std::vector<T> &v) {
+    size_t bytes = std::max<size_t>(1, v.size()) * sizeof(T);
+    hipError_t e = hipMalloc((void **)dptr, bytes);
+    if (e != hipSuccess) return e;
+    if (!v.empty()) e = hipMemcpy(*dptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+    return e;
+}
+
+hipError_t alloc_bytes(void **p, size_t bytes) { return hipMalloc(p, std::max<size_t>(bytes, 16)); }
+
+selinv_status ensure_prec(selinv_handle h, int prec) {
+    PrecBufs &b = h->pb[prec];
+    if (b.ready) return SELINV_OK;
+    const Plan &P = h->P;
+    const size_t e = elem_bytes(prec);
+    HIPCHK(h->err, alloc_bytes((void **)&b.Zd, P.tot_d * 8), "alloc Zd");
+    HIPCHK(h->err, alloc_bytes(&b.ZL, P.tot_l * e), "alloc ZL");
+    HIPCHK(h->err, alloc_bytes(&b.ZU, P.tot_u * e), "alloc ZU");
+    HIPCHK(h->err, alloc_bytes(&b.Lh, P.tot_l * e), "alloc Lh");
+    HIPCHK(h->err, alloc_bytes(&b.Uh, P.tot_u * e), "alloc Uh");
+    HIPCHK(h->err, alloc_bytes(&b.G, h->g_elems * e), "alloc G");
+    b.ready = true;
+    return SELINV_OK;
+}
+
+void add_tiles(std::vector<GemmTile> &tiles, int prob, int M, int N) {
+    for (int n0 = 0; n0 < N; n0 += 64)
+        for (int m0 = 0; m0 < M; m0 += 64) tiles.push_back(GemmTile{prob, m0, n0, 0});
+}
+
+// Device allocations a work list may touch: [base, base + bytes).
+struct Extents {
+    std::vector<std::pair<const char *, size_t>> allocs;
+    int64_t violations = 0;
+    void add(const void *p, size_t bytes) { allocs.push_back({(const char *)p, bytes}); }
+    // the element range [first, last] of a column-major operand lies inside one allocation
+    void check(const void *p, int64_t rows, int64_t cols, int64_t ld, int esize) {
+        if (rows <= 0 || cols <= 0) return;
+        const char *lo = (const char *)p;
+        const char *hi = lo + ((rows - 1) + (cols - 1) * ld + 1) * esize;
+        for (auto &a : allocs)
+            if (lo >= a.first && hi <= a.first + a.second) return;
+        violations++;
+    }
+};
+
+int add_prob(std::vector<GemmProb> &probs, std::vector<GemmTile> &tiles, const void *A, int opA, int lda,
+             const void *B, int opB, int ldb, void *C, int ldc, const void *Cin, int ldcin, int M, int N, int K,
+             double alpha, double beta, Extents *ext = nullptr, int ein = 8, int eout = 8) {
+    if (M <= 0 || N <= 0) return 0;
+    if (ext) {
+        if (opA == 0) ext->check(A, M, K, lda, ein); else ext->check(A, K, M, lda, ein);
+        if (opB == 0) ext->check(B, K, N, ldb, ein); else ext->check(B, N, K, ldb, ein);
+        ext->check(C, M, N, ldc, eout);
+        if (Cin) ext->check(Cin, M, N, ldcin, eout);
+        if (lda < (opA == 0 ? M : K) || ldb < (opB == 0 ? K : N) || ldc < M) ext->violations++;
+    }
+    GemmProb p;
+    p.A = A;
+    p.B = B;
+    p.C = C;
+    p.Cin = Cin;
+    p.M = M;
+    p.N = N;
+    p.K = K;
+    p.lda = std::max(lda, 1);
+    p.ldb = std::max(ldb, 1);
+    p.ldc = std::max(ldc, 1);
+    p.ldcin = std::max(ldcin, 1);
+    p.opA = opA;
+    p.opB = opB;
+    p.pad = 0;
+    p.alpha = alpha;
+    p.beta = beta;
+    probs.push_back(p);
+    size_t before = tiles.size();
+    add_tiles(tiles, (int)probs.size() - 1, M, N);
+    return (int)(tiles.size() - before);
+}
+
+// Build the work lists of one sweep over a set of factored handles.
+selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, std::unique_ptr<Sweep> &out,
+                          std::string &err) {
+    std::unique_ptr<Sweep> S(new Sweep());
+    S->prec = prec;
+    const int e = elem_bytes(prec);
+    std::vector<MatDev> mats;
+    std::vector<TriItem> tri;
+    std::vector<GemmProb> probs;
+    std::vector<GemmTile> tiles;
+    std::vector<GatherTile> gts;
+    int depth = 0;
+    Extents X;
+    for (auto h : hs) {
+        selinv_status st = ensure_prec(h, prec);
+        if (st) {
+            err = h->err;
+            return st;
+        }
+        const PrecBufs &b = h->pb[prec];
+        const Plan &P = h->P;
+        X.add(h->d_lpan, P.tot_l * 8);
+        X.add(h->d_upan, P.tot_u * 8);
+        X.add(h->d_Linv, P.tot_d * 8);
+        X.add(h->d_Uinv, P.tot_d * 8);
+        X.add(b.Zd, P.tot_d * 8);
+        X.add(b.ZL, P.tot_l * e);
+        X.add(b.ZU, P.tot_u * e);
+        X.add(b.Lh, P.tot_l * e);
+        X.add(b.Uh, P.tot_u * e);
+        X.add(b.G, h->g_elems * e);
+        MatDev m;
+        m.sn = h->d_sn;
+        m.supof = h->d_supof;
+        m.rl = h->d_rl;
+        m.ru = h->d_ru;
+        m.l_coloff = h->d_lcol;
+        m.u_rowoff = h->d_urow;
+        m.mapL = h->d_mapL;
+        m.mapU = h->d_mapU;
+        m.Zd = b.Zd;
+        m.ZL = b.ZL;
+        m.ZU = b.ZU;
+        m.G = b.G;
+        mats.push_back(m);
+        depth = std::max(depth, h->P.nlevels);
+    }
+    // diagonal-block inversion
+    for (auto h : hs)
+        for (int32_t K = 0; K < h->P.ns; K++) {
+            const SnRec &r = h->sn[K];
+            for (int j0 = 0; j0 < r.s; j0 += 4)
+                tri.push_back(TriItem{h->d_diag + r.off_d, h->d_Linv + r.off_d, h->d_Uinv + r.off_d, r.s, j0});
+        }
+    S->tri.count = (int)tri.size();
+    // normalisation (FP64 arithmetic, output in the run's precision)
+    S->norm.off = tiles.size();
+    for (auto h : hs) {
+        const PrecBufs &b = h->pb[prec];
+        for (int32_t K = 0; K < h->P.ns; K++) {
+            const SnRec &r = h->sn[K];
+            char *Lh = (char *)b.Lh + r.off_l * e;
+            char *Uh = (char *)b.Uh + r.off_u * e;
+            S->norm.count += add_prob(probs, tiles, h->d_lpan + r.off_l, 0, r.cl, h->d_Linv + r.off_d, 0, r.s, Lh,
+                                      r.cl, nullptr, 1, r.cl, r.s, r.s, 1.0, 0.0, &X, 8, e);
+            S->norm.count += add_prob(probs, tiles, h->d_upan + r.off_u, 0, r.cu, h->d_Uinv + r.off_d, 1, r.s, Uh,
+                                      r.cu, nullptr, 1, r.cu, r.s, r.s, 1.0, 0.0, &X, 8, e);
+        }
+    }
+    S->dt.off = tiles.size();
+    for (auto h : hs) {
+        const PrecBufs &b = h->pb[prec];
+        for (int32_t K = 0; K < h->P.ns; K++) {
+            const SnRec &r = h->sn[K];
+            S->dt.count += add_prob(probs, tiles, h->d_Linv + r.off_d, 1, r.s, h->d_Uinv + r.off_d, 1, r.s,
+                                    b.Zd + r.off_d, r.s, nullptr, 1, r.s, r.s, r.s, 1.0, 0.0, &X, 8, 8);
+        }
+    }
+    S->gat.resize(depth);
+    S->g35.resize(depth);
+    S->g4.resize(depth);
+    S->lev_flops35.assign(depth, 0);
+    S->lev_flops4.assign(depth, 0);
+    S->lev_gather_elems.assign(depth, 0);
+    S->lev_nsup.assign(depth, 0);
+    S->lev_maxs.assign(depth, 0);
+    for (int d = 0; d < depth; d++) {
+        S->gat[d].off = gts.size();
+        for (size_t mi = 0; mi < hs.size(); mi++) {
+            selinv_handle h = hs[mi];
+            if (d >= h->P.nlevels) continue;
+            for (int32_t K : h->P.levels[d]) {
+                const SnRec &r = h->sn[K];
+                for (int b0 = 0; b0 < r.cu; b0 += 64)
+                    for (int a0 = 0; a0 < r.cl; a0 += 64) gts.push_back(GatherTile{(int32_t)mi, K, a0, b0});
+                S->lev_gather_elems[d] += (double)r.cl * r.cu;
+                S->lev_nsup[d]++;
+                S->lev_maxs[d] = std::max(S->lev_maxs[d], r.s);
+            }
+        }
+        S->gat[d].count = (int)(gts.size() - S->gat[d].off);
+        S->g35[d].off = tiles.size();
+        for (auto h : hs) {
+            if (d >= h->P.nlevels) continue;
+            const PrecBufs &b = h->pb[prec];
+            for (int32_t K : h->P.levels[d]) {
+                const SnRec &r = h->sn[K];
+                const char *G = (const char *)b.G + r.g_off * e;
+                char *Lh = (char *)b.Lh + r.off_l * e, *Uh = (char *)b.Uh + r.off_u * e;
+                char *ZL = (char *)b.ZL + r.off_l * e, *ZU = (char *)b.ZU + r.off_u * e;
+                // step 3 (stored transposed): A^{-T}(K,R_U)^T = -G^T Lhat
+                S->g35[d].count += add_prob(probs, tiles, G, 1, r.cl, Lh, 0, r.cl, ZU, r.cu, nullptr, 1, r.cu, r.s,
+                                            r.cl, -1.0, 0.0, &X, e, e);
+                // step 5: A^{-T}(R_L,K) = -G Uhat^T
+                S->g35[d].count += add_prob(probs, tiles, G, 0, r.cl, Uh, 0, r.cu, ZL, r.cl, nullptr, 1, r.cl, r.s,
+                                            r.cu, -1.0, 0.0, &X, e, e);
+                S->lev_flops35[d] += 4.0 * r.s * (double)r.cl * r.cu;
+            }
+        }
+        S->g35[d].count = (int)(tiles.size() - S->g35[d].off);
+        S->g4[d].off = tiles.size();
+        for (auto h : hs) {
+            if (d >= h->P.nlevels) continue;
+            const PrecBufs &b = h->pb[prec];
+            for (int32_t K : h->P.levels[d]) {
+                const SnRec &r = h->sn[K];
+                if (r.cu == 0) continue;
+                char *Uh = (char *)b.Uh + r.off_u * e, *ZU = (char *)b.ZU + r.off_u * e;
+                // step 4: A^{-T}(K,K) = (L_KK)^{-T}(U_KK)^{-T} - A^{-T}(K,R_U) Uhat^T
+                S->g4[d].count += add_prob(probs, tiles, ZU, 1, r.cu, Uh, 0, r.cu, b.Zd + r.off_d, r.s,
+                                           b.Zd + r.off_d, r.s, r.s, r.s, r.cu, -1.0, 1.0, &X, e, 8);
+                S->lev_flops4[d] += 2.0 * r.s * (double)r.s * r.cu;
+            }
+        }
+        S->g4[d].count = (int)(tiles.size() - S->g4[d].off);
+    }
+    // gather tiles stay inside their supernode's G block
+    for (const GatherTile &t : gts) {
+        const SnRec &r = hs[t.mat]->sn[t.K];
+        if (t.a0 < 0 || t.b0 < 0 || t.a0 >= r.cl || t.b0 >= r.cu ||
+            r.g_off + (int64_t)r.cl * r.cu > hs[t.mat]->g_elems)
+            X.violations++;
+    }
+    for (auto h : hs)
+        for (const SnRec &r : h->sn)
+            if (r.s > TRI_MAX_S || r.off_d + (int64_t)r.s * r.s > h->P.tot_d) X.violations++;
+    if (X.violations) {
+        err = "internal error: " + std::to_string(X.violations) + " work-list entries outside their buffers";
+        return SELINV_E_INVALID_ARG;
+    }
+    HIPCHK(err, upload(&S->d_mats, mats), "upload mats");
+    HIPCHK(err, upload(&S->d_tri, tri), "upload tri");
+    HIPCHK(err, upload(&S->d_probs, probs), "upload probs");
+    HIPCHK(err, upload(&S->d_tiles, tiles), "upload tiles");
+    HIPCHK(err, upload(&S->d_gt, gts), "upload gather tiles");
+    out = std::move(S);
+    return SELINV_OK;
+}
+
+// Launch a sweep; `ev` (optional) receives one event after each phase.
+hipError_t launch_sweep(const Sweep &S, hipStream_t st, std::vector<hipEvent_t> *ev) {
+    const int prec = S.prec, mode = mode_of(prec);
+    const int f64 = prec == SELINV_FP64;
+    hipError_t e;
+    auto mark = [&](int i) {
+        if (ev) (void)hipEventRecord((*ev)[i], st);
+    };
+    mark(0);
+    if ((e = launch_tri_inv(S.d_tri, S.tri.count, st))) return e;
+    mark(1);
+    if ((e = launch_gemm(1, f64, CMP_F64, S.d_probs, S.d_tiles + S.norm.off, S.norm.count, st))) return e;
+    mark(2);
+    if ((e = launch_gemm(1, 1, CMP_F64, S.d_probs, S.d_tiles + S.dt.off, S.dt.count, st))) return e;
+    mark(3);
+    for (size_t d = 0; d < S.gat.size(); d++) {
+        if ((e = launch_gather(f64, S.d_mats, S.d_gt + S.gat[d].off, S.gat[d].count, st))) return e;
+        mark(4 + 3 * d);
+        if ((e = launch_gemm(f64, f64, mode, S.d_probs, S.d_tiles + S.g35[d].off, S.g35[d].count, st))) return e;
+        mark(5 + 3 * d);
+        if ((e = launch_gemm(f64, 1, mode, S.d_probs, S.d_tiles + S.g4[d].off, S.g4[d].count, st))) return e;
+        mark(6 + 3 * d);
+    }
+    return hipSuccess;
+}
+
+bool valid_prec(int p) { return p >= 0 && p < NPREC; }
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char *selinv_status_string(selinv_status s) {
+    switch (s) {
+        case SELINV_OK: return "OK";
+        case SELINV_E_INVALID_ARG: return "INVALID_ARG";
+        case SELINV_E_BAD_PATTERN: return "BAD_PATTERN";
+        case SELINV_E_BAD_PERM: return "BAD_PERM";
+        case SELINV_E_ZERO_PIVOT: return "ZERO_PIVOT";
+        case SELINV_E_NOT_SELECTED: return "NOT_SELECTED";
+        case SELINV_E_STATE: return "STATE";
+        case SELINV_E_NOMEM: return "NOMEM";
+        case SELINV_E_DEVICE: return "DEVICE";
+    }
+    return "UNKNOWN";
+}
+
+// message of the last failed selinv_analyze on this thread
+static thread_local std::string g_analyze_err;
+
+const char *selinv_last_error(selinv_handle h) { return h ? h->err.c_str() : g_analyze_err.c_str(); }
+
+selinv_status selinv_analyze(int64_t n, const int64_t *colptr, const int32_t *rowind, const int32_t *perm,
+                             const selinv_analyze_opts *opts, selinv_handle *out) {
+    if (!out) return SELINV_E_INVALID_ARG;
+    *out = nullptr;
+    selinv_handle h = new (std::nothrow) selinv_handle_s();
+    if (!h) return SELINV_E_NOMEM;
+    int32_t cap = opts ? opts->max_super : 0;
+    int32_t relax = opts ? std::max<int32_t>(0, opts->relax) : 0;
+    int32_t pad = opts ? std::min<int32_t>(100, std::max<int32_t>(0, opts->pad_pct)) : 0;
+    if (cap <= 0 || cap > TRI_MAX_S) cap = TRI_MAX_S;
+    selinv_status st;
+    try {
+        st = analyze(h->P, n, colptr, rowind, perm, cap, relax, pad, h->err);
+    } catch (const std::bad_alloc &) {
+        st = SELINV_E_NOMEM;
+        h->err = "host allocation failed in analyze";
+    }
+    if (st) {
+        g_analyze_err = h->err;
+        delete h;
+        return st;
+    }
+    const Plan &P = h->P;
+    h->sn.resize(P.ns);
+    std::vector<int64_t> lev_g(P.nlevels, 0);
+    for (int32_t K = 0; K < P.ns; K++) {
+        SnRec &r = h->sn[K];
+        r.f = P.xsup[K];
+        r.s = P.width(K);
+        r.cl = (int32_t)P.cl(K);
+        r.cu = (int32_t)P.cu(K);
+        r.off_d = P.off_d[K];
+        r.off_l = P.off_l[K];
+        r.off_u = P.off_u[K];
+        r.rl_off = P.rl_ptr[K];
+        r.ru_off = P.ru_ptr[K];
+        int lv = P.level[K];
+        r.g_off = lev_g[lv];
+        lev_g[lv] += (int64_t)r.cl * r.cu;
+    }
+    h->g_elems = 0;
+    for (auto g : lev_g) h->g_elems = std::max(h->g_elems, g);
+    *out = h;
+    return SELINV_OK;
+}
+
+selinv_status selinv_factor(selinv_handle h, const double *values) {
+    if (!h || !values) return SELINV_E_INVALID_ARG;
+    if (h->state < 0) return SELINV_E_STATE;
+    HostFactors F;
+    selinv_status st;
+    try {
+        st = factor_host(h->P, values, F, h->err);
+    } catch (const std::bad_alloc &) {
+        h->err = "host allocation failed in factor";
+        return SELINV_E_NOMEM;
+    }
+    if (st) return st;
+    int dev = 0;
+    HIPCHK(h->err, hipGetDevice(&dev), "hipGetDevice");
+    if (h->device >= 0 && h->device != dev) {
+        h->err = "factor called on a different device than before";
+        return SELINV_E_STATE;
+    }
+    h->device = dev;
+    const Plan &P = h->P;
+    if (!h->d_diag) {
+        HIPCHK(h->err, alloc_bytes((void **)&h->d_diag, P.tot_d * 8), "alloc diag");
+        HIPCHK(h->err, alloc_bytes((void **)&h->d_lpan, P.tot_l * 8), "alloc lpan");
+        HIPCHK(h->err, alloc_bytes((void **)&h->d_upan, P.tot_u * 8), "alloc upan");
+        HIPCHK(h->err, alloc_bytes((void **)&h->d_Linv, P.tot_d * 8), "alloc Linv");
+        HIPCHK(h->err, alloc_bytes((void **)&h->d_Uinv, P.tot_d * 8), "alloc Uinv");
+        HIPCHK(h->err, upload(&h->d_sn, h->sn), "upload sn");
+        HIPCHK(h->err, upload(&h->d_supof, P.supof), "upload supof");
+        HIPCHK(h->err, upload(&h->d_rl, P.rl), "upload rl");
+        HIPCHK(h->err, upload(&h->d_ru, P.ru), "upload ru");
+        HIPCHK(h->err, upload(&h->d_mapL, P.mapL), "upload mapL");
+        HIPCHK(h->err, upload(&h->d_mapU, P.mapU), "upload mapU");
+        HIPCHK(h->err, upload(&h->d_lcol, P.l_coloff), "upload l_coloff");
+        HIPCHK(h->err, upload(&h->d_urow, P.u_rowoff), "upload u_rowoff");
+        HIPCHK(h->err, upload(&h->d_aloc, P.a_loc), "upload a_loc");
+    }
+    if (P.tot_d) HIPCHK(h->err, hipMemcpy(h->d_diag, F.d.data(), P.tot_d * 8, hipMemcpyHostToDevice), "H2D diag");
+    if (P.tot_l) HIPCHK(h->err, hipMemcpy(h->d_lpan, F.l.data(), P.tot_l * 8, hipMemcpyHostToDevice), "H2D lpan");
+    if (P.tot_u) HIPCHK(h->err, hipMemcpy(h->d_upan, F.u.data(), P.tot_u * 8, hipMemcpyHostToDevice), "H2D upan");
+    h->state = 1;
+    return SELINV_OK;
+}
+
+static selinv_status check_run(selinv_handle h, int prec) {
+    if (!h || !valid_prec(prec)) return SELINV_E_INVALID_ARG;
+    if (h->state < 1) {
+        h->err = "run before factor";
+        return SELINV_E_STATE;
+    }
+    int dev = 0;
+    HIPCHK(h->err, hipGetDevice(&dev), "hipGetDevice");
+    if (dev != h->device) {
+        h->err = "run on a different device than factor";
+        return SELINV_E_STATE;
+    }
+    return SELINV_OK;
+}
+
+static selinv_status ensure_sweep(selinv_handle h, int prec) {
+    if (h->sweep[prec]) return SELINV_OK;
+    std::vector<selinv_handle> one{h};
+    return build_sweep(one, prec, h->sweep[prec], h->err);
+}
+
+selinv_status selinv_run(selinv_handle h, selinv_precision prec, void *stream) {
+    selinv_status st = check_run(h, prec);
+    if (st) return st;
+    if ((st = ensure_sweep(h, prec))) return st;
+    hipStream_t s = (hipStream_t)stream;
+    const Sweep &S = *h->sweep[prec];
+    std::vector<hipEvent_t> *ev = nullptr;
+    if (h->profiling) {
+        size_t need = 4 + 3 * S.gat.size();
+        while (h->events.size() < need) {
+            hipEvent_t e;
+            HIPCHK(h->err, hipEventCreate(&e), "hipEventCreate");
+            h->events.push_back(e);
+        }
+        ev = &h->events;
+    }
+    hipError_t e = launch_sweep(S, s, ev);
+    if (e != hipSuccess) return dev_fail(h->err, e, "kernel launch");
+    h->last_prec = prec;
+    h->last_stream = s;
+    h->state = 2;
+    return SELINV_OK;
+}
+
+selinv_status selinv_run_graph(selinv_handle h, selinv_precision prec, void *stream) {
+    selinv_status st = check_run(h, prec);
+    if (st) return st;
+    if ((st = ensure_sweep(h, prec))) return st;
+    Sweep &S = *h->sweep[prec];
+    hipStream_t s = (hipStream_t)stream;
+    if (!s) {
+        if (!h->own_stream) HIPCHK(h->err, hipStreamCreateWithFlags(&h->own_stream, hipStreamNonBlocking), "stream");
+        s = h->own_stream;
+    }
+    if (!S.gexec) {
+        HIPCHK(h->err, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
+        hipError_t e = launch_sweep(S, s, nullptr);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(s, &g);
+        if (e != hipSuccess) return dev_fail(h->err, e, "capture launch");
+        if (e2 != hipSuccess) return dev_fail(h->err, e2, "end capture");
+        S.graph = g;
+        HIPCHK(h->err, hipGraphInstantiate(&S.gexec, g, nullptr, nullptr, 0), "graph instantiate");
+    }
+    HIPCHK(h->err, hipGraphLaunch(S.gexec, s), "graph launch");
+    h->last_prec = prec;
+    h->last_stream = s;
+    h->state = 2;
+    return SELINV_OK;
+}
+
+selinv_status selinv_set_profiling(selinv_handle h, int32_t on) {
+    if (!h) return SELINV_E_INVALID_ARG;
+    h->profiling = on != 0;
+    return SELINV_OK;
+}
+
+selinv_status selinv_timings(selinv_handle h, double *ms, int32_t count) {
+    if (!h || !ms) return SELINV_E_INVALID_ARG;
+    if (h->state < 2 || h->last_prec < 0 || !h->profiling) return SELINV_E_STATE;
+    const Sweep &S = *h->sweep[h->last_prec];
+    size_t nev = 4 + 3 * S.gat.size();
+    if (h->events.size() < nev) return SELINV_E_STATE;
+    HIPCHK(h->err, hipEventSynchronize(h->events[nev - 1]), "event sync");
+    for (int32_t i = 0; i < count; i++) {
+        if ((size_t)i + 1 >= nev) {
+            ms[i] = 0;
+            continue;
+        }
+        float t = 0;
+        HIPCHK(h->err, hipEventElapsedTime(&t, h->events[i], h->events[i + 1]), "elapsed");
+        ms[i] = t;
+    }
+    return SELINV_OK;
+}
+
+selinv_status selinv_level_stats(selinv_handle h, int32_t level, double *stats) {
+    if (!h || !stats || h->last_prec < 0) return SELINV_E_INVALID_ARG;
+    const Sweep &S = *h->sweep[h->last_prec];
+    if (level < 0 || level >= (int32_t)S.gat.size()) return SELINV_E_INVALID_ARG;
+    stats[0] = S.lev_nsup[level];
+    stats[1] = S.lev_maxs[level];
+    stats[2] = S.lev_flops35[level];
+    stats[3] = S.lev_flops4[level];
+    stats[4] = S.lev_gather_elems[level];
+    stats[5] = S.gat[level].count;
+    stats[6] = S.g35[level].count;
+    stats[7] = S.g4[level].count;
+    return SELINV_OK;
+}
+
+static selinv_status sync_last(selinv_handle h) {
+    if (h->state < 2 || h->last_prec < 0) {
+        h->err = "no completed run";
+        return SELINV_E_STATE;
+    }
+    HIPCHK(h->err, hipStreamSynchronize(h->last_stream), "stream sync");
+    return SELINV_OK;
+}
+
+selinv_status selinv_get(selinv_handle h, int64_t i, int64_t j, double *out) {
+    if (!h || !out) return SELINV_E_INVALID_ARG;
+    if (h->state < 0) return SELINV_E_STATE;
+    const Plan &P = h->P;
+    if (i < 0 || j < 0 || i >= P.n || j >= P.n) return SELINV_E_INVALID_ARG;
+    selinv_status st = sync_last(h);
+    if (st) return st;
+    int64_t loc = P.locate(P.q[j], P.q[i]);
+    if (loc < 0) return SELINV_E_NOT_SELECTED;
+    const PrecBufs &b = h->pb[h->last_prec];
+    int64_t kind = loc >> LOC_SHIFT, off = loc & LOC_MASK;
+    if (kind == LOC_DIAG) {
+        HIPCHK(h->err, hipMemcpy(out, b.Zd + off, 8, hipMemcpyDeviceToHost), "D2H");
+    } else {
+        const void *base = kind == LOC_L ? b.ZL : b.ZU;
+        if (h->last_prec == SELINV_FP64) {
+            HIPCHK(h->err, hipMemcpy(out, (const double *)base + off, 8, hipMemcpyDeviceToHost), "D2H");
+        } else {
+            float f = 0;
+            HIPCHK(h->err, hipMemcpy(&f, (const float *)base + off, 4, hipMemcpyDeviceToHost), "D2H");
+            *out = f;
+        }
+    }
+    return SELINV_OK;
+}
+
+selinv_status selinv_get_selected_device(selinv_handle h, double *out, void *stream) {
+    if (!h || !out) return SELINV_E_INVALID_ARG;
+    if (h->state < 2 || h->last_prec < 0) return SELINV_E_STATE;
+    const PrecBufs &b = h->pb[h->last_prec];
+    ExtractArgs a{h->d_aloc, b.Zd, b.ZL, b.ZU, out, h->P.nnz_a};
+    hipError_t e = launch_extract(h->last_prec == SELINV_FP64, a, (hipStream_t)stream);
+    if (e != hipSuccess) return dev_fail(h->err, e, "extract launch");
+    return SELINV_OK;
+}
+
+selinv_status selinv_get_selected(selinv_handle h, double *out) {
+    if (!h || !out) return SELINV_E_INVALID_ARG;
+    selinv_status st = sync_last(h);
+    if (st) return st;
+    double *d = nullptr;
+    HIPCHK(h->err, alloc_bytes((void **)&d, h->P.nnz_a * 8), "alloc extract");
+    st = selinv_get_selected_device(h, d, h->last_stream);
+    if (!st) {
+        hipError_t e = hipStreamSynchronize(h->last_stream);
+        if (e == hipSuccess) e = hipMemcpy(out, d, h->P.nnz_a * 8, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) st = dev_fail(h->err, e, "extract copy");
+    }
+    (void)hipFree(d);
+    return st;
+}
+
+selinv_status selinv_export(selinv_handle h, int32_t *row, int32_t *col, double *val) {
+    if (!h || !row || !col || !val) return SELINV_E_INVALID_ARG;
+    selinv_status st = sync_last(h);
+    if (st) return st;
+    const Plan &P = h->P;
+    const PrecBufs &b = h->pb[h->last_prec];
+    std::vector<double> zd(P.tot_d), zl(P.tot_l), zu(P.tot_u);
+    if (P.tot_d) HIPCHK(h->err, hipMemcpy(zd.data(), b.Zd, P.tot_d * 8, hipMemcpyDeviceToHost), "D2H Zd");
+    if (h->last_prec == SELINV_FP64) {
+        if (P.tot_l) HIPCHK(h->err, hipMemcpy(zl.data(), b.ZL, P.tot_l * 8, hipMemcpyDeviceToHost), "D2H ZL");
+        if (P.tot_u) HIPCHK(h->err, hipMemcpy(zu.data(), b.ZU, P.tot_u * 8, hipMemcpyDeviceToHost), "D2H ZU");
+    } else {
+        std::vector<float> tl(P.tot_l), tu(P.tot_u);
+        if (P.tot_l) HIPCHK(h->err, hipMemcpy(tl.data(), b.ZL, P.tot_l * 4, hipMemcpyDeviceToHost), "D2H ZL");
+        if (P.tot_u) HIPCHK(h->err, hipMemcpy(tu.data(), b.ZU, P.tot_u * 4, hipMemcpyDeviceToHost), "D2H ZU");
+        std::copy(tl.begin(), tl.end(), zl.begin());
+        std::copy(tu.begin(), tu.end(), zu.begin());
+    }
+    int64_t k = 0;
+    // A^{-T}(r, c) (permuted) = A^{-1}(p[c], p[r])
+    for (int32_t K = 0; K < P.ns; K++) {
+        const int32_t f = P.xsup[K], s = P.width(K);
+        const int64_t cl = P.cl(K), cu = P.cu(K);
+        const int32_t *RL = P.rl.data() + P.rl_ptr[K], *RU = P.ru.data() + P.ru_ptr[K];
+        for (int32_t c = 0; c < s; c++)
+            for (int32_t r = 0; r < s; r++, k++) {
+                row[k] = P.p[f + c];
+                col[k] = P.p[f + r];
+                val[k] = zd[P.off_d[K] + r + (int64_t)c * s];
+            }
+        for (int32_t t = 0; t < s; t++)
+            for (int64_t a = 0; a < cl; a++, k++) {
+                row[k] = P.p[f + t];
+                col[k] = P.p[RL[a]];
+                val[k] = zl[P.off_l[K] + a + t * cl];
+            }
+        for (int32_t t = 0; t < s; t++)
+            for (int64_t bb = 0; bb < cu; bb++, k++) {
+                row[k] = P.p[RU[bb]];
+                col[k] = P.p[f + t];
+                val[k] = zu[P.off_u[K] + bb + t * cu];
+            }
+    }
+    return SELINV_OK;
+}
+
+selinv_status selinv_structure(selinv_handle h, int32_t *perm_out, int32_t *xsup, int64_t *rl_ptr, int32_t *rl,
+                               int64_t *ru_ptr, int32_t *ru, int32_t *level) {
+    if (!h || h->state < 0) return SELINV_E_INVALID_ARG;
+    const Plan &P = h->P;
+    if (perm_out) std::copy(P.p.begin(), P.p.end(), perm_out);
+    if (xsup) std::copy(P.xsup.begin(), P.xsup.end(), xsup);
+    if (rl_ptr) std::copy(P.rl_ptr.begin(), P.rl_ptr.end(), rl_ptr);
+    if (rl) std::copy(P.rl.begin(), P.rl.end(), rl);
+    if (ru_ptr) std::copy(P.ru_ptr.begin(), P.ru_ptr.end(), ru_ptr);
+    if (ru) std::copy(P.ru.begin(), P.ru.end(), ru);
+    if (level) std::copy(P.level.begin(), P.level.end(), level);
+    return SELINV_OK;
+}
+
+selinv_status selinv_check_plan(selinv_handle h, int64_t *mismatches) {
+    if (!h || !mismatches) return SELINV_E_INVALID_ARG;
+    *mismatches = check_gather_maps(h->P, h->err);
+    return SELINV_OK;
+}
+
+selinv_status selinv_query(selinv_handle h, selinv_info *info) {
+    if (!h || !info || h->state < 0) return SELINV_E_INVALID_ARG;
+    const Plan &P = h->P;
+    info->n = P.n;
+    info->nnz_a = P.nnz_a;
+    info->nnz_lu = P.tot_d + P.tot_l + P.tot_u;
+    info->nsuper = P.ns;
+    info->nlevels = P.nlevels;
+    info->max_s = P.max_s;
+    info->max_c = P.max_c;
+    info->flops = P.flops;
+    info->flops_gemm = P.flops_gemm;
+    info->bytes_min_fp64 = P.bytes64;
+    info->bytes_min_fp32 = P.bytes32;
+    info->max_gemm_flops = P.max_gemm_flops;
+    info->max_gemm_m = P.max_gemm_m;
+    info->max_gemm_n = P.max_gemm_n;
+    info->max_gemm_k = P.max_gemm_k;
+    return SELINV_OK;
+}
+
+void selinv_destroy(selinv_handle h) {
+    if (!h) return;
+    for (int p = 0; p < NPREC; p++) {
+        h->sweep[p].reset();
+        PrecBufs &b = h->pb[p];
+        (void)hipFree(b.Zd);
+        (void)hipFree(b.ZL);
+        (void)hipFree(b.ZU);
+        (void)hipFree(b.Lh);
+        (void)hipFree(b.Uh);
+        (void)hipFree(b.G);
+    }
+    for (void *q : {(void *)h->d_diag, (void *)h->d_lpan, (void *)h->d_upan, (void *)h->d_Linv, (void *)h->d_Uinv,
+                    (void *)h->d_sn, (void *)h->d_supof, (void *)h->d_rl, (void *)h->d_ru, (void *)h->d_mapL,
+                    (void *)h->d_mapU, (void *)h->d_lcol, (void *)h->d_urow, (void *)h->d_aloc})
+        (void)hipFree(q);
+    for (auto e : h->events) (void)hipEventDestroy(e);
+    if (h->own_stream) (void)hipStreamDestroy(h->own_stream);
+    delete h;
+}
+
+selinv_status selinv_batch_create(selinv_handle *hs, int32_t count, selinv_batch *out) {
+    if (!hs || count <= 0 || !out) return SELINV_E_INVALID_ARG;
+    *out = nullptr;
+    for (int32_t i = 0; i < count; i++)
+        if (!hs[i] || hs[i]->state < 1) return SELINV_E_STATE;
+    selinv_batch b = new (std::nothrow) selinv_batch_s();
+    if (!b) return SELINV_E_NOMEM;
+    b->hs.assign(hs, hs + count);
+    *out = b;
+    return SELINV_OK;
+}
+
+selinv_status selinv_batch_run(selinv_batch b, selinv_precision prec, void *stream) {
+    if (!b || !valid_prec(prec)) return SELINV_E_INVALID_ARG;
+    for (auto h : b->hs) {
+        selinv_status st = check_run(h, prec);
+        if (st) return st;
+    }
+    if (!b->sweep[prec]) {
+        selinv_status st = build_sweep(b->hs, prec, b->sweep[prec], b->err);
+        if (st) return st;
+    }
+    hipError_t e = launch_sweep(*b->sweep[prec], (hipStream_t)stream, nullptr);
+    if (e != hipSuccess) return dev_fail(b->err, e, "batch launch");
+    for (auto h : b->hs) {
+        h->last_prec = prec;
+        h->last_stream = (hipStream_t)stream;
+        h->state = 2;
+    }
+    return SELINV_OK;
+}
+
+void selinv_batch_destroy(selinv_batch b) { delete b; }
+
+}  // extern "C"

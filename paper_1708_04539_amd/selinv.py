@@ -1,0 +1,261 @@
+"""ctypes binding of the C ABI in include/selinv.h (argument marshalling only).
+
+Every step of the selected inversion runs in the HIP library
+(``libselinv.so``); this module only converts arrays and status codes.  The
+library must have been built (``paper_1708_04539_amd.build.build()``); if it is
+missing, importing this module raises.
+
+torch is imported first so that the HIP runtime torch ships is the one the
+library binds to (both use the soname libamdhip64.so.7); streams passed to
+``run`` are torch stream handles.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch  # noqa: F401  (loads the process-wide HIP runtime first)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libselinv.so")
+
+FP64, MIXED_FP32, MIXED_BF16X3 = 0, 1, 2
+PRECISIONS = {"fp64": FP64, "mixed_fp32": MIXED_FP32, "mixed_bf16x3": MIXED_BF16X3}
+STATUS = {0: "OK", 1: "INVALID_ARG", 2: "BAD_PATTERN", 3: "BAD_PERM", 4: "ZERO_PIVOT",
+          5: "NOT_SELECTED", 6: "STATE", 7: "NOMEM", 8: "DEVICE"}
+
+EXPORTED = ["selinv_analyze", "selinv_factor", "selinv_run", "selinv_run_graph", "selinv_batch_create",
+            "selinv_batch_run", "selinv_batch_destroy", "selinv_get", "selinv_get_selected",
+            "selinv_get_selected_device", "selinv_export", "selinv_structure", "selinv_query",
+            "selinv_set_profiling", "selinv_timings", "selinv_level_stats", "selinv_last_error",
+            "selinv_status_string", "selinv_destroy", "selinv_check_plan"]
+
+
+class SelinvError(RuntimeError):
+    def __init__(self, code, msg=""):
+        self.code = int(code)
+        self.status = STATUS.get(self.code, str(code))
+        super().__init__(f"selinv {self.status}: {msg}")
+
+
+class Info(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nnz_a", C.c_int64), ("nnz_lu", C.c_int64), ("nsuper", C.c_int32),
+                ("nlevels", C.c_int32), ("max_s", C.c_int32), ("max_c", C.c_int32), ("flops", C.c_double),
+                ("flops_gemm", C.c_double), ("bytes_min_fp64", C.c_double), ("bytes_min_fp32", C.c_double),
+                ("max_gemm_flops", C.c_double), ("max_gemm_m", C.c_int32), ("max_gemm_n", C.c_int32),
+                ("max_gemm_k", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Opts(C.Structure):
+    _fields_ = [("max_super", C.c_int32), ("relax", C.c_int32), ("pad_pct", C.c_int32)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_1708_04539_amd.build.build()")
+    lib = C.CDLL(LIB_PATH)
+    P, vp = C.POINTER, C.c_void_p
+    i32, i64, dbl = C.c_int32, C.c_int64, C.c_double
+    sig = {
+        "selinv_analyze": ([i64, P(i64), P(i32), P(i32), P(Opts), P(vp)], C.c_int),
+        "selinv_factor": ([vp, P(dbl)], C.c_int),
+        "selinv_run": ([vp, C.c_int, vp], C.c_int),
+        "selinv_run_graph": ([vp, C.c_int, vp], C.c_int),
+        "selinv_batch_create": ([P(vp), i32, P(vp)], C.c_int),
+        "selinv_batch_run": ([vp, C.c_int, vp], C.c_int),
+        "selinv_batch_destroy": ([vp], None),
+        "selinv_get": ([vp, i64, i64, P(dbl)], C.c_int),
+        "selinv_get_selected": ([vp, P(dbl)], C.c_int),
+        "selinv_get_selected_device": ([vp, vp, vp], C.c_int),
+        "selinv_export": ([vp, P(i32), P(i32), P(dbl)], C.c_int),
+        "selinv_structure": ([vp, P(i32), P(i32), P(i64), P(i32), P(i64), P(i32), P(i32)], C.c_int),
+        "selinv_query": ([vp, P(Info)], C.c_int),
+        "selinv_set_profiling": ([vp, i32], C.c_int),
+        "selinv_timings": ([vp, P(dbl), i32], C.c_int),
+        "selinv_level_stats": ([vp, i32, P(dbl)], C.c_int),
+        "selinv_last_error": ([vp], C.c_char_p),
+        "selinv_status_string": ([C.c_int], C.c_char_p),
+        "selinv_destroy": ([vp], None),
+        "selinv_check_plan": ([vp, P(i64)], C.c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    return lib
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def _p(a, t):
+    return a.ctypes.data_as(C.POINTER(t))
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _prec(p):
+    return PRECISIONS[p] if isinstance(p, str) else int(p)
+
+
+class SelInv:
+    """One matrix: analyze (construction) -> factor -> run -> get*/export."""
+
+    def __init__(self, n, colptr, rowind, perm=None, max_super=0, relax=0, pad_pct=0):
+        self._h = C.c_void_p()
+        self.n = int(n)
+        self._colptr = np.ascontiguousarray(colptr, dtype=np.int64)
+        self._rowind = np.ascontiguousarray(rowind, dtype=np.int32)
+        self.nnz = int(self._colptr[-1])
+        pp = None
+        if perm is not None:
+            self._perm = np.ascontiguousarray(perm, dtype=np.int32)
+            pp = _p(self._perm, C.c_int32)
+        opts = Opts(int(max_super), int(relax), int(pad_pct))
+        rc = _lib.selinv_analyze(self.n, _p(self._colptr, C.c_int64), _p(self._rowind, C.c_int32), pp,
+                                 C.byref(opts), C.byref(self._h))
+        if rc:
+            msg = _lib.selinv_last_error(None).decode()
+            raise SelinvError(rc, "analyze: " + msg)
+        self.info = self.query()
+
+    def _check(self, rc, what):
+        if rc:
+            raise SelinvError(rc, f"{what}: {_lib.selinv_last_error(self._h).decode()}")
+
+    def factor(self, values):
+        v = np.ascontiguousarray(values, dtype=np.float64)
+        self._check(_lib.selinv_factor(self._h, _p(v, C.c_double)), "factor")
+        return self
+
+    def run(self, precision="fp64", stream=None, graph=False):
+        f = _lib.selinv_run_graph if graph else _lib.selinv_run
+        self._check(f(self._h, _prec(precision), _stream_ptr(stream)), "run")
+        return self
+
+    def get(self, i, j) -> float:
+        out = C.c_double()
+        self._check(_lib.selinv_get(self._h, int(i), int(j), C.byref(out)), "get")
+        return out.value
+
+    def get_selected(self) -> np.ndarray:
+        out = np.empty(self.nnz, dtype=np.float64)
+        self._check(_lib.selinv_get_selected(self._h, _p(out, C.c_double)), "get_selected")
+        return out
+
+    def get_selected_device(self, out: "torch.Tensor", stream=None):
+        assert out.dtype == torch.float64 and out.is_cuda and out.numel() >= self.nnz and out.is_contiguous()
+        self._check(_lib.selinv_get_selected_device(self._h, C.c_void_p(out.data_ptr()), _stream_ptr(stream)),
+                    "get_selected_device")
+        return out
+
+    def export(self):
+        m = int(self.info["nnz_lu"])
+        r = np.empty(m, np.int32)
+        c = np.empty(m, np.int32)
+        v = np.empty(m, np.float64)
+        self._check(_lib.selinv_export(self._h, _p(r, C.c_int32), _p(c, C.c_int32), _p(v, C.c_double)), "export")
+        order = np.lexsort((r, c))
+        return r[order], c[order], v[order]
+
+    def structure(self) -> dict:
+        ns = self.info["nsuper"]
+        perm = np.empty(self.n, np.int32)
+        xsup = np.empty(ns + 1, np.int32)
+        rlp = np.empty(ns + 1, np.int64)
+        rup = np.empty(ns + 1, np.int64)
+        lev = np.empty(ns, np.int32)
+        self._check(_lib.selinv_structure(self._h, _p(perm, C.c_int32), _p(xsup, C.c_int32), _p(rlp, C.c_int64),
+                                          None, _p(rup, C.c_int64), None, _p(lev, C.c_int32)), "structure")
+        rl = np.empty(max(int(rlp[-1]), 1), np.int32)
+        ru = np.empty(max(int(rup[-1]), 1), np.int32)
+        self._check(_lib.selinv_structure(self._h, None, None, None, _p(rl, C.c_int32), None, _p(ru, C.c_int32),
+                                          None), "structure")
+        return {"perm": perm, "xsup": xsup, "rl_ptr": rlp, "rl": rl[:int(rlp[-1])], "ru_ptr": rup,
+                "ru": ru[:int(rup[-1])], "level": lev}
+
+    def query(self) -> dict:
+        info = Info()
+        self._check(_lib.selinv_query(self._h, C.byref(info)), "query")
+        return info.as_dict()
+
+    def check_plan(self) -> int:
+        """Host-side check of every gather/extraction index; returns the mismatch count."""
+        out = C.c_int64()
+        self._check(_lib.selinv_check_plan(self._h, C.byref(out)), "check_plan")
+        return out.value
+
+    def set_profiling(self, on=True):
+        self._check(_lib.selinv_set_profiling(self._h, 1 if on else 0), "set_profiling")
+
+    def timings(self):
+        """Per-phase device ms of the last profiled run: tri_inv, normalise, diag init,
+        then (gather, steps 3+5, step 4) for every level."""
+        k = 3 + 3 * self.info["nlevels"]
+        out = np.zeros(k, np.float64)
+        self._check(_lib.selinv_timings(self._h, _p(out, C.c_double), k), "timings")
+        return out
+
+    def level_stats(self, level):
+        out = np.zeros(8, np.float64)
+        self._check(_lib.selinv_level_stats(self._h, int(level), _p(out, C.c_double)), "level_stats")
+        keys = ["nsup", "max_s", "flops35", "flops4", "gather_elems", "gather_tiles", "tiles35", "tiles4"]
+        return dict(zip(keys, out.tolist()))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.selinv_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """One level sweep over several factored matrices (levels aligned at the roots)."""
+
+    def __init__(self, mats):
+        self.mats = list(mats)
+        arr = (C.c_void_p * len(self.mats))(*[m.handle.value for m in self.mats])
+        self._b = C.c_void_p()
+        rc = _lib.selinv_batch_create(arr, len(self.mats), C.byref(self._b))
+        if rc:
+            raise SelinvError(rc, "batch_create")
+
+    def run(self, precision="fp64", stream=None):
+        rc = _lib.selinv_batch_run(self._b, _prec(precision), _stream_ptr(stream))
+        if rc:
+            raise SelinvError(rc, "batch_run")
+        return self
+
+    def close(self):
+        if getattr(self, "_b", None) is not None and self._b.value:
+            _lib.selinv_batch_destroy(self._b)
+            self._b = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,289 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bar (R-9 reading of the paper's accuracy table): over the compared entries X
+(library) and R (oracle),
+    err_norm = max |X - R| / max |R|,   err_diag = max_i |X_ii - R_ii| / |R_ii|,
+    max(err_norm, err_diag) <= 1e-11 for the FP64 form and <= 1e-5 for the
+    mixed forms.
+Index sets (which entries are computed) must match the oracle's bit for bit.
+Full-size cases are compared on sampled columns solved from the definition
+(oracle.sampled) and on identities that hold at any size.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import Oracle
+from workloads import config_c0, config_c1, config_c2, config_c3, config_c4, random_sparse, tridiag_csc
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-11, "mixed_fp32": 1e-5, "mixed_bf16x3": 1e-5}
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def si():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1708_04539_amd import selinv
+    return selinv
+
+
+def errs(X, R, rows, cols):
+    err_norm = np.abs(X - R).max() / np.abs(R).max()
+    d = rows == cols
+    err_diag = (np.abs(X[d] - R[d]) / np.abs(R[d])).max() if d.any() else 0.0
+    return err_norm, err_diag
+
+
+def compare_superset(s, o, tol):
+    r1, c1, v1 = s.export()
+    r2, c2, v2 = o.export()
+    assert np.array_equal(r1, r2) and np.array_equal(c1, c2)
+    en, ed = errs(v1, v2, r2, c2)
+    assert max(en, ed) <= tol, (en, ed)
+    return en, ed
+
+
+def lib_and_oracle(si, n, cp, ri, v, perm, cap, relax, pad):
+    s = si.SelInv(n, cp, ri, perm, cap, relax, pad)
+    assert s.check_plan() == 0
+    s.factor(v)
+    o = Oracle(n, cp, ri, perm, cap, relax, 0, pad).factor(v).selinv()
+    return s, o
+
+
+# --------------------------------------------------------------------------
+# small and ragged cases, whole computed superset
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("prec", ["fp64", "mixed_fp32", "mixed_bf16x3"])
+def test_c0_whole_superset(si, prec):
+    w = config_c0()
+    say("c0", prec)
+    s, o = lib_and_oracle(si, w.n, w.colptr, w.rowind, w.values, w.perm, w.max_super, w.relax, w.pad_pct)
+    s.run(prec)
+    compare_superset(s, o, TOL[prec])
+    if prec == "fp64":
+        inv = np.linalg.inv(w.to_scipy().toarray())
+        r, c, v = s.export()
+        assert np.abs(v - inv[r, c]).max() / np.abs(inv).max() < 1e-11
+
+
+CASES = [  # n, density, seed, cap, relax, pad
+    (1, 0.0, 0, 1, 0, 0),
+    (2, 0.5, 1, 1, 0, 0),
+    (37, 0.08, 2, 5, 0, 0),
+    (150, 0.03, 3, 16, 4, 5),
+    (400, 0.01, 4, 70, 10, 20),
+    (300, 0.6, 5, 300, 0, 0),     # one dense supernode of 300 columns
+    (700, 0.004, 6, 3, 0, 100),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"n{c[0]}_cap{c[3]}" for c in CASES])
+@pytest.mark.parametrize("prec", ["fp64", "mixed_fp32"])
+def test_random_ragged(si, case, prec):
+    n, dens, seed, cap, relax, pad = case
+    say("random", case, prec)
+    cp, ri, v, _ = random_sparse(n, dens, seed, symmetric_pattern=seed % 2 == 0)
+    perm = np.random.default_rng(seed).permutation(n).astype(np.int32)
+    s, o = lib_and_oracle(si, n, cp, ri, v, perm, cap, relax, pad)
+    s.run(prec)
+    compare_superset(s, o, TOL[prec])
+
+
+def test_widest_supernode_1024(si):
+    """Diagonal blocks of the maximal width the inversion kernel takes."""
+    n = 1100
+    say("wide 1024")
+    cp, ri, v, dense = random_sparse(n, 0.01, 8, symmetric_pattern=True)
+    s, o = lib_and_oracle(si, n, cp, ri, v, None, 1024, n, 0)
+    assert s.info["max_s"] == 1024
+    s.run("fp64")
+    compare_superset(s, o, TOL["fp64"])
+
+
+def test_tridiagonal_closed_form(si):
+    n = 500
+    say("tridiag")
+    cp, ri, v = tridiag_csc(-np.ones(n - 1), 2 * np.ones(n), -np.ones(n - 1))
+    s = si.SelInv(n, cp, ri, None, 7, 0, 0).factor(v).run("fp64")
+    r, c, val = s.export()
+    ref = np.minimum(r + 1, c + 1) * (n + 1 - np.maximum(r + 1, c + 1)) / (n + 1)
+    assert np.abs(val - ref).max() / ref.max() < 1e-11
+
+
+# --------------------------------------------------------------------------
+# C1 at full size: whole superset against the oracle
+# --------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def c1_pair(si):
+    w = config_c1()
+    say("c1 setup")
+    s, o = lib_and_oracle(si, w.n, w.colptr, w.rowind, w.values, w.perm, w.max_super, w.relax, w.pad_pct)
+    return w, s, o
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed_fp32", "mixed_bf16x3"])
+def test_c1_whole_superset(si, c1_pair, prec):
+    w, s, o = c1_pair
+    say("c1", prec)
+    s.run(prec)
+    en, ed = compare_superset(s, o, TOL[prec])
+    say("c1", prec, "err_norm", en, "err_diag", ed)
+
+
+def test_c1_graph_replay_and_determinism(si, c1_pair):
+    import torch
+    w, s, o = c1_pair
+    say("c1 graph")
+    s.run("fp64")
+    ref = s.get_selected()
+    s.run("fp64")
+    assert np.array_equal(s.get_selected(), ref)  # bitwise deterministic
+    st = torch.cuda.Stream()
+    for rep in range(3):
+        s.run("fp64", stream=st, graph=True)
+        got = s.get_selected()
+        assert np.array_equal(got, ref), rep
+        torch.cuda.synchronize()
+        s.run("fp64")  # eager work between replays
+        assert np.array_equal(s.get_selected(), ref)
+
+
+def test_c1_get_and_extraction(si, c1_pair):
+    import torch
+    w, s, o = c1_pair
+    say("c1 get")
+    s.run("fp64")
+    sel = s.get_selected()
+    ref = o.get_selected()
+    assert np.abs(sel - ref).max() / np.abs(ref).max() < 1e-11
+    dev = torch.empty(w.nnz, dtype=torch.float64, device="cuda")
+    s.get_selected_device(dev)
+    torch.cuda.synchronize()
+    assert np.array_equal(dev.cpu().numpy(), sel)
+    rng = np.random.default_rng(0)
+    cols = np.repeat(np.arange(w.n), np.diff(w.colptr))
+    for p in rng.integers(0, w.nnz, 50):
+        i, j = int(w.rowind[p]), int(cols[p])
+        assert s.get(j, i) == sel[p]  # out[p] = A^{-1}(j, i)
+    with pytest.raises(si.SelinvError) as e:
+        s.get(0, w.n - 1)
+    assert e.value.status == "NOT_SELECTED"
+
+
+# --------------------------------------------------------------------------
+# batches (C3 shape): one sweep over several matrices
+# --------------------------------------------------------------------------
+def test_c3_batch_matches_single_runs(si):
+    ws = config_c3(count=4)
+    say("c3 batch", [w.n for w in ws])
+    mats = [si.SelInv(w.n, w.colptr, w.rowind, w.perm, w.max_super, w.relax, w.pad_pct).factor(w.values)
+            for w in ws]
+    single = []
+    for m in mats:
+        m.run("fp64")
+        single.append(m.get_selected())
+    b = si.Batch(mats)
+    for prec in ["fp64", "mixed_fp32"]:
+        b.run(prec)
+        for m, ref in zip(mats, single):
+            got = m.get_selected()
+            if prec == "fp64":
+                assert np.array_equal(got, ref)
+            else:
+                assert np.abs(got - ref).max() / np.abs(ref).max() < 1e-5
+    o = Oracle(ws[1].n, ws[1].colptr, ws[1].rowind, ws[1].perm, ws[1].max_super, ws[1].relax, 0,
+               ws[1].pad_pct).factor(ws[1].values).selinv()
+    b.run("fp64")
+    compare_superset(mats[1], o, TOL["fp64"])
+    b.close()
+
+
+# --------------------------------------------------------------------------
+# full-size 3D cases: identities on the selected set + sampled exact columns
+# --------------------------------------------------------------------------
+def identity_residuals(w, sel):
+    cols = np.repeat(np.arange(w.n), np.diff(w.colptr))
+    prod = w.values * sel
+    row = np.bincount(w.rowind, weights=prod, minlength=w.n)
+    col = np.bincount(cols, weights=prod, minlength=w.n)
+    return np.abs(row - 1).max(), np.abs(col - 1).max()
+
+
+def sampled_column_errors(s, w, js, xs):
+    A = w.to_scipy().tocsr()
+    errs_n, errs_d = [], []
+    for j, x in zip(js, xs):
+        rows = A.indices[A.indptr[j]:A.indptr[j + 1]]  # A(j, i) != 0 -> A^{-1}(i, j) selected
+        got = np.array([s.get(int(i), j) for i in rows])
+        ref = x[rows]
+        errs_n.append(np.abs(got - ref).max() / np.abs(ref).max())
+        errs_d.append(abs(s.get(j, j) - x[j]) / abs(x[j]))
+    return max(errs_n), max(errs_d)
+
+
+@pytest.fixture(scope="module")
+def sampled_c2():
+    from oracle.sampled import solve_column
+    w = config_c2()
+    js = [int(j) for j in np.random.default_rng(2).integers(0, w.n, 2)] + [int(w.perm[-1])]
+    xs = []
+    for j in js:
+        x, bound = solve_column(w.to_scipy(), j)
+        assert bound < 1e-13
+        xs.append(x)
+    return w, js, xs
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed_fp32", "mixed_bf16x3"])
+def test_c2_full_size(si, sampled_c2, prec):
+    w, js, xs = sampled_c2
+    say("c2", prec)
+    s = getattr(test_c2_full_size, "_s", None)
+    if s is None:
+        s = si.SelInv(w.n, w.colptr, w.rowind, w.perm, w.max_super, w.relax, w.pad_pct).factor(w.values)
+        test_c2_full_size._s = s
+    s.run(prec)
+    rr, cr = identity_residuals(w, s.get_selected())
+    en, ed = sampled_column_errors(s, w, js, xs)
+    say("c2", prec, "identity", rr, cr, "sampled", en, ed)
+    assert max(rr, cr) <= (1e-10 if prec == "fp64" else 1e-4)
+    assert max(en, ed) <= TOL[prec]
+
+
+@pytest.fixture(scope="module")
+def sampled_c4():
+    from oracle.sampled import solve_column
+    w = config_c4()
+    js = [int(j) for j in np.random.default_rng(4).integers(0, w.n, 2)] + [int(w.perm[-1])]
+    xs = []
+    for j in js:
+        x, bound = solve_column(w.to_scipy(), j)
+        assert bound < 1e-13
+        xs.append(x)
+    return w, js, xs
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed_fp32", "mixed_bf16x3"])
+def test_c4_full_size(si, sampled_c4, prec):
+    w, js, xs = sampled_c4
+    say("c4", prec)
+    s = getattr(test_c4_full_size, "_s", None)
+    if s is None:
+        s = si.SelInv(w.n, w.colptr, w.rowind, w.perm, w.max_super, w.relax, w.pad_pct).factor(w.values)
+        test_c4_full_size._s = s
+    s.run(prec)
+    rr, cr = identity_residuals(w, s.get_selected())
+    en, ed = sampled_column_errors(s, w, js, xs)
+    say("c4", prec, "identity", rr, cr, "sampled", en, ed)
+    assert max(rr, cr) <= (1e-10 if prec == "fp64" else 1e-4)
+    assert max(en, ed) <= TOL[prec]
