@@ -49,7 +49,7 @@ struct GemmTile {
     int32_t prob, m0, n0, pad;
 };
 
-// triangular inversion of one diagonal block: 4 columns (one per wave)
+// triangular inversion: one 64x64 diagonal sub-block of one supernode
 struct TriItem {
     const double *D;  // packed L\U, s x s column-major
     double *Linv, *Uinv;

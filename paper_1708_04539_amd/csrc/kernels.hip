@@ -1,14 +1,10 @@
 // kernels.hip -- gfx950 kernels of supernodal selected inversion
 // (arXiv:1708.04539, Algorithm 1).
 //
-//   tri_inv_kernel   (L_KK)^{-1} and (U_KK)^{-1} in FP64 (step 2 / step 4
-//                    initialisation), one wavefront per column.
-//   gemm_kernel      grouped GEMM C = alpha op(A) op(B) + beta Cin over a list
-//                    of 64x64 output tiles of many problems, on MFMA:
-//                    FP64 (v_mfma_f64_16x16x4), FP32 (v_mfma_f32_16x16x4) or a
-//                    two-term bfloat16 split of both operands with three
-//                    products (v_mfma_f32_16x16x32_bf16).  Used for the
-//                    normalisation of step 2, and steps 3, 4 and 5.
+//   tri_base_kernel  diagonal 64x64 sub-blocks of (L_KK)^{-1} and (U_KK)^{-1}
+//                    in FP64 (step 2 / step 4 initialisation); the rest of the
+//                    triangular inverses comes from GEMM rounds.
+//   (the grouped MFMA GEMM of steps 2-5 lives in gemm.hip)
 //   gather_kernel    G_K = A^{-T}(R_L(K), R_U(K)) from the diagonal blocks and
 //                    panels of the ancestors (Theorem 1), one 64x64 tile per
 //                    workgroup with the tile's index metadata staged in LDS;
@@ -22,244 +18,65 @@
 
 namespace selinv {
 
-typedef double v4d __attribute__((ext_vector_type(4)));
-typedef float v4f __attribute__((ext_vector_type(4)));
-typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
 // ---------------------------------------------------------------------------
-// triangular inversion
+// triangular inversion, diagonal 64x64 blocks
 // ---------------------------------------------------------------------------
-// Row i of a column is held by lane (i mod 64) in register x[i / 64]; the
-// substitution broadcasts the finished entry with a lane shuffle and updates
-// the remaining rows with coalesced loads of one column of the factor.
-constexpr int TRI_MAXM = TRI_MAX_S / 64;
-
-__global__ __launch_bounds__(256) void tri_inv_kernel(const TriItem *__restrict__ items) {
+// One wavefront handles the 64x64 diagonal sub-block that starts at
+// row/column o of one supernode's packed L_KK \ U_KK (column-major, s x s);
+// ragged sub-blocks (s - o < 64) are padded with the identity.
+//   UPPER = false: column l of (L_oo)^{-1} (forward substitution, unit
+//                  diagonal);
+//   UPPER = true:  column l of (U_oo^T)^{-1} = row l of (U_oo)^{-1} (forward
+//                  substitution on the transpose, dividing by the diagonal),
+//                  so that the stores of a row are coalesced across lanes.
+// Lane l keeps its 64 entries in registers; the substitution is fully
+// unrolled and every factor entry it uses is the same for all lanes (an LDS
+// broadcast).  The kernel also writes the zeros of L^{-1} above the sub-block
+// and of U^{-1} left of it; the off-diagonal blocks come from the GEMM rounds
+// of the recursive doubling (X21 = -B^{-1} C A^{-1} for L,
+// X12 = -A^{-1} C B^{-1} for U).
+template <bool UPPER>
+__global__ __launch_bounds__(64) void tri_base_kernel(const TriItem *__restrict__ items) {
     const TriItem it = items[blockIdx.x];
-    const int lane = threadIdx.x & 63;
-    const int j = it.j0 + (threadIdx.x >> 6);
-    const int s = it.s;
-    if (j >= s) return;
-    const double *D = it.D;
-    double x[TRI_MAXM];
-
-    // (L_KK)^{-1} e_j, L unit lower: forward substitution
+    const int l = threadIdx.x;
+    const int s = it.s, o = it.j0;
+    const int b = min(64, s - o);
+    // Ds[c][r] = D(o + r, o + c); reused for the result after the substitution
+    __shared__ double Ds[64][65];
+    for (int c = 0; c < 64; c++)
+        Ds[c][l] = (l < b && c < b) ? it.D[(int64_t)(o + l) + (int64_t)(o + c) * s] : (l == c ? 1.0 : 0.0);
+    __syncthreads();
+    double x[64];
 #pragma unroll
-    for (int m = 0; m < TRI_MAXM; m++) x[m] = (64 * m + lane == j) ? 1.0 : 0.0;
+    for (int r = 0; r < 64; r++) x[r] = (r == l) ? 1.0 : 0.0;
 #pragma unroll
-    for (int m = 0; m < TRI_MAXM; m++) {
-        if (64 * m >= s) break;
-        for (int kk = 0; kk < 64; kk++) {
-            const int k = 64 * m + kk;
-            if (k >= s) break;
-            if (k < j) continue;
-            const double xk = __shfl(x[m], kk, 64);
-            const double *col = D + (int64_t)k * s;
+    for (int k = 0; k < 64; k++) {
+        if constexpr (UPPER) x[k] = x[k] / Ds[k][k];
+        const double xk = x[k];
 #pragma unroll
-            for (int m2 = m; m2 < TRI_MAXM; m2++) {
-                const int i = 64 * m2 + lane;
-                if (i > k && i < s) x[m2] -= col[i] * xk;
-            }
-        }
+        for (int r = k + 1; r < 64; r++) x[r] -= (UPPER ? Ds[r][k] : Ds[k][r]) * xk;
     }
+    // Through LDS to global memory: x goes to row l of the tile (all 64
+    // entries, unconditionally), then each column of the result is written
+    // with the lanes along its rows (coalesced).  Lane l's x is column l of
+    // (L_oo)^{-1}, or row l of (U_oo)^{-1}.
+    __syncthreads();
+    double(&Xs)[64][65] = Ds;
 #pragma unroll
-    for (int m = 0; m < TRI_MAXM; m++) {
-        const int i = 64 * m + lane;
-        if (i < s) it.Linv[i + (int64_t)j * s] = x[m];
+    for (int r = 0; r < 64; r++) Xs[l][r] = x[r];
+    __syncthreads();
+    double *out = UPPER ? it.Uinv : it.Linv;
+    for (int c = 0; c < b; c++) {
+        double *col = out + (int64_t)(o + c) * s;
+        if (l < b) col[o + l] = UPPER ? Xs[l][c] : Xs[c][l];
+        // zeros of L^{-1} above the sub-block
+        if (!UPPER)
+            for (int r = l; r < o; r += 64) col[r] = 0.0;
     }
-
-    // (U_KK)^{-1} e_j, U upper: back substitution
-#pragma unroll
-    for (int m = 0; m < TRI_MAXM; m++) x[m] = (64 * m + lane == j) ? 1.0 : 0.0;
-#pragma unroll
-    for (int m = TRI_MAXM - 1; m >= 0; m--) {
-        if (64 * m > j) continue;
-        for (int kk = 63; kk >= 0; kk--) {
-            const int k = 64 * m + kk;
-            if (k > j) continue;
-            const double *col = D + (int64_t)k * s;
-            if (lane == kk) x[m] = x[m] / col[k];
-            const double xk = __shfl(x[m], kk, 64);
-#pragma unroll
-            for (int m2 = 0; m2 <= m; m2++) {
-                const int i = 64 * m2 + lane;
-                if (i < k) x[m2] -= col[i] * xk;
-            }
-        }
-    }
-#pragma unroll
-    for (int m = 0; m < TRI_MAXM; m++) {
-        const int i = 64 * m + lane;
-        if (i < s) it.Uinv[i + (int64_t)j * s] = x[m];
-    }
-}
-
-// ---------------------------------------------------------------------------
-// grouped GEMM on MFMA
-// ---------------------------------------------------------------------------
-// Tile 64x64, 256 threads = 4 wavefronts in a 2x2 arrangement, each owning a
-// 32x32 quarter as 2x2 MFMA 16x16 blocks.  The MFMA is fed with op(B) as its
-// first operand and op(A) as its second, i.e. it computes the transposed
-// product; a lane then holds four n-columns of one m-row, and the 16 lanes of
-// a row group store 16 consecutive rows of one column of the column-major C
-// (coalesced).
-constexpr int GBM = 64, GBN = 64;
-
-template <int MODE>
-struct GemmCfg;
-template <>
-struct GemmCfg<CMP_F64> {
-    typedef double T;
-    static constexpr int BK = 16;
-    typedef v4d Acc;
-};
-template <>
-struct GemmCfg<CMP_F32> {
-    typedef float T;
-    static constexpr int BK = 16;
-    typedef v4f Acc;
-};
-template <>
-struct GemmCfg<CMP_BF16X3> {
-    typedef float T;
-    static constexpr int BK = 32;
-    typedef v4f Acc;
-};
-
-__device__ inline void split_bf16(float x, __bf16 &hi, __bf16 &lo) {
-    hi = (__bf16)x;
-    lo = (__bf16)(x - (float)hi);
-}
-
-template <typename TA, typename TC, int MODE>
-__global__ __launch_bounds__(256) void gemm_kernel(const GemmProb *__restrict__ probs,
-                                                   const GemmTile *__restrict__ tiles) {
-    typedef typename GemmCfg<MODE>::T T;
-    typedef typename GemmCfg<MODE>::Acc Acc;
-    constexpr int BK = GemmCfg<MODE>::BK;
-    __shared__ T As[BK][GBM + 1];
-    __shared__ T Bs[BK][GBN + 1];
-
-    const GemmTile tl = tiles[blockIdx.x];
-    const GemmProb p = probs[tl.prob];
-    const TA *__restrict__ A = (const TA *)p.A;
-    const TA *__restrict__ B = (const TA *)p.B;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
-    const int m0 = tl.m0, n0 = tl.n0;
-    const int M = p.M, N = p.N, K = p.K;
-
-    Acc acc[2][2];
-#pragma unroll
-    for (int a = 0; a < 2; a++)
-#pragma unroll
-        for (int b = 0; b < 2; b++) acc[a][b] = Acc{0, 0, 0, 0};
-
-    for (int k0 = 0; k0 < K; k0 += BK) {
-        // stage op(A)(m0.., k0..) into As[k][m] and op(B)(k0.., n0..) into Bs[k][n]
-#pragma unroll
-        for (int e = tid; e < GBM * BK; e += 256) {
-            int i, k;
-            if (p.opA == 0) {
-                i = e % GBM;
-                k = e / GBM;
-            } else {
-                k = e % BK;
-                i = e / BK;
-            }
-            const int gi = m0 + i, gk = k0 + k;
-            T v = 0;
-            if (gi < M && gk < K)
-                v = (T)(p.opA == 0 ? A[gi + (int64_t)gk * p.lda] : A[gk + (int64_t)gi * p.lda]);
-            As[k][i] = v;
-        }
-#pragma unroll
-        for (int e = tid; e < GBN * BK; e += 256) {
-            int jn, k;
-            if (p.opB == 0) {
-                k = e % BK;
-                jn = e / BK;
-            } else {
-                jn = e % GBN;
-                k = e / GBN;
-            }
-            const int gj = n0 + jn, gk = k0 + k;
-            T v = 0;
-            if (gj < N && gk < K)
-                v = (T)(p.opB == 0 ? B[gk + (int64_t)gj * p.ldb] : B[gj + (int64_t)gk * p.ldb]);
-            Bs[k][jn] = v;
-        }
-        __syncthreads();
-        if constexpr (MODE == CMP_F64 || MODE == CMP_F32) {
-#pragma unroll
-            for (int kk = 0; kk < BK; kk += 4) {
-                const int kr = kk + (lane >> 4);
-                T av[2], bv[2];
-#pragma unroll
-                for (int t = 0; t < 2; t++) {
-                    av[t] = As[kr][wm * 32 + t * 16 + (lane & 15)];
-                    bv[t] = Bs[kr][wn * 32 + t * 16 + (lane & 15)];
-                }
-#pragma unroll
-                for (int si = 0; si < 2; si++)
-#pragma unroll
-                    for (int sj = 0; sj < 2; sj++) {
-                        if constexpr (MODE == CMP_F64)
-                            acc[si][sj] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[sj], av[si], acc[si][sj], 0, 0, 0);
-                        else
-                            acc[si][sj] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[sj], av[si], acc[si][sj], 0, 0, 0);
-                    }
-            }
-        } else {
-            // two-term bfloat16 split: x = hi + lo; products hi*hi + hi*lo + lo*hi
-            const int kb = 8 * (lane >> 4);
-            v8bf ah[2], al[2], bh[2], bl[2];
-#pragma unroll
-            for (int t = 0; t < 2; t++) {
-#pragma unroll
-                for (int e = 0; e < 8; e++) {
-                    __bf16 h, l;
-                    split_bf16(As[kb + e][wm * 32 + t * 16 + (lane & 15)], h, l);
-                    ah[t][e] = h;
-                    al[t][e] = l;
-                    split_bf16(Bs[kb + e][wn * 32 + t * 16 + (lane & 15)], h, l);
-                    bh[t][e] = h;
-                    bl[t][e] = l;
-                }
-            }
-#pragma unroll
-            for (int si = 0; si < 2; si++)
-#pragma unroll
-                for (int sj = 0; sj < 2; sj++) {
-                    acc[si][sj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bl[sj], ah[si], acc[si][sj], 0, 0, 0);
-                    acc[si][sj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh[sj], al[si], acc[si][sj], 0, 0, 0);
-                    acc[si][sj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh[sj], ah[si], acc[si][sj], 0, 0, 0);
-                }
-        }
-        __syncthreads();
-    }
-
-    TC *__restrict__ C = (TC *)p.C;
-    const TC *__restrict__ Cin = (const TC *)p.Cin;
-#pragma unroll
-    for (int si = 0; si < 2; si++)
-#pragma unroll
-        for (int sj = 0; sj < 2; sj++) {
-            const int gm = m0 + wm * 32 + si * 16 + (lane & 15);
-            if (gm >= M) continue;
-#pragma unroll
-            for (int v = 0; v < 4; v++) {
-                // result rows held by this lane: v_mfma_f64_16x16x4 interleaves the
-                // four row groups (row = lane/16 + 4v); the f32 and bf16 forms keep
-                // them contiguous (row = 4 (lane/16) + v)
-                const int nr = (MODE == CMP_F64) ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v;
-                const int gn = n0 + wn * 32 + sj * 16 + nr;
-                if (gn >= N) continue;
-                double r = p.alpha * (double)acc[si][sj][v];
-                if (Cin) r += p.beta * (double)Cin[gm + (int64_t)gn * p.ldcin];
-                C[gm + (int64_t)gn * p.ldc] = (TC)r;
-            }
-        }
+    // zeros of U^{-1} left of the sub-block (rows o .. o+b-1)
+    if (UPPER && l < b)
+        for (int c = 0; c < o; c++) out[(o + l) + (int64_t)c * s] = 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -349,35 +166,10 @@ __global__ __launch_bounds__(256) void extract_kernel(ExtractArgs a) {
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-hipError_t launch_tri_inv(const TriItem *items, int count, hipStream_t st) {
+hipError_t launch_tri_base(const TriItem *items, int count, hipStream_t st) {
     if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(tri_inv_kernel, dim3(count), dim3(256), 0, st, items);
-    return hipGetLastError();
-}
-
-hipError_t launch_gemm(int in_f64, int out_f64, int mode, const GemmProb *probs, const GemmTile *tiles,
-                       int ntiles, hipStream_t st) {
-    if (ntiles <= 0) return hipSuccess;
-    dim3 g(ntiles), b(256);
-    if (mode == CMP_F64) {
-        if (!in_f64) return hipErrorInvalidValue;
-        if (out_f64)
-            hipLaunchKernelGGL((gemm_kernel<double, double, CMP_F64>), g, b, 0, st, probs, tiles);
-        else
-            hipLaunchKernelGGL((gemm_kernel<double, float, CMP_F64>), g, b, 0, st, probs, tiles);
-    } else if (mode == CMP_F32) {
-        if (in_f64) return hipErrorInvalidValue;
-        if (out_f64)
-            hipLaunchKernelGGL((gemm_kernel<float, double, CMP_F32>), g, b, 0, st, probs, tiles);
-        else
-            hipLaunchKernelGGL((gemm_kernel<float, float, CMP_F32>), g, b, 0, st, probs, tiles);
-    } else {
-        if (in_f64) return hipErrorInvalidValue;
-        if (out_f64)
-            hipLaunchKernelGGL((gemm_kernel<float, double, CMP_BF16X3>), g, b, 0, st, probs, tiles);
-        else
-            hipLaunchKernelGGL((gemm_kernel<float, float, CMP_BF16X3>), g, b, 0, st, probs, tiles);
-    }
+    hipLaunchKernelGGL(tri_base_kernel<false>, dim3(count), dim3(64), 0, st, items);
+    hipLaunchKernelGGL(tri_base_kernel<true>, dim3(count), dim3(64), 0, st, items);
     return hipGetLastError();
 }
 

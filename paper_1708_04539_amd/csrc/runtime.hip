@@ -2,7 +2,8 @@
 // handle life cycle, device buffers, per-level work lists and the level sweep.
 //
 // One run (selinv_run) is
-//   tri_inv              (L_KK)^{-1}, (U_KK)^{-1} for every supernode
+//   tri_base + gemm      (L_KK)^{-1}, (U_KK)^{-1} for every supernode (64x64
+//                        diagonal sub-blocks, then recursive-doubling rounds)
 //   gemm [F64]           Lhat = L(R_L,K) (L_KK)^{-1},  Uhat^T = U(K,R_U)^T (U_KK)^{-T}
 //   gemm [F64]           A^{-T}(K,K) := (L_KK)^{-T} (U_KK)^{-T}
 //   for level = 0 .. depth-1 (root first; Algorithm 1 walks K = N..1 and a
@@ -15,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -37,6 +39,7 @@ struct PrecBufs {
 struct Range {
     int64_t off = 0;
     int count = 0;
+    int tile = GEMM_TILE_64;
 };
 
 struct Sweep {
@@ -47,6 +50,7 @@ struct Sweep {
     GemmTile *d_tiles = nullptr;
     GatherTile *d_gt = nullptr;
     Range tri, norm, dt;
+    std::vector<Range> tri_rounds;  // pairs (T products, X products) per doubling round
     std::vector<Range> gat, g35, g4;
     std::vector<double> lev_flops35, lev_flops4, lev_gather_elems;
     std::vector<int> lev_nsup, lev_maxs;
@@ -81,6 +85,7 @@ struct selinv_handle_s {
     std::vector<SnRec> sn;
     int64_t g_elems = 0;
     double *d_diag = nullptr, *d_lpan = nullptr, *d_upan = nullptr, *d_Linv = nullptr, *d_Uinv = nullptr;
+    double *d_tl = nullptr, *d_tu = nullptr;  // scratch of the triangular-inversion rounds
     SnRec *d_sn = nullptr;
     int32_t *d_supof = nullptr, *d_rl = nullptr, *d_ru = nullptr, *d_mapL = nullptr, *d_mapU = nullptr;
     int64_t *d_lcol = nullptr, *d_urow = nullptr, *d_aloc = nullptr;
@@ -139,9 +144,29 @@ selinv_status ensure_prec(selinv_handle h, int prec) {
     return SELINV_OK;
 }
 
-void add_tiles(std::vector<GemmTile> &tiles, int prob, int M, int N) {
-    for (int n0 = 0; n0 < N; n0 += 64)
-        for (int m0 = 0; m0 < M; m0 += 64) tiles.push_back(GemmTile{prob, m0, n0, 0});
+void add_tiles(std::vector<GemmTile> &tiles, int prob, int M, int N, int T) {
+    for (int n0 = 0; n0 < N; n0 += T)
+        for (int m0 = 0; m0 < M; m0 += T) tiles.push_back(GemmTile{prob, m0, n0, 0});
+}
+
+// Tiles of one GEMM launch over problems [first, probs.size()).  128x128
+// tiles when they still give a few waves of work over the 256 compute units
+// and waste little more of their area than 64x64 tiles would; 64x64
+// otherwise (small supernodes near the leaves).
+void emit_launch(const std::vector<GemmProb> &probs, size_t first, std::vector<GemmTile> &tiles, Range &r) {
+    double area = 0, t128 = 0, t64 = 0;
+    for (size_t q = first; q < probs.size(); q++) {
+        const double M = probs[q].M, N = probs[q].N;
+        area += M * N;
+        t128 += std::ceil(M / 128) * std::ceil(N / 128);
+        t64 += std::ceil(M / 64) * std::ceil(N / 64);
+    }
+    r.tile = GEMM_TILE_64;
+    if (t128 > 0 && t128 >= 192 && area / (t128 * 128 * 128) >= 0.75 * area / (t64 * 64 * 64))
+        r.tile = GEMM_TILE_128;
+    r.off = tiles.size();
+    for (size_t q = first; q < probs.size(); q++) add_tiles(tiles, (int)q, probs[q].M, probs[q].N, r.tile);
+    r.count = (int)(tiles.size() - r.off);
 }
 
 // Device allocations a work list may touch: [base, base + bytes).
@@ -160,7 +185,7 @@ struct Extents {
     }
 };
 
-int add_prob(std::vector<GemmProb> &probs, std::vector<GemmTile> &tiles, const void *A, int opA, int lda,
+int add_prob(std::vector<GemmProb> &probs, const void *A, int opA, int lda,
              const void *B, int opB, int ldb, void *C, int ldc, const void *Cin, int ldcin, int M, int N, int K,
              double alpha, double beta, Extents *ext = nullptr, int ein = 8, int eout = 8) {
     if (M <= 0 || N <= 0) return 0;
@@ -189,9 +214,7 @@ int add_prob(std::vector<GemmProb> &probs, std::vector<GemmTile> &tiles, const v
     p.alpha = alpha;
     p.beta = beta;
     probs.push_back(p);
-    size_t before = tiles.size();
-    add_tiles(tiles, (int)probs.size() - 1, M, N);
-    return (int)(tiles.size() - before);
+    return 1;
 }
 
 // Build the work lists of one sweep over a set of factored handles.
@@ -219,6 +242,9 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, std::unique_
         X.add(h->d_upan, P.tot_u * 8);
         X.add(h->d_Linv, P.tot_d * 8);
         X.add(h->d_Uinv, P.tot_d * 8);
+        X.add(h->d_tl, P.tot_d * 8);
+        X.add(h->d_tu, P.tot_d * 8);
+        X.add(h->d_diag, P.tot_d * 8);
         X.add(b.Zd, P.tot_d * 8);
         X.add(b.ZL, P.tot_l * e);
         X.add(b.ZU, P.tot_u * e);
@@ -241,37 +267,82 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, std::unique_
         mats.push_back(m);
         depth = std::max(depth, h->P.nlevels);
     }
-    // diagonal-block inversion
+    // diagonal-block inversion: 64x64 diagonal sub-blocks, then recursive
+    // doubling.  Round h joins neighbouring inverted blocks A (h x h, at o) and
+    // B (h' x h', at o + h) of every supernode wider than h:
+    //   L: X21 = -B^{-1} (C A^{-1}),   C = L(o+h.., o..)
+    //   U: X12 = -A^{-1} (C B^{-1}),   C = U(o.., o+h..)
+    // the inner products go to scratch (tl / tu) in a first launch, the outer
+    // ones into L^{-1} / U^{-1} in a second.
     for (auto h : hs)
         for (int32_t K = 0; K < h->P.ns; K++) {
             const SnRec &r = h->sn[K];
-            for (int j0 = 0; j0 < r.s; j0 += 4)
+            for (int j0 = 0; j0 < r.s; j0 += 64)
                 tri.push_back(TriItem{h->d_diag + r.off_d, h->d_Linv + r.off_d, h->d_Uinv + r.off_d, r.s, j0});
         }
     S->tri.count = (int)tri.size();
+    for (int hb = 64;; hb *= 2) {
+        bool any = false;
+        for (auto h : hs)
+            for (const SnRec &r : h->sn) any |= r.s > hb;
+        if (!any) break;
+        for (int part = 0; part < 2; part++) {
+            size_t first0 = probs.size();
+            for (auto h : hs)
+                for (const SnRec &r : h->sn) {
+                    if (r.s <= hb) continue;
+                    const int64_t s_ = r.s;
+                    const double *D = h->d_diag + r.off_d;
+                    double *Li = h->d_Linv + r.off_d, *Ui = h->d_Uinv + r.off_d;
+                    for (int o = 0; o + hb < r.s; o += 2 * hb) {
+                        const int hp = std::min(hb, r.s - o - hb);
+                        double *TL = h->d_tl + r.off_d + (int64_t)o * hb;
+                        double *TU = h->d_tu + r.off_d + (int64_t)o * hb;
+                        const int64_t oo = o + (int64_t)o * s_, ob = (o + hb) + (int64_t)(o + hb) * s_;
+                        const int64_t lo_off = (o + hb) + (int64_t)o * s_, up_off = o + (int64_t)(o + hb) * s_;
+                        if (part == 0) {
+                            add_prob(probs, D + lo_off, 0, r.s, Li + oo, 0, r.s, TL, hp, nullptr, 1, hp, hb, hb, 1.0,
+                                     0.0, &X, 8, 8);
+                            add_prob(probs, D + up_off, 0, r.s, Ui + ob, 0, r.s, TU, hb, nullptr, 1, hb, hp, hp, 1.0,
+                                     0.0, &X, 8, 8);
+                        } else {
+                            add_prob(probs, Li + ob, 0, r.s, TL, 0, hp, Li + lo_off, r.s, nullptr, 1, hp, hb, hp, -1.0,
+                                     0.0, &X, 8, 8);
+                            add_prob(probs, Ui + oo, 0, r.s, TU, 0, hb, Ui + up_off, r.s, nullptr, 1, hb, hp, hb, -1.0,
+                                     0.0, &X, 8, 8);
+                        }
+                    }
+                }
+            Range rr;
+            emit_launch(probs, first0, tiles, rr);
+            S->tri_rounds.push_back(rr);
+        }
+    }
     // normalisation (FP64 arithmetic, output in the run's precision)
-    S->norm.off = tiles.size();
+    size_t first = probs.size();
     for (auto h : hs) {
         const PrecBufs &b = h->pb[prec];
         for (int32_t K = 0; K < h->P.ns; K++) {
             const SnRec &r = h->sn[K];
             char *Lh = (char *)b.Lh + r.off_l * e;
             char *Uh = (char *)b.Uh + r.off_u * e;
-            S->norm.count += add_prob(probs, tiles, h->d_lpan + r.off_l, 0, r.cl, h->d_Linv + r.off_d, 0, r.s, Lh,
+            add_prob(probs, h->d_lpan + r.off_l, 0, r.cl, h->d_Linv + r.off_d, 0, r.s, Lh,
                                       r.cl, nullptr, 1, r.cl, r.s, r.s, 1.0, 0.0, &X, 8, e);
-            S->norm.count += add_prob(probs, tiles, h->d_upan + r.off_u, 0, r.cu, h->d_Uinv + r.off_d, 1, r.s, Uh,
+            add_prob(probs, h->d_upan + r.off_u, 0, r.cu, h->d_Uinv + r.off_d, 1, r.s, Uh,
                                       r.cu, nullptr, 1, r.cu, r.s, r.s, 1.0, 0.0, &X, 8, e);
         }
     }
-    S->dt.off = tiles.size();
+    emit_launch(probs, first, tiles, S->norm);
+    first = probs.size();
     for (auto h : hs) {
         const PrecBufs &b = h->pb[prec];
         for (int32_t K = 0; K < h->P.ns; K++) {
             const SnRec &r = h->sn[K];
-            S->dt.count += add_prob(probs, tiles, h->d_Linv + r.off_d, 1, r.s, h->d_Uinv + r.off_d, 1, r.s,
+            add_prob(probs, h->d_Linv + r.off_d, 1, r.s, h->d_Uinv + r.off_d, 1, r.s,
                                     b.Zd + r.off_d, r.s, nullptr, 1, r.s, r.s, r.s, 1.0, 0.0, &X, 8, 8);
         }
     }
+    emit_launch(probs, first, tiles, S->dt);
     S->gat.resize(depth);
     S->g35.resize(depth);
     S->g4.resize(depth);
@@ -295,7 +366,7 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, std::unique_
             }
         }
         S->gat[d].count = (int)(gts.size() - S->gat[d].off);
-        S->g35[d].off = tiles.size();
+        first = probs.size();
         for (auto h : hs) {
             if (d >= h->P.nlevels) continue;
             const PrecBufs &b = h->pb[prec];
@@ -305,16 +376,16 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, std::unique_
                 char *Lh = (char *)b.Lh + r.off_l * e, *Uh = (char *)b.Uh + r.off_u * e;
                 char *ZL = (char *)b.ZL + r.off_l * e, *ZU = (char *)b.ZU + r.off_u * e;
                 // step 3 (stored transposed): A^{-T}(K,R_U)^T = -G^T Lhat
-                S->g35[d].count += add_prob(probs, tiles, G, 1, r.cl, Lh, 0, r.cl, ZU, r.cu, nullptr, 1, r.cu, r.s,
+                add_prob(probs, G, 1, r.cl, Lh, 0, r.cl, ZU, r.cu, nullptr, 1, r.cu, r.s,
                                             r.cl, -1.0, 0.0, &X, e, e);
                 // step 5: A^{-T}(R_L,K) = -G Uhat^T
-                S->g35[d].count += add_prob(probs, tiles, G, 0, r.cl, Uh, 0, r.cu, ZL, r.cl, nullptr, 1, r.cl, r.s,
+                add_prob(probs, G, 0, r.cl, Uh, 0, r.cu, ZL, r.cl, nullptr, 1, r.cl, r.s,
                                             r.cu, -1.0, 0.0, &X, e, e);
                 S->lev_flops35[d] += 4.0 * r.s * (double)r.cl * r.cu;
             }
         }
-        S->g35[d].count = (int)(tiles.size() - S->g35[d].off);
-        S->g4[d].off = tiles.size();
+        emit_launch(probs, first, tiles, S->g35[d]);
+        first = probs.size();
         for (auto h : hs) {
             if (d >= h->P.nlevels) continue;
             const PrecBufs &b = h->pb[prec];
@@ -323,12 +394,12 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, std::unique_
                 if (r.cu == 0) continue;
                 char *Uh = (char *)b.Uh + r.off_u * e, *ZU = (char *)b.ZU + r.off_u * e;
                 // step 4: A^{-T}(K,K) = (L_KK)^{-T}(U_KK)^{-T} - A^{-T}(K,R_U) Uhat^T
-                S->g4[d].count += add_prob(probs, tiles, ZU, 1, r.cu, Uh, 0, r.cu, b.Zd + r.off_d, r.s,
+                add_prob(probs, ZU, 1, r.cu, Uh, 0, r.cu, b.Zd + r.off_d, r.s,
                                            b.Zd + r.off_d, r.s, r.s, r.s, r.cu, -1.0, 1.0, &X, e, 8);
                 S->lev_flops4[d] += 2.0 * r.s * (double)r.s * r.cu;
             }
         }
-        S->g4[d].count = (int)(tiles.size() - S->g4[d].off);
+        emit_launch(probs, first, tiles, S->g4[d]);
     }
     // gather tiles stay inside their supernode's G block
     for (const GatherTile &t : gts) {
@@ -362,18 +433,20 @@ hipError_t launch_sweep(const Sweep &S, hipStream_t st, std::vector<hipEvent_t> 
         if (ev) (void)hipEventRecord((*ev)[i], st);
     };
     mark(0);
-    if ((e = launch_tri_inv(S.d_tri, S.tri.count, st))) return e;
+    if ((e = launch_tri_base(S.d_tri, S.tri.count, st))) return e;
+    for (const Range &r : S.tri_rounds)
+        if ((e = launch_gemm(1, 1, CMP_F64, r.tile, S.d_probs, S.d_tiles + r.off, r.count, st))) return e;
     mark(1);
-    if ((e = launch_gemm(1, f64, CMP_F64, S.d_probs, S.d_tiles + S.norm.off, S.norm.count, st))) return e;
+    if ((e = launch_gemm(1, f64, CMP_F64, S.norm.tile, S.d_probs, S.d_tiles + S.norm.off, S.norm.count, st))) return e;
     mark(2);
-    if ((e = launch_gemm(1, 1, CMP_F64, S.d_probs, S.d_tiles + S.dt.off, S.dt.count, st))) return e;
+    if ((e = launch_gemm(1, 1, CMP_F64, S.dt.tile, S.d_probs, S.d_tiles + S.dt.off, S.dt.count, st))) return e;
     mark(3);
     for (size_t d = 0; d < S.gat.size(); d++) {
         if ((e = launch_gather(f64, S.d_mats, S.d_gt + S.gat[d].off, S.gat[d].count, st))) return e;
         mark(4 + 3 * d);
-        if ((e = launch_gemm(f64, f64, mode, S.d_probs, S.d_tiles + S.g35[d].off, S.g35[d].count, st))) return e;
+        if ((e = launch_gemm(f64, f64, mode, S.g35[d].tile, S.d_probs, S.d_tiles + S.g35[d].off, S.g35[d].count, st))) return e;
         mark(5 + 3 * d);
-        if ((e = launch_gemm(f64, 1, mode, S.d_probs, S.d_tiles + S.g4[d].off, S.g4[d].count, st))) return e;
+        if ((e = launch_gemm(f64, 1, mode, S.g4[d].tile, S.d_probs, S.d_tiles + S.g4[d].off, S.g4[d].count, st))) return e;
         mark(6 + 3 * d);
     }
     return hipSuccess;
@@ -480,6 +553,8 @@ selinv_status selinv_factor(selinv_handle h, const double *values) {
         HIPCHK(h->err, alloc_bytes((void **)&h->d_upan, P.tot_u * 8), "alloc upan");
         HIPCHK(h->err, alloc_bytes((void **)&h->d_Linv, P.tot_d * 8), "alloc Linv");
         HIPCHK(h->err, alloc_bytes((void **)&h->d_Uinv, P.tot_d * 8), "alloc Uinv");
+        HIPCHK(h->err, alloc_bytes((void **)&h->d_tl, P.tot_d * 8), "alloc tri scratch");
+        HIPCHK(h->err, alloc_bytes((void **)&h->d_tu, P.tot_d * 8), "alloc tri scratch");
         HIPCHK(h->err, upload(&h->d_sn, h->sn), "upload sn");
         HIPCHK(h->err, upload(&h->d_supof, P.supof), "upload supof");
         HIPCHK(h->err, upload(&h->d_rl, P.rl), "upload rl");
@@ -770,6 +845,7 @@ void selinv_destroy(selinv_handle h) {
         (void)hipFree(b.G);
     }
     for (void *q : {(void *)h->d_diag, (void *)h->d_lpan, (void *)h->d_upan, (void *)h->d_Linv, (void *)h->d_Uinv,
+                    (void *)h->d_tl, (void *)h->d_tu,
                     (void *)h->d_sn, (void *)h->d_supof, (void *)h->d_rl, (void *)h->d_ru, (void *)h->d_mapL,
                     (void *)h->d_mapU, (void *)h->d_lcol, (void *)h->d_urow, (void *)h->d_aloc})
         (void)hipFree(q);
