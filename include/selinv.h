@@ -185,9 +185,11 @@ selinv_status selinv_check_plan(selinv_handle h, int64_t *mismatches);
 selinv_status selinv_set_profiling(selinv_handle h, int32_t on);
 selinv_status selinv_timings(selinv_handle h, double *ms, int32_t count);
 
-/* Work of one level of the last run's sweep: stats[0] supernodes, [1] widest
- * supernode, [2] flops of steps 3+5, [3] flops of step 4, [4] entries of G
- * gathered, [5] gather tiles, [6] product tiles of steps 3+5, [7] of step 4. */
+/* Work of one level of the last run's sweep (stats: 10 doubles): [0]
+ * supernodes, [1] widest supernode, [2] flops of steps 3+5, [3] flops of step
+ * 4, [4] entries of G gathered, [5] gather tiles, [6] product tiles of steps
+ * 3+5, [7] of step 4, [8] and [9] the output tile edge (64 or 128) of those two
+ * product launches. */
 selinv_status selinv_level_stats(selinv_handle h, int32_t level, double *stats);
 
 /* Message of the last failure on handle h; with h == NULL, of the last failed

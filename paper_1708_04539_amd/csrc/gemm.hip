@@ -72,7 +72,10 @@ struct Smem<CMP_BF16X3, BM, BN> {
     __bf16 bh[2][BN][P], bl[2][BN][P];
 };
 
-template <int MODE, int BM, int BN, typename TA, typename TC>
+// ROLE only names the launch site in profiles (0: triangular inversion,
+// normalisation and diagonal initialisation; 1: products of steps 3 and 5;
+// 2: product of step 4); the code is the same.
+template <int MODE, int BM, int BN, typename TA, typename TC, int ROLE>
 __global__ __launch_bounds__(256) void gemm_v2(const GemmProb *__restrict__ probs,
                                                const GemmTile *__restrict__ tiles) {
     typedef typename Mode<MODE>::T T;
@@ -250,39 +253,47 @@ __global__ __launch_bounds__(256) void gemm_v2(const GemmProb *__restrict__ prob
         }
 }
 
-template <int MODE, typename TA, typename TC>
+template <int MODE, typename TA, typename TC, int ROLE>
 static void launch_mode(int tile, const GemmProb *probs, const GemmTile *tiles, int ntiles, hipStream_t st) {
     if (tile == GEMM_TILE_128)
-        hipLaunchKernelGGL((gemm_v2<MODE, 128, 128, TA, TC>), dim3(ntiles), dim3(256), 0, st, probs, tiles);
+        hipLaunchKernelGGL((gemm_v2<MODE, 128, 128, TA, TC, ROLE>), dim3(ntiles), dim3(256), 0, st, probs, tiles);
     else
-        hipLaunchKernelGGL((gemm_v2<MODE, 64, 64, TA, TC>), dim3(ntiles), dim3(256), 0, st, probs, tiles);
+        hipLaunchKernelGGL((gemm_v2<MODE, 64, 64, TA, TC, ROLE>), dim3(ntiles), dim3(256), 0, st, probs, tiles);
 }
 
-hipError_t launch_gemm(int in_f64, int out_f64, int mode, int tile, const GemmProb *probs, const GemmTile *tiles,
-                       int ntiles, hipStream_t st) {
+hipError_t launch_gemm(int role, int mode, int tile, const GemmProb *probs, const GemmTile *tiles, int ntiles,
+                       hipStream_t st) {
     if (ntiles <= 0) return hipSuccess;
     if (tile != GEMM_TILE_64 && tile != GEMM_TILE_128) return hipErrorInvalidValue;
-    if (mode == CMP_F64) {
-        if (!in_f64) return hipErrorInvalidValue;
-        if (out_f64)
-            launch_mode<CMP_F64, double, double>(tile, probs, tiles, ntiles, st);
-        else
-            launch_mode<CMP_F64, double, float>(tile, probs, tiles, ntiles, st);
-    } else if (mode == CMP_F32 || mode == CMP_BF16X3) {
-        if (in_f64) return hipErrorInvalidValue;
-        if (mode == CMP_F32) {
-            if (out_f64)
-                launch_mode<CMP_F32, float, double>(tile, probs, tiles, ntiles, st);
+    switch (role) {
+        case GEMM_PRO_F64:  // FP64 in and out
+            launch_mode<CMP_F64, double, double, 0>(tile, probs, tiles, ntiles, st);
+            break;
+        case GEMM_PRO_F32OUT:  // FP64 in, FP32 out (normalised panels of the mixed forms)
+            launch_mode<CMP_F64, double, float, 0>(tile, probs, tiles, ntiles, st);
+            break;
+        case GEMM_STEP35:  // operands and results in the run's storage precision
+            if (mode == CMP_F64)
+                launch_mode<CMP_F64, double, double, 1>(tile, probs, tiles, ntiles, st);
+            else if (mode == CMP_F32)
+                launch_mode<CMP_F32, float, float, 1>(tile, probs, tiles, ntiles, st);
+            else if (mode == CMP_BF16X3)
+                launch_mode<CMP_BF16X3, float, float, 1>(tile, probs, tiles, ntiles, st);
             else
-                launch_mode<CMP_F32, float, float>(tile, probs, tiles, ntiles, st);
-        } else {
-            if (out_f64)
-                launch_mode<CMP_BF16X3, float, double>(tile, probs, tiles, ntiles, st);
+                return hipErrorInvalidValue;
+            break;
+        case GEMM_STEP4:  // FP64 accumulation into the diagonal block
+            if (mode == CMP_F64)
+                launch_mode<CMP_F64, double, double, 2>(tile, probs, tiles, ntiles, st);
+            else if (mode == CMP_F32)
+                launch_mode<CMP_F32, float, double, 2>(tile, probs, tiles, ntiles, st);
+            else if (mode == CMP_BF16X3)
+                launch_mode<CMP_BF16X3, float, double, 2>(tile, probs, tiles, ntiles, st);
             else
-                launch_mode<CMP_BF16X3, float, float>(tile, probs, tiles, ntiles, st);
-        }
-    } else {
-        return hipErrorInvalidValue;
+                return hipErrorInvalidValue;
+            break;
+        default:
+            return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }

@@ -16,10 +16,18 @@ hipError_t launch_tri_base(const TriItem *items, int count, hipStream_t st);
 // output tile of the grouped GEMM
 enum : int { GEMM_TILE_64 = 64, GEMM_TILE_128 = 128 };
 
-// in_f64: operands in FP64 (else FP32); out_f64: C / Cin in FP64 (else FP32);
-// tile: GEMM_TILE_64 or GEMM_TILE_128 (the tile list must use the same size)
-hipError_t launch_gemm(int in_f64, int out_f64, int mode, int tile, const GemmProb *probs,
-                       const GemmTile *tiles, int ntiles, hipStream_t st);
+// launch sites of the grouped GEMM (each is its own kernel symbol in profiles)
+enum : int {
+    GEMM_PRO_F64 = 0,     // FP64 -> FP64 (triangular rounds, normalisation, diag init)
+    GEMM_PRO_F32OUT = 1,  // FP64 -> FP32 (normalisation in the mixed forms)
+    GEMM_STEP35 = 2,      // steps 3 and 5, operands/results in the storage precision
+    GEMM_STEP4 = 3        // step 4, accumulated into the FP64 diagonal block
+};
+
+// mode: arithmetic for GEMM_STEP35 / GEMM_STEP4 (CMP_*); tile: GEMM_TILE_64 or
+// GEMM_TILE_128 (the tile list must use the same size)
+hipError_t launch_gemm(int role, int mode, int tile, const GemmProb *probs, const GemmTile *tiles, int ntiles,
+                       hipStream_t st);
 hipError_t launch_gather(int f64, const MatDev *mats, const GatherTile *tiles, int ntiles, hipStream_t st);
 hipError_t launch_extract(int f64, const ExtractArgs &a, hipStream_t st);
 

@@ -435,18 +435,21 @@ hipError_t launch_sweep(const Sweep &S, hipStream_t st, std::vector<hipEvent_t> 
     mark(0);
     if ((e = launch_tri_base(S.d_tri, S.tri.count, st))) return e;
     for (const Range &r : S.tri_rounds)
-        if ((e = launch_gemm(1, 1, CMP_F64, r.tile, S.d_probs, S.d_tiles + r.off, r.count, st))) return e;
+        if ((e = launch_gemm(GEMM_PRO_F64, CMP_F64, r.tile, S.d_probs, S.d_tiles + r.off, r.count, st))) return e;
     mark(1);
-    if ((e = launch_gemm(1, f64, CMP_F64, S.norm.tile, S.d_probs, S.d_tiles + S.norm.off, S.norm.count, st))) return e;
+    if ((e = launch_gemm(f64 ? GEMM_PRO_F64 : GEMM_PRO_F32OUT, CMP_F64, S.norm.tile, S.d_probs,
+                         S.d_tiles + S.norm.off, S.norm.count, st))) return e;
     mark(2);
-    if ((e = launch_gemm(1, 1, CMP_F64, S.dt.tile, S.d_probs, S.d_tiles + S.dt.off, S.dt.count, st))) return e;
+    if ((e = launch_gemm(GEMM_PRO_F64, CMP_F64, S.dt.tile, S.d_probs, S.d_tiles + S.dt.off, S.dt.count, st))) return e;
     mark(3);
     for (size_t d = 0; d < S.gat.size(); d++) {
         if ((e = launch_gather(f64, S.d_mats, S.d_gt + S.gat[d].off, S.gat[d].count, st))) return e;
         mark(4 + 3 * d);
-        if ((e = launch_gemm(f64, f64, mode, S.g35[d].tile, S.d_probs, S.d_tiles + S.g35[d].off, S.g35[d].count, st))) return e;
+        if ((e = launch_gemm(GEMM_STEP35, mode, S.g35[d].tile, S.d_probs, S.d_tiles + S.g35[d].off,
+                             S.g35[d].count, st))) return e;
         mark(5 + 3 * d);
-        if ((e = launch_gemm(f64, 1, mode, S.g4[d].tile, S.d_probs, S.d_tiles + S.g4[d].off, S.g4[d].count, st))) return e;
+        if ((e = launch_gemm(GEMM_STEP4, mode, S.g4[d].tile, S.d_probs, S.d_tiles + S.g4[d].off, S.g4[d].count,
+                             st))) return e;
         mark(6 + 3 * d);
     }
     return hipSuccess;
@@ -681,6 +684,8 @@ selinv_status selinv_level_stats(selinv_handle h, int32_t level, double *stats) 
     stats[5] = S.gat[level].count;
     stats[6] = S.g35[level].count;
     stats[7] = S.g4[level].count;
+    stats[8] = S.g35[level].tile;
+    stats[9] = S.g4[level].tile;
     return SELINV_OK;
 }
 

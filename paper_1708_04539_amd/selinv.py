@@ -211,9 +211,10 @@ class SelInv:
         return out
 
     def level_stats(self, level):
-        out = np.zeros(8, np.float64)
+        out = np.zeros(10, np.float64)
         self._check(_lib.selinv_level_stats(self._h, int(level), _p(out, C.c_double)), "level_stats")
-        keys = ["nsup", "max_s", "flops35", "flops4", "gather_elems", "gather_tiles", "tiles35", "tiles4"]
+        keys = ["nsup", "max_s", "flops35", "flops4", "gather_elems", "gather_tiles", "tiles35", "tiles4",
+                "tile35", "tile4"]
         return dict(zip(keys, out.tolist()))
 
     @property
