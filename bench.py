@@ -38,6 +38,7 @@ def parse():
     ap.add_argument("--precision", default=None, help="fp64 | mixed_fp32 | mixed_bf16x3 (default: per config)")
     ap.add_argument("--mixed", default="mixed_fp32", help="mixed form reported beside the main one")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--sweep", default="auto", choices=["auto", "levels", "persistent"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="bound on the oracle's CPU time")
     return ap.parse_args()
@@ -92,20 +93,24 @@ def phase_profile(s, prec, stream, reps=5):
         "tri_inv_ms": float(t[0]),
         "normalise_ms": float(t[1]),
         "diag_init_ms": float(t[2]),
-        "gather_ms": float(sum(t[3 + 3 * d] for d in range(L))),
-        "gemm35_ms": float(sum(t[4 + 3 * d] for d in range(L))),
-        "gemm4_ms": float(sum(t[5 + 3 * d] for d in range(L))),
+        "small_ms": float(sum(t[3 + 4 * d] for d in range(L))),
+        "gather_ms": float(sum(t[4 + 4 * d] for d in range(L))),
+        "gemm35_ms": float(sum(t[5 + 4 * d] for d in range(L))),
+        "gemm4_ms": float(sum(t[6 + 4 * d] for d in range(L))),
     }
     launches = []
     for d in range(L):
+        if lev[d]["small_count"] > 0:
+            launches.append({"cls": "small", "tile": 64, "ms": float(t[3 + 4 * d]),
+                             "flops": lev[d]["small_flops"]})
         if lev[d]["gather_tiles"] > 0:
-            launches.append({"cls": "gather", "tile": 64, "ms": float(t[3 + 3 * d]),
+            launches.append({"cls": "gather", "tile": 64, "ms": float(t[4 + 4 * d]),
                              "elems": lev[d]["gather_elems"]})
         if lev[d]["tiles35"] > 0:
-            launches.append({"cls": "gemm35", "tile": int(lev[d]["tile35"]), "ms": float(t[4 + 3 * d]),
+            launches.append({"cls": "gemm35", "tile": int(lev[d]["tile35"]), "ms": float(t[5 + 4 * d]),
                              "flops": lev[d]["flops35"]})
         if lev[d]["tiles4"] > 0:
-            launches.append({"cls": "gemm4", "tile": int(lev[d]["tile4"]), "ms": float(t[5 + 3 * d]),
+            launches.append({"cls": "gemm4", "tile": int(lev[d]["tile4"]), "ms": float(t[6 + 4 * d]),
                              "flops": lev[d]["flops4"]})
     ph["launches"] = launches
     return ph
@@ -116,6 +121,7 @@ KERNEL_SYMBOL = {
     "gemm35": "selinv::gemm_v2<{mode}, {t}, {t}, {T}, {T}, 1>",
     "gemm4": "selinv::gemm_v2<{mode}, {t}, {t}, {T}, double, 2>",
     "gather": "selinv::gather_kernel<{T}>",
+    "small": "selinv::small_kernel<{mode}>",
 }
 
 
@@ -184,6 +190,7 @@ def main():
     stream = torch.cuda.Stream()  # graphs cannot be captured on the legacy null stream
     t0 = time.perf_counter()
     s = SelInv(w.n, w.colptr, w.rowind, w.perm, w.max_super, w.relax, w.pad_pct)
+    s.set_sweep_mode(args.sweep)
     t_an = time.perf_counter() - t0
     t0 = time.perf_counter()
     s.factor(w.values)
@@ -225,7 +232,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.config], "n": w.n, "nnz": w.nnz, "precision": prec,
                    "supernodes": info["nsuper"], "levels": info["nlevels"], "gflop": F / 1e9,
-                   "hip_graph": graph, "parallelism": "single GPU"},
+                   "hip_graph": graph, "sweep": "persistent" if s.sweep_is_persistent(prec) == 1 else "levels",
+                   "parallelism": "single GPU"},
         "wall_s_timed": wall_s,
         "setup_s": {"analyze": t_an, "factor_host_lu_and_h2d": t_fa},
         "phases_ms": {k: v for k, v in ph.items() if k.endswith("_ms")},

@@ -135,12 +135,27 @@ selinv_status selinv_run(selinv_handle h, selinv_precision prec, void *stream);
  * once into a HIP graph per (handle, precision) and replayed. */
 selinv_status selinv_run_graph(selinv_handle h, selinv_precision prec, void *stream);
 
+/* How the level sweep is launched.
+ *   0 (auto, default): persistent when the levels are too small to fill the
+ *     device on their own, per-level launches otherwise;
+ *   1: one launch per kernel class per level (gather, steps 3+5, step 4);
+ *   2: one persistent, dependency-driven launch for the whole sweep
+ *     (section on inter-supernode parallelism: tasks start as soon as their
+ *     data dependencies are met).  A dependency wait that runs out of its
+ *     bound makes the next synchronising call return SELINV_E_DEVICE.
+ * Changing the mode drops the cached work lists (and HIP graph) of the
+ * handle.  selinv_sweep_is_persistent() tells which form the last built sweep
+ * of that precision uses (-1: none built yet). */
+selinv_status selinv_set_sweep_mode(selinv_handle h, int32_t mode);
+int32_t selinv_sweep_is_persistent(selinv_handle h, selinv_precision prec);
+
 /* Batches: several factored handles processed by one level sweep, levels
  * aligned at the roots (section on inter-supernode parallelism: supernodes
  * with the same priority run together).  The batch keeps pointers to the
  * handles; destroy the batch before its handles. */
 selinv_status selinv_batch_create(selinv_handle *hs, int32_t count, selinv_batch *out);
 selinv_status selinv_batch_run(selinv_batch b, selinv_precision prec, void *stream);
+selinv_status selinv_batch_set_sweep_mode(selinv_batch b, int32_t mode);
 void selinv_batch_destroy(selinv_batch b);
 
 /* A^{-1}(i, j) = At^{-T}(q[j], q[i]), q = perm^{-1} (step 6; eq. unpermute).
@@ -179,17 +194,22 @@ selinv_status selinv_check_plan(selinv_handle h, int64_t *mismatches);
 /* Device-side timing of the last selinv_run, from HIP events recorded on the
  * run's stream while profiling is on (selinv_set_profiling; not recorded by
  * selinv_run_graph or batches).  ms[0] diagonal-block inversion, ms[1]
- * normalisation, ms[2] diagonal initialisation, then for every level d
- * ms[3+3d] gather, ms[4+3d] products of steps 3 and 5, ms[5+3d] product of
- * step 4.  count = number of doubles the caller provides. */
+ * normalisation (and, in the FP64 form, the diagonal initialisation), ms[2]
+ * diagonal initialisation of the mixed forms, then for every level d
+ * ms[3+4d] fused steps 3-5 of the level's small supernodes (s, |R_L|,
+ * |R_U| <= 64), ms[4+4d] gather of the others, ms[5+4d] their products of
+ * steps 3 and 5, ms[6+4d] their product of step 4.  count = number of doubles
+ * the caller provides (3 + 4 * nlevels covers all). */
 selinv_status selinv_set_profiling(selinv_handle h, int32_t on);
 selinv_status selinv_timings(selinv_handle h, double *ms, int32_t count);
 
-/* Work of one level of the last run's sweep (stats: 10 doubles): [0]
- * supernodes, [1] widest supernode, [2] flops of steps 3+5, [3] flops of step
- * 4, [4] entries of G gathered, [5] gather tiles, [6] product tiles of steps
- * 3+5, [7] of step 4, [8] and [9] the output tile edge (64 or 128) of those two
- * product launches. */
+/* Work of one level of the last run's sweep (stats: 13 doubles): [0]
+ * supernodes, [1] widest supernode; for the launches of the large supernodes
+ * [2] flops of steps 3+5, [3] flops of step 4, [4] entries of G gathered, [5]
+ * gather tiles, [6] product tiles of steps 3+5, [7] of step 4, [8] and [9] the
+ * output tile edge (64 or 128) of those two product launches; for the fused
+ * small-supernode launch [10] supernodes, [11] flops of steps 3-5, [12]
+ * entries of G gathered. */
 selinv_status selinv_level_stats(selinv_handle h, int32_t level, double *stats);
 
 /* Message of the last failure on handle h; with h == NULL, of the last failed

@@ -56,6 +56,13 @@ struct TriItem {
     int32_t s, j0;
 };
 
+// fused step 3/4/5 of one small supernode (every product a single 64x64
+// tile): problem indices of its step-3, step-5 and step-4 products (-1: none)
+struct SmallItem {
+    int32_t mat, K;
+    int32_t pzu, pzl, pg4;
+};
+
 // extraction of the selected entries
 struct ExtractArgs {
     const int64_t *loc;  // kind << 60 | offset per entry of A
@@ -66,5 +73,35 @@ struct ExtractArgs {
 };
 
 enum Compute : int { CMP_F64 = 0, CMP_F32 = 1, CMP_BF16X3 = 2 };
+
+// persistent sweep: task kinds, per-supernode dependency record, arguments
+enum : int32_t { PT_GATHER = 0, PT_STEP35 = 1, PT_STEP4 = 2 };
+
+struct PTask {
+    int32_t type;   // PT_*
+    int32_t gid;    // supernode id over all matrices of the sweep
+    int32_t mat, K; // matrix and local supernode (gather tiles)
+    int32_t i0, i1; // gather: a0, b0; products: m0, n0
+    int32_t prob;   // product problem index
+    int32_t is_zu;  // the tile belongs to the step-3 product (A^{-T}(K, R_U))
+};
+
+struct PSn {
+    int32_t parent;    // gid of the parent supernode, -1 for a root
+    int32_t n_gather;  // gather tiles of this supernode
+    int32_t n_zu;      // tiles of its step-3 product
+    int32_t n_all;     // tiles of its step-3, step-5 and step-4 products
+};
+
+struct PersistArgs {
+    const PTask *tasks;
+    int32_t ntasks;
+    const PSn *sn;
+    int32_t *cnt;  // 3 per supernode: gather tiles, step-3 tiles, all product tiles done
+    int32_t *head; // next task
+    int32_t *err;  // set when a dependency wait ran out
+    const MatDev *mats;
+    const GemmProb *probs;
+};
 
 }  // namespace selinv

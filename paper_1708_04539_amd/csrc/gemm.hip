@@ -27,50 +27,9 @@
 
 #include "device_types.hpp"
 #include "kernels.hpp"
+#include "tiles.hpp"
 
 namespace selinv {
-
-typedef double v4d __attribute__((ext_vector_type(4)));
-typedef float v4f __attribute__((ext_vector_type(4)));
-typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
-
-template <int MODE>
-struct Mode;
-template <>
-struct Mode<CMP_F64> {
-    typedef double T;
-    typedef v4d Acc;
-    static constexpr int BK = 16;
-};
-template <>
-struct Mode<CMP_F32> {
-    typedef float T;
-    typedef v4f Acc;
-    static constexpr int BK = 16;
-};
-template <>
-struct Mode<CMP_BF16X3> {
-    typedef float T;
-    typedef v4f Acc;
-    static constexpr int BK = 32;
-};
-
-// LDS layouts.  F64/F32: [k][m] (m contiguous: the 16 lanes of a row group
-// read 16 consecutive m of one k).  BF16X3: [m][k] (k contiguous: a lane reads
-// its 8 consecutive k of one m with one 16-byte load).
-template <int MODE, int BM, int BN>
-struct Smem {
-    typedef typename Mode<MODE>::T T;
-    static constexpr int BK = Mode<MODE>::BK;
-    T a[2][BK][BM + 2];
-    T b[2][BK][BN + 2];
-};
-template <int BM, int BN>
-struct Smem<CMP_BF16X3, BM, BN> {
-    static constexpr int BK = 32, P = BK + 8;
-    __bf16 ah[2][BM][P], al[2][BM][P];
-    __bf16 bh[2][BN][P], bl[2][BN][P];
-};
 
 // ROLE only names the launch site in profiles (0: triangular inversion,
 // normalisation and diagonal initialisation; 1: products of steps 3 and 5;
@@ -78,179 +37,9 @@ struct Smem<CMP_BF16X3, BM, BN> {
 template <int MODE, int BM, int BN, typename TA, typename TC, int ROLE>
 __global__ __launch_bounds__(256) void gemm_v2(const GemmProb *__restrict__ probs,
                                                const GemmTile *__restrict__ tiles) {
-    typedef typename Mode<MODE>::T T;
-    typedef typename Mode<MODE>::Acc Acc;
-    constexpr int BK = Mode<MODE>::BK;
-    constexpr int WM = BM / 2, WN = BN / 2, TM = WM / 16, TN = WN / 16;
-    constexpr int LA = BM * BK / 256, LB = BN * BK / 256;
     __shared__ Smem<MODE, BM, BN> sm;
-
     const GemmTile tl = tiles[blockIdx.x];
-    const GemmProb p = probs[tl.prob];
-    const TA *__restrict__ A = (const TA *)p.A;
-    const TA *__restrict__ B = (const TA *)p.B;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
-    const int m0 = tl.m0, n0 = tl.n0, M = p.M, N = p.N, K = p.K;
-    const int opA = p.opA, opB = p.opB;
-    const int64_t lda = p.lda, ldb = p.ldb;
-
-    Acc acc[TM][TN];
-#pragma unroll
-    for (int i = 0; i < TM; i++)
-#pragma unroll
-        for (int j = 0; j < TN; j++) acc[i][j] = Acc{0, 0, 0, 0};
-
-    T ra[LA], rb[LB];
-    // element t of this thread's share of a chunk: (row in tile, k in chunk)
-    auto a_idx = [&](int t, int &i, int &k) {
-        const int e = tid + 256 * t;
-        if (opA == 0) {
-            i = e % BM;
-            k = e / BM;
-        } else {
-            k = e % BK;
-            i = e / BK;
-        }
-    };
-    auto b_idx = [&](int t, int &j, int &k) {
-        const int e = tid + 256 * t;
-        if (opB == 0) {
-            k = e % BK;
-            j = e / BK;
-        } else {
-            j = e % BN;
-            k = e / BN;
-        }
-    };
-    auto gload = [&](int k0) {
-#pragma unroll
-        for (int t = 0; t < LA; t++) {
-            int i, k;
-            a_idx(t, i, k);
-            const int gi = m0 + i, gk = k0 + k;
-            T v = 0;
-            if (gi < M && gk < K) v = (T)(opA == 0 ? A[gi + gk * lda] : A[gk + gi * lda]);
-            ra[t] = v;
-        }
-#pragma unroll
-        for (int t = 0; t < LB; t++) {
-            int j, k;
-            b_idx(t, j, k);
-            const int gj = n0 + j, gk = k0 + k;
-            T v = 0;
-            if (gj < N && gk < K) v = (T)(opB == 0 ? B[gk + gj * ldb] : B[gj + gk * ldb]);
-            rb[t] = v;
-        }
-    };
-    auto sstore = [&](int buf) {
-#pragma unroll
-        for (int t = 0; t < LA; t++) {
-            int i, k;
-            a_idx(t, i, k);
-            if constexpr (MODE == CMP_BF16X3) {
-                const __bf16 h = (__bf16)ra[t];
-                sm.ah[buf][i][k] = h;
-                sm.al[buf][i][k] = (__bf16)(ra[t] - (float)h);
-            } else {
-                sm.a[buf][k][i] = ra[t];
-            }
-        }
-#pragma unroll
-        for (int t = 0; t < LB; t++) {
-            int j, k;
-            b_idx(t, j, k);
-            if constexpr (MODE == CMP_BF16X3) {
-                const __bf16 h = (__bf16)rb[t];
-                sm.bh[buf][j][k] = h;
-                sm.bl[buf][j][k] = (__bf16)(rb[t] - (float)h);
-            } else {
-                sm.b[buf][k][j] = rb[t];
-            }
-        }
-    };
-    auto compute = [&](int buf) {
-        if constexpr (MODE == CMP_BF16X3) {
-            const int kb = 8 * (lane >> 4);
-            v8bf ah[TM], al[TM], bh[TN], bl[TN];
-#pragma unroll
-            for (int i = 0; i < TM; i++) {
-                const int r = wm * WM + i * 16 + (lane & 15);
-                ah[i] = *(const v8bf *)&sm.ah[buf][r][kb];
-                al[i] = *(const v8bf *)&sm.al[buf][r][kb];
-            }
-#pragma unroll
-            for (int j = 0; j < TN; j++) {
-                const int c = wn * WN + j * 16 + (lane & 15);
-                bh[j] = *(const v8bf *)&sm.bh[buf][c][kb];
-                bl[j] = *(const v8bf *)&sm.bl[buf][c][kb];
-            }
-#pragma unroll
-            for (int i = 0; i < TM; i++)
-#pragma unroll
-                for (int j = 0; j < TN; j++) {
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bl[j], ah[i], acc[i][j], 0, 0, 0);
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh[j], al[i], acc[i][j], 0, 0, 0);
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh[j], ah[i], acc[i][j], 0, 0, 0);
-                }
-        } else {
-#pragma unroll
-            for (int kk = 0; kk < BK; kk += 4) {
-                const int kr = kk + (lane >> 4);
-                T av[TM], bv[TN];
-#pragma unroll
-                for (int i = 0; i < TM; i++) av[i] = sm.a[buf][kr][wm * WM + i * 16 + (lane & 15)];
-#pragma unroll
-                for (int j = 0; j < TN; j++) bv[j] = sm.b[buf][kr][wn * WN + j * 16 + (lane & 15)];
-#pragma unroll
-                for (int i = 0; i < TM; i++)
-#pragma unroll
-                    for (int j = 0; j < TN; j++) {
-                        if constexpr (MODE == CMP_F64)
-                            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[j], av[i], acc[i][j], 0, 0, 0);
-                        else
-                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[j], av[i], acc[i][j], 0, 0, 0);
-                    }
-            }
-        }
-    };
-
-    gload(0);
-    sstore(0);
-    __syncthreads();
-    int buf = 0;
-    for (int k0 = 0; k0 < K; k0 += BK) {
-        const bool more = k0 + BK < K;
-        if (more) gload(k0 + BK);
-        compute(buf);
-        if (more) sstore(buf ^ 1);
-        __syncthreads();
-        buf ^= 1;
-    }
-
-    TC *__restrict__ C = (TC *)p.C;
-    const TC *__restrict__ Cin = (const TC *)p.Cin;
-    const int64_t ldc = p.ldc, ldcin = p.ldcin;
-    const double alpha = p.alpha, beta = p.beta;
-#pragma unroll
-    for (int i = 0; i < TM; i++)
-#pragma unroll
-        for (int j = 0; j < TN; j++) {
-            const int gm = m0 + wm * WM + i * 16 + (lane & 15);
-            if (gm >= M) continue;
-#pragma unroll
-            for (int v = 0; v < 4; v++) {
-                // rows of the 16x16 result held by this lane: v_mfma_f64_16x16x4
-                // interleaves the four row groups (row = lane/16 + 4v); the f32
-                // and bf16 forms keep them contiguous (row = 4 (lane/16) + v)
-                const int nr = (MODE == CMP_F64) ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v;
-                const int gn = n0 + wn * WN + j * 16 + nr;
-                if (gn >= N) continue;
-                double r = alpha * (double)acc[i][j][v];
-                if (Cin) r += beta * (double)Cin[gm + gn * ldcin];
-                C[gm + gn * ldc] = (TC)r;
-            }
-        }
+    gemm_tile<MODE, BM, BN, TA, TC>(probs[tl.prob], tl.m0, tl.n0, sm);
 }
 
 template <int MODE, typename TA, typename TC, int ROLE>

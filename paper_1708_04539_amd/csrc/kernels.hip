@@ -15,6 +15,7 @@
 
 #include "device_types.hpp"
 #include "kernels.hpp"
+#include "tiles.hpp"
 
 namespace selinv {
 
@@ -22,61 +23,151 @@ namespace selinv {
 // ---------------------------------------------------------------------------
 // triangular inversion, diagonal 64x64 blocks
 // ---------------------------------------------------------------------------
-// One wavefront handles the 64x64 diagonal sub-block that starts at
-// row/column o of one supernode's packed L_KK \ U_KK (column-major, s x s);
-// ragged sub-blocks (s - o < 64) are padded with the identity.
-//   UPPER = false: column l of (L_oo)^{-1} (forward substitution, unit
-//                  diagonal);
-//   UPPER = true:  column l of (U_oo^T)^{-1} = row l of (U_oo)^{-1} (forward
-//                  substitution on the transpose, dividing by the diagonal),
-//                  so that the stores of a row are coalesced across lanes.
-// Lane l keeps its 64 entries in registers; the substitution is fully
-// unrolled and every factor entry it uses is the same for all lanes (an LDS
-// broadcast).  The kernel also writes the zeros of L^{-1} above the sub-block
-// and of U^{-1} left of it; the off-diagonal blocks come from the GEMM rounds
+// One workgroup (4 wavefronts) inverts both triangles of the 64x64 diagonal
+// sub-block that starts at row/column o of one supernode's packed
+// L_KK \ U_KK (column-major, s x s; L unit lower, U upper).  A ragged
+// sub-block (s - o < 64) is padded with the identity, whose inverse stays the
+// identity and is not stored.  Blocked by 16:
+//   1. the 16x16 diagonal blocks, by substitution: wavefront w takes block w;
+//      lane c < 16 forms column c of (L_ww)^{-1} and lane 16 + c column c of
+//      (U_ww^T)^{-1} = row c of (U_ww)^{-1}, the same forward recurrence for
+//      both (the L diagonal is 1);
+//   2. the off-diagonal 16x16 blocks by distance d = 1, 2, 3 from the
+//      diagonal, on v_mfma_f64_16x16x4 (X = L^{-1}, Y = U^{-1}):
+//        X_ij = -X_ii (sum_{k=j}^{i-1} L_ik X_kj)      (i = j + d)
+//        Y_ij = -Y_ii (sum_{k=i+1}^{j} U_ik Y_kj)      (j = i + d)
+//      every block of one distance in parallel, one per wavefront.
+// Both results live packed in one LDS tile (strict lower part: L^{-1}; upper
+// part with the diagonal: U^{-1}) and are written out with coalesced stores,
+// together with the zeros of L^{-1} above the sub-block and of U^{-1} left of
+// it.  The off-diagonal 64x64 blocks of the inverses come from the GEMM rounds
 // of the recursive doubling (X21 = -B^{-1} C A^{-1} for L,
 // X12 = -A^{-1} C B^{-1} for U).
-template <bool UPPER>
-__global__ __launch_bounds__(64) void tri_base_kernel(const TriItem *__restrict__ items) {
+struct TriSmem {
+    double Ds[64][65];     // Ds[c][r] = D(o + r, o + c), identity-padded
+    double Xs[64][65];     // Xs[c][r]: r > c: L^{-1}(r, c); r <= c: U^{-1}(r, c)
+    double Ts[4][16][17];  // per-wavefront 16x16 intermediate
+};
+
+typedef double v4d_t __attribute__((ext_vector_type(4)));
+
+// L^{-1}(r, c) and U^{-1}(r, c) read from the packed tile (zero outside the
+// triangle; the unit diagonal of L^{-1} is implicit)
+__device__ __forceinline__ double linv_at(const TriSmem &sm, int r, int c) {
+    return r > c ? sm.Xs[c][r] : (r == c ? 1.0 : 0.0);
+}
+__device__ __forceinline__ double uinv_at(const TriSmem &sm, int r, int c) { return r <= c ? sm.Xs[c][r] : 0.0; }
+
+// One off-diagonal block at distance D, computed by the calling wavefront.
+// The lanes feed the MFMA with A(i = lane % 16, k = lane / 16) and
+// B(k = lane / 16, j = lane % 16); the result row is lane / 16 + 4 v, its
+// column lane % 16 (register v of the accumulator).
+template <int D>
+__device__ __forceinline__ void tri_offdiag(TriSmem &sm, int t, int lane, int wave) {
+    const bool upper = t >= 4 - D;
+    const int i = upper ? t - (4 - D) : t + D;   // row block of the result
+    const int j = upper ? i + D : t;             // column block
+    const int kb = upper ? 16 * (i + 1) : 16 * j;  // contraction range [kb, kb + 16 D)
+    const int li = lane & 15, lk = lane >> 4;
+    v4d_t acc = {0, 0, 0, 0};
+#pragma unroll
+    for (int kk = 0; kk < 16 * D; kk += 4) {
+        const int k = kb + kk + lk;
+        // factor entry L(16 i + li, k) or U(16 i + li, k): strictly off the diagonal
+        const double a = sm.Ds[k][16 * i + li];
+        const double bv = upper ? uinv_at(sm, k, 16 * j + li) : linv_at(sm, k, 16 * j + li);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; v++) sm.Ts[wave][lk + 4 * v][li] = acc[v];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    v4d_t out = {0, 0, 0, 0};
+#pragma unroll
+    for (int kk = 0; kk < 16; kk += 4) {
+        const int r = 16 * i + li, c = 16 * i + kk + lk;
+        const double a = upper ? uinv_at(sm, r, c) : linv_at(sm, r, c);
+        out = __builtin_amdgcn_mfma_f64_16x16x4f64(a, sm.Ts[wave][kk + lk][li], out, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; v++) sm.Xs[16 * j + li][16 * i + lk + 4 * v] = -out[v];
+    // the wavefront's next task overwrites Ts
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+template <int D>
+__device__ __forceinline__ void tri_round(TriSmem &sm, int lane, int wave) {
+    __syncthreads();
+    for (int t = wave; t < 2 * (4 - D); t += 4) tri_offdiag<D>(sm, t, lane, wave);
+}
+
+__global__ __launch_bounds__(256) void tri_base_kernel(const TriItem *__restrict__ items) {
+    __shared__ TriSmem sm;
     const TriItem it = items[blockIdx.x];
-    const int l = threadIdx.x;
-    const int s = it.s, o = it.j0;
-    const int b = min(64, s - o);
-    // Ds[c][r] = D(o + r, o + c); reused for the result after the substitution
-    __shared__ double Ds[64][65];
-    for (int c = 0; c < 64; c++)
-        Ds[c][l] = (l < b && c < b) ? it.D[(int64_t)(o + l) + (int64_t)(o + c) * s] : (l == c ? 1.0 : 0.0);
-    __syncthreads();
-    double x[64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int s = it.s, o = it.j0, b = min(64, s - o);
+    {
+        // all 16 loads of a thread in flight at once; addresses clamped into
+        // the block, the identity padding selected afterwards
+        const int r = lane, rr = min(r, b - 1);
+        double v[16];
 #pragma unroll
-    for (int r = 0; r < 64; r++) x[r] = (r == l) ? 1.0 : 0.0;
+        for (int q = 0; q < 16; q++) {
+            const int c = wave + 4 * q;
+            v[q] = it.D[(int64_t)(o + rr) + (int64_t)(o + min(c, b - 1)) * s];
+        }
 #pragma unroll
-    for (int k = 0; k < 64; k++) {
-        if constexpr (UPPER) x[k] = x[k] / Ds[k][k];
-        const double xk = x[k];
-#pragma unroll
-        for (int r = k + 1; r < 64; r++) x[r] -= (UPPER ? Ds[r][k] : Ds[k][r]) * xk;
+        for (int q = 0; q < 16; q++) {
+            const int c = wave + 4 * q;
+            sm.Ds[c][r] = (r < b && c < b) ? v[q] : (r == c ? 1.0 : 0.0);
+        }
     }
-    // Through LDS to global memory: x goes to row l of the tile (all 64
-    // entries, unconditionally), then each column of the result is written
-    // with the lanes along its rows (coalesced).  Lane l's x is column l of
-    // (L_oo)^{-1}, or row l of (U_oo)^{-1}.
     __syncthreads();
-    double(&Xs)[64][65] = Ds;
+    {
+        const int base = 16 * wave, c = lane & 15;
+        const bool up = (lane & 16) != 0;  // lanes 32..63 repeat lanes 0..31 and store nothing
+        double x[16];
 #pragma unroll
-    for (int r = 0; r < 64; r++) Xs[l][r] = x[r];
-    __syncthreads();
-    double *out = UPPER ? it.Uinv : it.Linv;
-    for (int c = 0; c < b; c++) {
-        double *col = out + (int64_t)(o + c) * s;
-        if (l < b) col[o + l] = UPPER ? Xs[l][c] : Xs[c][l];
-        // zeros of L^{-1} above the sub-block
-        if (!UPPER)
-            for (int r = l; r < o; r += 64) col[r] = 0.0;
+        for (int r = 0; r < 16; r++) x[r] = r == c ? 1.0 : 0.0;
+#pragma unroll
+        for (int k = 0; k < 16; k++) {
+            if (up) x[k] = x[k] / sm.Ds[base + k][base + k];
+#pragma unroll
+            for (int r = k + 1; r < 16; r++)
+                x[r] = fma(-(up ? sm.Ds[base + r][base + k] : sm.Ds[base + k][base + r]), x[k], x[r]);
+        }
+        if (lane < 32) {
+#pragma unroll
+            for (int r = 0; r < 16; r++) {
+                if (!up && r > c) sm.Xs[base + c][base + r] = x[r];  // L^{-1}(r, c)
+                if (up && r >= c) sm.Xs[base + r][base + c] = x[r];  // U^{-1}(c, r)
+            }
+        }
     }
-    // zeros of U^{-1} left of the sub-block (rows o .. o+b-1)
-    if (UPPER && l < b)
-        for (int c = 0; c < o; c++) out[(o + l) + (int64_t)c * s] = 0.0;
+    tri_round<1>(sm, lane, wave);
+    tri_round<2>(sm, lane, wave);
+    tri_round<3>(sm, lane, wave);
+    __syncthreads();
+    double *Linv = it.Linv, *Uinv = it.Uinv;
+    {
+        const int r = lane;
+#pragma unroll
+        for (int q = 0; q < 16; q++) {
+            const int c = wave + 4 * q;
+            if (r < b && c < b) {
+                const int64_t g = (int64_t)(o + r) + (int64_t)(o + c) * s;
+                Linv[g] = linv_at(sm, r, c);
+                Uinv[g] = uinv_at(sm, r, c);
+            }
+        }
+    }
+    // zeros of L^{-1} above the sub-block and of U^{-1} left of it
+    for (int c = wave; c < b; c += 4)
+        for (int r = lane; r < o; r += 64) Linv[r + (int64_t)(o + c) * s] = 0.0;
+    if (lane < b)
+        for (int c = wave; c < o; c += 4) Uinv[(o + lane) + (int64_t)c * s] = 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -85,63 +176,9 @@ __global__ __launch_bounds__(64) void tri_base_kernel(const TriItem *__restrict_
 template <typename T>
 __global__ __launch_bounds__(256) void gather_kernel(const MatDev *__restrict__ mats,
                                                      const GatherTile *__restrict__ tiles) {
+    __shared__ GatherSmem<T> sm;
     const GatherTile tl = tiles[blockIdx.x];
-    const MatDev M = mats[tl.mat];
-    const SnRec sk = M.sn[tl.K];
-    __shared__ T tileS[64][65];  // [b][a]
-    __shared__ int32_t rowR[64], rowI[64], colJ[64];
-    __shared__ int64_t rowUp[64], rowUoff[64], colDiag[64], colLow[64], colLoff[64];
-    const int tid = threadIdx.x;
-    const int na = min(64, sk.cl - tl.a0), nb = min(64, sk.cu - tl.b0);
-    if (tid < 64) {
-        if (tid < na) {
-            const int64_t a = sk.rl_off + tl.a0 + tid;
-            const int32_t r = M.rl[a];
-            const int32_t I = M.supof[r];
-            const SnRec si = M.sn[I];
-            rowR[tid] = r;
-            rowI[tid] = I;
-            rowUp[tid] = si.off_u + (int64_t)(r - si.f) * si.cu;
-            rowUoff[tid] = M.u_rowoff[a] + tl.b0;
-        }
-    } else if (tid < 128) {
-        const int t = tid - 64;
-        if (t < nb) {
-            const int64_t b = sk.ru_off + tl.b0 + t;
-            const int32_t c = M.ru[b];
-            const int32_t J = M.supof[c];
-            const SnRec sj = M.sn[J];
-            colJ[t] = J;
-            colDiag[t] = sj.off_d + (int64_t)(c - sj.f) * sj.s - sj.f;
-            colLow[t] = sj.off_l + (int64_t)(c - sj.f) * sj.cl;
-            colLoff[t] = M.l_coloff[b] + tl.a0;
-        }
-    }
-    __syncthreads();
-    const T *ZL = (const T *)M.ZL;
-    const T *ZU = (const T *)M.ZU;
-    // diagonal and L-side sources: contiguous along the rows of G
-    for (int e = tid; e < 64 * 64; e += 256) {
-        const int ia = e & 63, ib = e >> 6;
-        if (ia < na && ib < nb) {
-            const int32_t I = rowI[ia], J = colJ[ib];
-            if (I == J)
-                tileS[ib][ia] = (T)M.Zd[colDiag[ib] + rowR[ia]];
-            else if (I > J)
-                tileS[ib][ia] = ZL[colLow[ib] + M.mapL[colLoff[ib] + ia]];
-        }
-    }
-    // U-side sources: contiguous along the columns of G
-    for (int e = tid; e < 64 * 64; e += 256) {
-        const int ib = e & 63, ia = e >> 6;
-        if (ia < na && ib < nb && rowI[ia] < colJ[ib]) tileS[ib][ia] = ZU[rowUp[ia] + M.mapU[rowUoff[ia] + ib]];
-    }
-    __syncthreads();
-    T *G = (T *)M.G + sk.g_off;
-    for (int e = tid; e < 64 * 64; e += 256) {
-        const int ia = e & 63, ib = e >> 6;
-        if (ia < na && ib < nb) G[(tl.a0 + ia) + (int64_t)(tl.b0 + ib) * sk.cl] = tileS[ib][ia];
-    }
+    gather_tile<T>(mats[tl.mat], tl.K, tl.a0, tl.b0, sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -168,8 +205,7 @@ __global__ __launch_bounds__(256) void extract_kernel(ExtractArgs a) {
 // ---------------------------------------------------------------------------
 hipError_t launch_tri_base(const TriItem *items, int count, hipStream_t st) {
     if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(tri_base_kernel<false>, dim3(count), dim3(64), 0, st, items);
-    hipLaunchKernelGGL(tri_base_kernel<true>, dim3(count), dim3(64), 0, st, items);
+    hipLaunchKernelGGL(tri_base_kernel, dim3(count), dim3(256), 0, st, items);
     return hipGetLastError();
 }
 

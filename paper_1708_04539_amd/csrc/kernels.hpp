@@ -29,6 +29,15 @@ enum : int {
 hipError_t launch_gemm(int role, int mode, int tile, const GemmProb *probs, const GemmTile *tiles, int ntiles,
                        hipStream_t st);
 hipError_t launch_gather(int f64, const MatDev *mats, const GatherTile *tiles, int ntiles, hipStream_t st);
+// gather + steps 3/5 + step 4 of small supernodes, one workgroup each (persist.hip)
+hipError_t launch_small(int mode, const MatDev *mats, const GemmProb *probs, const SmallItem *items, int count,
+                        hipStream_t st);
 hipError_t launch_extract(int f64, const ExtractArgs &a, hipStream_t st);
+
+// persistent sweep (64x64 product tiles): resets the ncnt counters, the queue
+// head and the error flag, then runs the task queue on `grid` workgroups
+hipError_t launch_persist(int mode, const PersistArgs &a, int64_t ncnt, int grid, hipStream_t st);
+// workgroups of the persistent sweep that fit on the device at once
+int persist_grid(int mode);
 
 }  // namespace selinv

@@ -51,9 +51,19 @@ struct Sweep {
     GatherTile *d_gt = nullptr;
     Range tri, norm, dt;
     std::vector<Range> tri_rounds;  // pairs (T products, X products) per doubling round
-    std::vector<Range> gat, g35, g4;
-    std::vector<double> lev_flops35, lev_flops4, lev_gather_elems;
+    std::vector<Range> small, gat, g35, g4;
+    SmallItem *d_small = nullptr;
+    std::vector<double> lev_flops35, lev_flops4, lev_gather_elems;  // launches of the large supernodes
+    std::vector<double> lev_small_flops, lev_small_elems;          // the fused small-supernode launch
     std::vector<int> lev_nsup, lev_maxs;
+    // persistent sweep (used instead of the per-level launches when `persistent`)
+    bool persistent = false;
+    PTask *d_ptasks = nullptr;
+    int32_t ntasks = 0;
+    PSn *d_psn = nullptr;
+    int32_t *d_cnt = nullptr;  // 3 counters per supernode, then head, then error flag
+    int64_t ncnt = 0;
+    int grid = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     hipStream_t graph_stream = nullptr;
@@ -65,8 +75,14 @@ struct Sweep {
         (void)hipFree(d_probs);
         (void)hipFree(d_tiles);
         (void)hipFree(d_gt);
+        (void)hipFree(d_small);
+        (void)hipFree(d_ptasks);
+        (void)hipFree(d_psn);
+        (void)hipFree(d_cnt);
     }
 };
+
+enum : int { SWEEP_AUTO = 0, SWEEP_LEVELS = 1, SWEEP_PERSISTENT = 2 };
 
 constexpr int NPREC = 3;
 
@@ -93,8 +109,10 @@ struct selinv_handle_s {
     std::unique_ptr<Sweep> sweep[NPREC];
     int last_prec = -1;
     hipStream_t last_stream = nullptr;
+    const Sweep *last_sweep = nullptr;  // sweep of the last run (own or a batch's)
     hipStream_t own_stream = nullptr;
     bool profiling = false;
+    int sweep_mode = SWEEP_AUTO;
     std::vector<hipEvent_t> events;
     std::vector<double> times;
 };
@@ -103,6 +121,7 @@ struct selinv_batch_s {
     std::vector<selinv_handle> hs;
     std::unique_ptr<Sweep> sweep[NPREC];
     std::string err;
+    int sweep_mode = SWEEP_AUTO;
 };
 
 namespace {
@@ -217,8 +236,22 @@ int add_prob(std::vector<GemmProb> &probs, const void *A, int opA, int lda,
     return 1;
 }
 
+// The persistent sweep pays off when the levels are too small to fill the
+// device on their own (launch latency dominates): use it when the average
+// level carries less than about two waves of 64x64 product tiles.
+bool persist_auto(const std::vector<selinv_handle> &hs) {
+    double tiles = 0;
+    int depth = 0;
+    for (auto h : hs) {
+        depth = std::max(depth, h->P.nlevels);
+        for (const SnRec &r : h->sn)
+            tiles += std::ceil(r.s / 64.0) * (std::ceil(r.cl / 64.0) + 2 * std::ceil(r.cu / 64.0));
+    }
+    return depth > 0 && tiles / depth < 512;
+}
+
 // Build the work lists of one sweep over a set of factored handles.
-selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, std::unique_ptr<Sweep> &out,
+selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, int sweep_mode, std::unique_ptr<Sweep> &out,
                           std::string &err) {
     std::unique_ptr<Sweep> S(new Sweep());
     S->prec = prec;
@@ -332,8 +365,13 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, std::unique_
                                       r.cu, nullptr, 1, r.cu, r.s, r.s, 1.0, 0.0, &X, 8, e);
         }
     }
-    emit_launch(probs, first, tiles, S->norm);
-    first = probs.size();
+    // In the FP64 form the normalisation and the diagonal initialisation run
+    // on the same kernel and share one launch; the mixed forms write FP32
+    // normalised panels and need a second kernel for the FP64 diagonal.
+    if (prec != SELINV_FP64) {
+        emit_launch(probs, first, tiles, S->norm);
+        first = probs.size();
+    }
     for (auto h : hs) {
         const PrecBufs &b = h->pb[prec];
         for (int32_t K = 0; K < h->P.ns; K++) {
@@ -342,15 +380,27 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, std::unique_
                                     b.Zd + r.off_d, r.s, nullptr, 1, r.s, r.s, r.s, 1.0, 0.0, &X, 8, 8);
         }
     }
-    emit_launch(probs, first, tiles, S->dt);
+    emit_launch(probs, first, tiles, prec == SELINV_FP64 ? S->norm : S->dt);
+    // supernode ids over the whole batch, and the product problems of each
+    std::vector<int32_t> gbase(hs.size() + 1, 0);
+    for (size_t mi = 0; mi < hs.size(); mi++) gbase[mi + 1] = gbase[mi] + hs[mi]->P.ns;
+    const int32_t nsn = gbase[hs.size()];
+    std::vector<int> prob_zu(nsn, -1), prob_zl(nsn, -1), prob_g4(nsn, -1);
+    std::vector<SmallItem> smalls;
+    S->small.resize(depth);
     S->gat.resize(depth);
     S->g35.resize(depth);
     S->g4.resize(depth);
     S->lev_flops35.assign(depth, 0);
     S->lev_flops4.assign(depth, 0);
     S->lev_gather_elems.assign(depth, 0);
+    S->lev_small_flops.assign(depth, 0);
+    S->lev_small_elems.assign(depth, 0);
     S->lev_nsup.assign(depth, 0);
     S->lev_maxs.assign(depth, 0);
+    // a supernode whose gather and three products are single 64x64 tiles is
+    // handled whole by one workgroup of the fused small-supernode kernel
+    auto is_small = [](const SnRec &r) { return r.s <= 64 && r.cl <= 64 && r.cu <= 64; };
     for (int d = 0; d < depth; d++) {
         S->gat[d].off = gts.size();
         for (size_t mi = 0; mi < hs.size(); mi++) {
@@ -358,48 +408,170 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, std::unique_
             if (d >= h->P.nlevels) continue;
             for (int32_t K : h->P.levels[d]) {
                 const SnRec &r = h->sn[K];
-                for (int b0 = 0; b0 < r.cu; b0 += 64)
-                    for (int a0 = 0; a0 < r.cl; a0 += 64) gts.push_back(GatherTile{(int32_t)mi, K, a0, b0});
-                S->lev_gather_elems[d] += (double)r.cl * r.cu;
+                if (!is_small(r)) {
+                    for (int b0 = 0; b0 < r.cu; b0 += 64)
+                        for (int a0 = 0; a0 < r.cl; a0 += 64) gts.push_back(GatherTile{(int32_t)mi, K, a0, b0});
+                    S->lev_gather_elems[d] += (double)r.cl * r.cu;
+                } else {
+                    S->lev_small_elems[d] += (double)r.cl * r.cu;
+                }
                 S->lev_nsup[d]++;
                 S->lev_maxs[d] = std::max(S->lev_maxs[d], r.s);
             }
         }
         S->gat[d].count = (int)(gts.size() - S->gat[d].off);
-        first = probs.size();
-        for (auto h : hs) {
+        // steps 3 and 5: the large supernodes' problems first (one launch), then
+        // those of the small supernodes (run by the fused kernel)
+        for (int pass = 0; pass < 2; pass++) {
+            first = probs.size();
+            for (size_t mi = 0; mi < hs.size(); mi++) {
+                selinv_handle h = hs[mi];
+                if (d >= h->P.nlevels) continue;
+                const PrecBufs &b = h->pb[prec];
+                for (int32_t K : h->P.levels[d]) {
+                    const SnRec &r = h->sn[K];
+                    if (is_small(r) != (pass == 1)) continue;
+                    const int32_t gid = gbase[mi] + K;
+                    const char *G = (const char *)b.G + r.g_off * e;
+                    char *Lh = (char *)b.Lh + r.off_l * e, *Uh = (char *)b.Uh + r.off_u * e;
+                    char *ZL = (char *)b.ZL + r.off_l * e, *ZU = (char *)b.ZU + r.off_u * e;
+                    // step 3 (stored transposed): A^{-T}(K,R_U)^T = -G^T Lhat
+                    prob_zu[gid] = add_prob(probs, G, 1, r.cl, Lh, 0, r.cl, ZU, r.cu, nullptr, 1, r.cu, r.s, r.cl,
+                                            -1.0, 0.0, &X, e, e)
+                                       ? (int)probs.size() - 1
+                                       : -1;
+                    // step 5: A^{-T}(R_L,K) = -G Uhat^T
+                    prob_zl[gid] = add_prob(probs, G, 0, r.cl, Uh, 0, r.cu, ZL, r.cl, nullptr, 1, r.cl, r.s, r.cu,
+                                            -1.0, 0.0, &X, e, e)
+                                       ? (int)probs.size() - 1
+                                       : -1;
+                    (pass == 0 ? S->lev_flops35[d] : S->lev_small_flops[d]) += 4.0 * r.s * (double)r.cl * r.cu;
+                }
+            }
+            if (pass == 0) emit_launch(probs, first, tiles, S->g35[d]);
+        }
+        // step 4
+        for (int pass = 0; pass < 2; pass++) {
+            first = probs.size();
+            for (size_t mi = 0; mi < hs.size(); mi++) {
+                selinv_handle h = hs[mi];
+                if (d >= h->P.nlevels) continue;
+                const PrecBufs &b = h->pb[prec];
+                for (int32_t K : h->P.levels[d]) {
+                    const SnRec &r = h->sn[K];
+                    if (is_small(r) != (pass == 1)) continue;
+                    const int32_t gid = gbase[mi] + K;
+                    if (r.cu == 0) continue;
+                    char *Uh = (char *)b.Uh + r.off_u * e, *ZU = (char *)b.ZU + r.off_u * e;
+                    // step 4: A^{-T}(K,K) = (L_KK)^{-T}(U_KK)^{-T} - A^{-T}(K,R_U) Uhat^T
+                    prob_g4[gid] = add_prob(probs, ZU, 1, r.cu, Uh, 0, r.cu, b.Zd + r.off_d, r.s, b.Zd + r.off_d,
+                                            r.s, r.s, r.s, r.cu, -1.0, 1.0, &X, e, 8)
+                                       ? (int)probs.size() - 1
+                                       : -1;
+                    (pass == 0 ? S->lev_flops4[d] : S->lev_small_flops[d]) += 2.0 * r.s * (double)r.s * r.cu;
+                }
+            }
+            if (pass == 0) emit_launch(probs, first, tiles, S->g4[d]);
+        }
+        S->small[d].off = smalls.size();
+        for (size_t mi = 0; mi < hs.size(); mi++) {
+            selinv_handle h = hs[mi];
             if (d >= h->P.nlevels) continue;
-            const PrecBufs &b = h->pb[prec];
             for (int32_t K : h->P.levels[d]) {
                 const SnRec &r = h->sn[K];
-                const char *G = (const char *)b.G + r.g_off * e;
-                char *Lh = (char *)b.Lh + r.off_l * e, *Uh = (char *)b.Uh + r.off_u * e;
-                char *ZL = (char *)b.ZL + r.off_l * e, *ZU = (char *)b.ZU + r.off_u * e;
-                // step 3 (stored transposed): A^{-T}(K,R_U)^T = -G^T Lhat
-                add_prob(probs, G, 1, r.cl, Lh, 0, r.cl, ZU, r.cu, nullptr, 1, r.cu, r.s,
-                                            r.cl, -1.0, 0.0, &X, e, e);
-                // step 5: A^{-T}(R_L,K) = -G Uhat^T
-                add_prob(probs, G, 0, r.cl, Uh, 0, r.cu, ZL, r.cl, nullptr, 1, r.cl, r.s,
-                                            r.cu, -1.0, 0.0, &X, e, e);
-                S->lev_flops35[d] += 4.0 * r.s * (double)r.cl * r.cu;
+                const int32_t gid = gbase[mi] + K;
+                if (!is_small(r) || (prob_zu[gid] < 0 && prob_zl[gid] < 0 && prob_g4[gid] < 0)) continue;
+                smalls.push_back(SmallItem{(int32_t)mi, K, prob_zu[gid], prob_zl[gid], prob_g4[gid]});
             }
         }
-        emit_launch(probs, first, tiles, S->g35[d]);
-        first = probs.size();
-        for (auto h : hs) {
-            if (d >= h->P.nlevels) continue;
-            const PrecBufs &b = h->pb[prec];
-            for (int32_t K : h->P.levels[d]) {
+        S->small[d].count = (int)(smalls.size() - S->small[d].off);
+    }
+    // persistent task queue: level by level from the root; per level all
+    // gather tiles, then the step-3 tiles, the step-5 tiles, the step-4 tiles
+    {
+        std::vector<PTask> pt;
+        std::vector<PSn> psn(nsn);
+        auto tiles64 = [](int M, int N) { return ((M + 63) / 64) * ((N + 63) / 64); };
+        for (size_t mi = 0; mi < hs.size(); mi++) {
+            selinv_handle h = hs[mi];
+            for (int32_t K = 0; K < h->P.ns; K++) {
+                const int32_t gid = gbase[mi] + K;
                 const SnRec &r = h->sn[K];
-                if (r.cu == 0) continue;
-                char *Uh = (char *)b.Uh + r.off_u * e, *ZU = (char *)b.ZU + r.off_u * e;
-                // step 4: A^{-T}(K,K) = (L_KK)^{-T}(U_KK)^{-T} - A^{-T}(K,R_U) Uhat^T
-                add_prob(probs, ZU, 1, r.cu, Uh, 0, r.cu, b.Zd + r.off_d, r.s,
-                                           b.Zd + r.off_d, r.s, r.s, r.s, r.cu, -1.0, 1.0, &X, e, 8);
-                S->lev_flops4[d] += 2.0 * r.s * (double)r.s * r.cu;
+                PSn &q = psn[gid];
+                q.parent = h->P.sparent[K] >= 0 ? gbase[mi] + h->P.sparent[K] : -1;
+                q.n_gather = tiles64(r.cl, r.cu);
+                q.n_zu = prob_zu[gid] >= 0 ? tiles64(probs[prob_zu[gid]].M, probs[prob_zu[gid]].N) : 0;
+                q.n_all = q.n_zu;
+                if (prob_zl[gid] >= 0) q.n_all += tiles64(probs[prob_zl[gid]].M, probs[prob_zl[gid]].N);
+                if (prob_g4[gid] >= 0) q.n_all += tiles64(probs[prob_g4[gid]].M, probs[prob_g4[gid]].N);
             }
         }
-        emit_launch(probs, first, tiles, S->g4[d]);
+        auto push_prob = [&](int type, int32_t gid, int mat, int32_t K, int prob, int is_zu) {
+            if (prob < 0) return;
+            const GemmProb &p = probs[prob];
+            for (int n0 = 0; n0 < p.N; n0 += 64)
+                for (int m0 = 0; m0 < p.M; m0 += 64) pt.push_back(PTask{type, gid, mat, K, m0, n0, prob, is_zu});
+        };
+        for (int d = 0; d < depth; d++) {
+            for (size_t mi = 0; mi < hs.size(); mi++) {
+                selinv_handle h = hs[mi];
+                if (d >= h->P.nlevels) continue;
+                for (int32_t K : h->P.levels[d]) {
+                    const SnRec &r = h->sn[K];
+                    for (int b0 = 0; b0 < r.cu; b0 += 64)
+                        for (int a0 = 0; a0 < r.cl; a0 += 64)
+                            pt.push_back(PTask{PT_GATHER, gbase[mi] + K, (int32_t)mi, K, a0, b0, -1, 0});
+                }
+            }
+            for (int pass = 0; pass < 3; pass++)
+                for (size_t mi = 0; mi < hs.size(); mi++) {
+                    selinv_handle h = hs[mi];
+                    if (d >= h->P.nlevels) continue;
+                    for (int32_t K : h->P.levels[d]) {
+                        const int32_t gid = gbase[mi] + K;
+                        if (pass == 0) push_prob(PT_STEP35, gid, (int)mi, K, prob_zu[gid], 1);
+                        if (pass == 1) push_prob(PT_STEP35, gid, (int)mi, K, prob_zl[gid], 0);
+                        if (pass == 2) push_prob(PT_STEP4, gid, (int)mi, K, prob_g4[gid], 0);
+                    }
+                }
+        }
+        // a task may only wait for tasks earlier in the queue
+        std::vector<int64_t> last_gather(nsn, -1), last_zu(nsn, -1), last_all(nsn, -1), first_any(nsn, INT64_MAX);
+        for (int64_t t = 0; t < (int64_t)pt.size(); t++) {
+            const PTask &k = pt[t];
+            first_any[k.gid] = std::min(first_any[k.gid], t);
+            if (k.type == PT_GATHER) last_gather[k.gid] = t;
+            if (k.type != PT_GATHER) last_all[k.gid] = t;
+            if (k.is_zu) last_zu[k.gid] = t;
+        }
+        for (int32_t g = 0; g < nsn; g++) {
+            const int32_t P = psn[g].parent;
+            if (P >= 0 && first_any[g] != INT64_MAX && last_all[P] >= first_any[g]) X.violations++;
+        }
+        for (int64_t t = 0; t < (int64_t)pt.size(); t++) {
+            const PTask &k = pt[t];
+            if (k.type == PT_STEP35 && last_gather[k.gid] > t) X.violations++;
+            if (k.type == PT_STEP4 && last_zu[k.gid] > t) X.violations++;
+        }
+        const bool small = pt.size() <= 400000;
+        S->persistent = sweep_mode == SWEEP_PERSISTENT || (sweep_mode == SWEEP_AUTO && small && persist_auto(hs));
+        if (S->persistent) {
+            if (pt.size() >= (size_t)INT32_MAX) {
+                err = "persistent task queue too long";
+                return SELINV_E_INVALID_ARG;
+            }
+            S->ntasks = (int32_t)pt.size();
+            S->ncnt = 3 * (int64_t)nsn;
+            std::vector<int32_t> zero(S->ncnt + 2, 0);
+            HIPCHK(err, upload(&S->d_ptasks, pt), "upload tasks");
+            HIPCHK(err, upload(&S->d_psn, psn), "upload task deps");
+            HIPCHK(err, upload(&S->d_cnt, zero), "upload counters");
+            S->grid = persist_grid(mode_of(prec));
+            if (S->grid <= 0) {
+                err = "could not size the persistent grid";
+                return SELINV_E_DEVICE;
+            }
+        }
     }
     // gather tiles stay inside their supernode's G block
     for (const GatherTile &t : gts) {
@@ -407,6 +579,13 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, std::unique_
         if (t.a0 < 0 || t.b0 < 0 || t.a0 >= r.cl || t.b0 >= r.cu ||
             r.g_off + (int64_t)r.cl * r.cu > hs[t.mat]->g_elems)
             X.violations++;
+    }
+    // a small item's products are single tiles of problems in the list
+    for (const SmallItem &it : smalls) {
+        const SnRec &r = hs[it.mat]->sn[it.K];
+        if (r.s > 64 || r.cl > 64 || r.cu > 64) X.violations++;
+        for (int32_t p : {it.pzu, it.pzl, it.pg4})
+            if (p >= (int32_t)probs.size() || (p >= 0 && (probs[p].M > 64 || probs[p].N > 64))) X.violations++;
     }
     for (auto h : hs)
         for (const SnRec &r : h->sn)
@@ -420,6 +599,7 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, std::unique_
     HIPCHK(err, upload(&S->d_probs, probs), "upload probs");
     HIPCHK(err, upload(&S->d_tiles, tiles), "upload tiles");
     HIPCHK(err, upload(&S->d_gt, gts), "upload gather tiles");
+    HIPCHK(err, upload(&S->d_small, smalls), "upload small supernodes");
     out = std::move(S);
     return SELINV_OK;
 }
@@ -442,15 +622,32 @@ hipError_t launch_sweep(const Sweep &S, hipStream_t st, std::vector<hipEvent_t> 
     mark(2);
     if ((e = launch_gemm(GEMM_PRO_F64, CMP_F64, S.dt.tile, S.d_probs, S.d_tiles + S.dt.off, S.dt.count, st))) return e;
     mark(3);
+    if (S.persistent) {
+        PersistArgs a;
+        a.tasks = S.d_ptasks;
+        a.ntasks = S.ntasks;
+        a.sn = S.d_psn;
+        a.cnt = S.d_cnt;
+        a.head = S.d_cnt + S.ncnt;
+        a.err = S.d_cnt + S.ncnt + 1;
+        a.mats = S.d_mats;
+        a.probs = S.d_probs;
+        if ((e = launch_persist(mode, a, S.ncnt, S.grid, st))) return e;
+        for (size_t d = 0; d < 4 * S.gat.size(); d++) mark(4 + d);
+        return hipSuccess;
+    }
     for (size_t d = 0; d < S.gat.size(); d++) {
+        if ((e = launch_small(mode, S.d_mats, S.d_probs, S.d_small + S.small[d].off, S.small[d].count, st)))
+            return e;
+        mark(4 + 4 * d);
         if ((e = launch_gather(f64, S.d_mats, S.d_gt + S.gat[d].off, S.gat[d].count, st))) return e;
-        mark(4 + 3 * d);
+        mark(5 + 4 * d);
         if ((e = launch_gemm(GEMM_STEP35, mode, S.g35[d].tile, S.d_probs, S.d_tiles + S.g35[d].off,
                              S.g35[d].count, st))) return e;
-        mark(5 + 3 * d);
+        mark(6 + 4 * d);
         if ((e = launch_gemm(GEMM_STEP4, mode, S.g4[d].tile, S.d_probs, S.d_tiles + S.g4[d].off, S.g4[d].count,
                              st))) return e;
-        mark(6 + 3 * d);
+        mark(7 + 4 * d);
     }
     return hipSuccess;
 }
@@ -508,7 +705,7 @@ selinv_status selinv_analyze(int64_t n, const int64_t *colptr, const int32_t *ro
     }
     const Plan &P = h->P;
     h->sn.resize(P.ns);
-    std::vector<int64_t> lev_g(P.nlevels, 0);
+    h->g_elems = 0;
     for (int32_t K = 0; K < P.ns; K++) {
         SnRec &r = h->sn[K];
         r.f = P.xsup[K];
@@ -520,12 +717,11 @@ selinv_status selinv_analyze(int64_t n, const int64_t *colptr, const int32_t *ro
         r.off_u = P.off_u[K];
         r.rl_off = P.rl_ptr[K];
         r.ru_off = P.ru_ptr[K];
-        int lv = P.level[K];
-        r.g_off = lev_g[lv];
-        lev_g[lv] += (int64_t)r.cl * r.cu;
+        // every supernode has its own G block: the persistent sweep overlaps
+        // levels, so blocks are not reused from one level to the next
+        r.g_off = h->g_elems;
+        h->g_elems += (int64_t)r.cl * r.cu;
     }
-    h->g_elems = 0;
-    for (auto g : lev_g) h->g_elems = std::max(h->g_elems, g);
     *out = h;
     return SELINV_OK;
 }
@@ -593,7 +789,7 @@ static selinv_status check_run(selinv_handle h, int prec) {
 static selinv_status ensure_sweep(selinv_handle h, int prec) {
     if (h->sweep[prec]) return SELINV_OK;
     std::vector<selinv_handle> one{h};
-    return build_sweep(one, prec, h->sweep[prec], h->err);
+    return build_sweep(one, prec, h->sweep_mode, h->sweep[prec], h->err);
 }
 
 selinv_status selinv_run(selinv_handle h, selinv_precision prec, void *stream) {
@@ -604,7 +800,7 @@ selinv_status selinv_run(selinv_handle h, selinv_precision prec, void *stream) {
     const Sweep &S = *h->sweep[prec];
     std::vector<hipEvent_t> *ev = nullptr;
     if (h->profiling) {
-        size_t need = 4 + 3 * S.gat.size();
+        size_t need = 4 + 4 * S.gat.size();
         while (h->events.size() < need) {
             hipEvent_t e;
             HIPCHK(h->err, hipEventCreate(&e), "hipEventCreate");
@@ -614,6 +810,7 @@ selinv_status selinv_run(selinv_handle h, selinv_precision prec, void *stream) {
     }
     hipError_t e = launch_sweep(S, s, ev);
     if (e != hipSuccess) return dev_fail(h->err, e, "kernel launch");
+    h->last_sweep = &S;
     h->last_prec = prec;
     h->last_stream = s;
     h->state = 2;
@@ -641,10 +838,41 @@ selinv_status selinv_run_graph(selinv_handle h, selinv_precision prec, void *str
         HIPCHK(h->err, hipGraphInstantiate(&S.gexec, g, nullptr, nullptr, 0), "graph instantiate");
     }
     HIPCHK(h->err, hipGraphLaunch(S.gexec, s), "graph launch");
+    h->last_sweep = &S;
     h->last_prec = prec;
     h->last_stream = s;
     h->state = 2;
     return SELINV_OK;
+}
+
+selinv_status selinv_set_sweep_mode(selinv_handle h, int32_t mode) {
+    if (!h || mode < SWEEP_AUTO || mode > SWEEP_PERSISTENT) return SELINV_E_INVALID_ARG;
+    if (mode != h->sweep_mode) {
+        h->sweep_mode = mode;
+        for (int p = 0; p < NPREC; p++) {
+            if (h->last_sweep == h->sweep[p].get()) h->last_sweep = nullptr;
+            h->sweep[p].reset();
+        }
+    }
+    return SELINV_OK;
+}
+
+selinv_status selinv_batch_set_sweep_mode(selinv_batch b, int32_t mode) {
+    if (!b || mode < SWEEP_AUTO || mode > SWEEP_PERSISTENT) return SELINV_E_INVALID_ARG;
+    if (mode != b->sweep_mode) {
+        b->sweep_mode = mode;
+        for (int p = 0; p < NPREC; p++) {
+            for (auto h : b->hs)
+                if (h->last_sweep == b->sweep[p].get()) h->last_sweep = nullptr;
+            b->sweep[p].reset();
+        }
+    }
+    return SELINV_OK;
+}
+
+int32_t selinv_sweep_is_persistent(selinv_handle h, selinv_precision prec) {
+    if (!h || !valid_prec(prec) || !h->sweep[prec]) return -1;
+    return h->sweep[prec]->persistent ? 1 : 0;
 }
 
 selinv_status selinv_set_profiling(selinv_handle h, int32_t on) {
@@ -657,7 +885,7 @@ selinv_status selinv_timings(selinv_handle h, double *ms, int32_t count) {
     if (!h || !ms) return SELINV_E_INVALID_ARG;
     if (h->state < 2 || h->last_prec < 0 || !h->profiling) return SELINV_E_STATE;
     const Sweep &S = *h->sweep[h->last_prec];
-    size_t nev = 4 + 3 * S.gat.size();
+    size_t nev = 4 + 4 * S.gat.size();
     if (h->events.size() < nev) return SELINV_E_STATE;
     HIPCHK(h->err, hipEventSynchronize(h->events[nev - 1]), "event sync");
     for (int32_t i = 0; i < count; i++) {
@@ -686,6 +914,20 @@ selinv_status selinv_level_stats(selinv_handle h, int32_t level, double *stats) 
     stats[7] = S.g4[level].count;
     stats[8] = S.g35[level].tile;
     stats[9] = S.g4[level].tile;
+    stats[10] = S.small[level].count;
+    stats[11] = S.lev_small_flops[level];
+    stats[12] = S.lev_small_elems[level];
+    return SELINV_OK;
+}
+
+static selinv_status check_sweep_error(std::string &err, const Sweep *S) {
+    if (!S || !S->persistent) return SELINV_OK;
+    int32_t flag = 0;
+    HIPCHK(err, hipMemcpy(&flag, S->d_cnt + S->ncnt + 1, 4, hipMemcpyDeviceToHost), "read sweep flag");
+    if (flag) {
+        err = "persistent sweep: a dependency wait ran out (results invalid)";
+        return SELINV_E_DEVICE;
+    }
     return SELINV_OK;
 }
 
@@ -695,7 +937,7 @@ static selinv_status sync_last(selinv_handle h) {
         return SELINV_E_STATE;
     }
     HIPCHK(h->err, hipStreamSynchronize(h->last_stream), "stream sync");
-    return SELINV_OK;
+    return check_sweep_error(h->err, h->last_sweep);
 }
 
 selinv_status selinv_get(selinv_handle h, int64_t i, int64_t j, double *out) {
@@ -878,7 +1120,7 @@ selinv_status selinv_batch_run(selinv_batch b, selinv_precision prec, void *stre
         if (st) return st;
     }
     if (!b->sweep[prec]) {
-        selinv_status st = build_sweep(b->hs, prec, b->sweep[prec], b->err);
+        selinv_status st = build_sweep(b->hs, prec, b->sweep_mode, b->sweep[prec], b->err);
         if (st) return st;
     }
     hipError_t e = launch_sweep(*b->sweep[prec], (hipStream_t)stream, nullptr);
@@ -886,11 +1128,18 @@ selinv_status selinv_batch_run(selinv_batch b, selinv_precision prec, void *stre
     for (auto h : b->hs) {
         h->last_prec = prec;
         h->last_stream = (hipStream_t)stream;
+        h->last_sweep = b->sweep[prec].get();
         h->state = 2;
     }
     return SELINV_OK;
 }
 
-void selinv_batch_destroy(selinv_batch b) { delete b; }
+void selinv_batch_destroy(selinv_batch b) {
+    if (!b) return;
+    for (int p = 0; p < NPREC; p++)
+        for (auto h : b->hs)
+            if (h->last_sweep == b->sweep[p].get()) h->last_sweep = nullptr;
+    delete b;
+}
 
 }  // extern "C"

@@ -29,7 +29,8 @@ EXPORTED = ["selinv_analyze", "selinv_factor", "selinv_run", "selinv_run_graph",
             "selinv_batch_run", "selinv_batch_destroy", "selinv_get", "selinv_get_selected",
             "selinv_get_selected_device", "selinv_export", "selinv_structure", "selinv_query",
             "selinv_set_profiling", "selinv_timings", "selinv_level_stats", "selinv_last_error",
-            "selinv_status_string", "selinv_destroy", "selinv_check_plan"]
+            "selinv_status_string", "selinv_destroy", "selinv_check_plan", "selinv_set_sweep_mode",
+            "selinv_sweep_is_persistent", "selinv_batch_set_sweep_mode"]
 
 
 class SelinvError(RuntimeError):
@@ -81,6 +82,9 @@ def _load():
         "selinv_status_string": ([C.c_int], C.c_char_p),
         "selinv_destroy": ([vp], None),
         "selinv_check_plan": ([vp, P(i64)], C.c_int),
+        "selinv_set_sweep_mode": ([vp, i32], C.c_int),
+        "selinv_sweep_is_persistent": ([vp, C.c_int], i32),
+        "selinv_batch_set_sweep_mode": ([vp, i32], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -199,22 +203,32 @@ class SelInv:
         self._check(_lib.selinv_check_plan(self._h, C.byref(out)), "check_plan")
         return out.value
 
+    SWEEP_MODES = {"auto": 0, "levels": 1, "persistent": 2}
+
+    def set_sweep_mode(self, mode="auto"):
+        m = self.SWEEP_MODES[mode] if isinstance(mode, str) else int(mode)
+        self._check(_lib.selinv_set_sweep_mode(self._h, m), "set_sweep_mode")
+        return self
+
+    def sweep_is_persistent(self, precision="fp64") -> int:
+        return int(_lib.selinv_sweep_is_persistent(self._h, _prec(precision)))
+
     def set_profiling(self, on=True):
         self._check(_lib.selinv_set_profiling(self._h, 1 if on else 0), "set_profiling")
 
     def timings(self):
         """Per-phase device ms of the last profiled run: tri_inv, normalise, diag init,
-        then (gather, steps 3+5, step 4) for every level."""
-        k = 3 + 3 * self.info["nlevels"]
+        then (small supernodes fused, gather, steps 3+5, step 4) for every level."""
+        k = 3 + 4 * self.info["nlevels"]
         out = np.zeros(k, np.float64)
         self._check(_lib.selinv_timings(self._h, _p(out, C.c_double), k), "timings")
         return out
 
     def level_stats(self, level):
-        out = np.zeros(10, np.float64)
+        out = np.zeros(13, np.float64)
         self._check(_lib.selinv_level_stats(self._h, int(level), _p(out, C.c_double)), "level_stats")
         keys = ["nsup", "max_s", "flops35", "flops4", "gather_elems", "gather_tiles", "tiles35", "tiles4",
-                "tile35", "tile4"]
+                "tile35", "tile4", "small_count", "small_flops", "small_elems"]
         return dict(zip(keys, out.tolist()))
 
     @property
@@ -243,6 +257,13 @@ class Batch:
         rc = _lib.selinv_batch_create(arr, len(self.mats), C.byref(self._b))
         if rc:
             raise SelinvError(rc, "batch_create")
+
+    def set_sweep_mode(self, mode="auto"):
+        m = SelInv.SWEEP_MODES[mode] if isinstance(mode, str) else int(mode)
+        rc = _lib.selinv_batch_set_sweep_mode(self._b, m)
+        if rc:
+            raise SelinvError(rc, "batch_set_sweep_mode")
+        return self
 
     def run(self, precision="fp64", stream=None):
         rc = _lib.selinv_batch_run(self._b, _prec(precision), _stream_ptr(stream))

@@ -287,3 +287,82 @@ def test_c4_full_size(si, sampled_c4, prec):
     say("c4", prec, "identity", rr, cr, "sampled", en, ed)
     assert max(rr, cr) <= (1e-10 if prec == "fp64" else 1e-4)
     assert max(en, ed) <= TOL[prec]
+
+
+# --------------------------------------------------------------------------
+# persistent, dependency-driven sweep vs per-level launches
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("prec", ["fp64", "mixed_fp32", "mixed_bf16x3"])
+def test_persistent_sweep_matches_level_sweep_c1(si, c1_pair, prec):
+    import torch
+    w, s, o = c1_pair
+    say("c1 persistent", prec)
+    s.set_sweep_mode("levels")
+    s.run(prec)
+    ref = s.get_selected()
+    s.set_sweep_mode("persistent")
+    s.run(prec)
+    assert s.sweep_is_persistent(prec) == 1
+    assert np.array_equal(s.get_selected(), ref)
+    st = torch.cuda.Stream()
+    for rep in range(3):
+        s.run(prec, stream=st, graph=True)
+        assert np.array_equal(s.get_selected(), ref), rep
+    s.set_sweep_mode("auto")
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"n{c[0]}_cap{c[3]}" for c in CASES])
+def test_persistent_sweep_random(si, case):
+    n, dens, seed, cap, relax, pad = case
+    say("persistent random", case)
+    cp, ri, v, _ = random_sparse(n, dens, seed, symmetric_pattern=seed % 2 == 0)
+    perm = np.random.default_rng(seed).permutation(n).astype(np.int32)
+    s, o = lib_and_oracle(si, n, cp, ri, v, perm, cap, relax, pad)
+    s.set_sweep_mode("persistent").run("fp64")
+    compare_superset(s, o, TOL["fp64"])
+
+
+def test_persistent_sweep_batch(si):
+    ws = config_c3(count=3)
+    say("persistent batch", [w.n for w in ws])
+    mats = [si.SelInv(w.n, w.colptr, w.rowind, w.perm, w.max_super, w.relax, w.pad_pct).factor(w.values)
+            for w in ws]
+    refs = []
+    for m in mats:
+        m.set_sweep_mode("levels").run("fp64")
+        refs.append(m.get_selected())
+    b = si.Batch(mats).set_sweep_mode("persistent")
+    b.run("fp64")
+    for m, ref in zip(mats, refs):
+        assert np.array_equal(m.get_selected(), ref)
+    b.close()
+
+
+# --------------------------------------------------------------------------
+# profiled run: per-phase events and per-level work accounting
+# --------------------------------------------------------------------------
+def test_c1_profiled_run_and_level_work(si, c1_pair):
+    w, s, o = c1_pair
+    say("c1 profiled")
+    s.set_sweep_mode("levels")
+    s.set_profiling(True)
+    s.run("fp64")
+    t = s.timings()
+    s.set_profiling(False)
+    L = s.info["nlevels"]
+    assert t.shape == (3 + 4 * L,) and np.all(np.isfinite(t)) and np.all(t >= 0)
+    # the profiled run computes the same result
+    assert np.abs(s.get_selected() - o.get_selected()).max() / np.abs(o.get_selected()).max() < 1e-11
+    lev = [s.level_stats(d) for d in range(L)]
+    st = s.structure()
+    assert sum(l["nsup"] for l in lev) == len(st["xsup"]) - 1
+    # every supernode's steps 3-5 are counted once, in the fused launch or in
+    # the large-supernode launches: total flops = sum_K 4 s c_L c_U + 2 s^2 c_U
+    rl = np.diff(st["rl_ptr"]).astype(np.float64)
+    ru = np.diff(st["ru_ptr"]).astype(np.float64)
+    s_ = np.diff(st["xsup"]).astype(np.float64)
+    want = float(np.sum(4 * s_ * rl * ru + 2 * s_ * s_ * ru * (ru > 0)))
+    got = sum(l["flops35"] + l["flops4"] + l["small_flops"] for l in lev)
+    assert abs(got - want) <= 1e-9 * want
+    assert sum(l["small_count"] for l in lev) > 0
+    s.set_sweep_mode("auto")
