@@ -26,6 +26,9 @@ HOST_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-fopenmp", "-march=x86-64-v3", "-Wa
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-mcode-object-version=5",
              # keep packed FP32 instructions out of every kernel
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             # MFMA accumulators in ordinary VGPRs: keeps the loop-carried
+             # accumulators from being copied between register files
+             "-mllvm", "-amdgpu-mfma-vgpr-form=1",
              "-Wall", "-Wno-unused-parameter"]
 
 

@@ -39,7 +39,8 @@ __global__ __launch_bounds__(256) void gemm_v2(const GemmProb *__restrict__ prob
                                                const GemmTile *__restrict__ tiles) {
     __shared__ Smem<MODE, BM, BN> sm;
     const GemmTile tl = tiles[blockIdx.x];
-    gemm_tile<MODE, BM, BN, TA, TC>(probs[tl.prob], tl.m0, tl.n0, sm);
+    // only the step-4 product accumulates into an input matrix
+    gemm_tile<MODE, BM, BN, TA, TC, ROLE == 2>(probs[tl.prob], tl.m0, tl.n0, sm);
 }
 
 template <int MODE, typename TA, typename TC, int ROLE>

@@ -116,7 +116,7 @@ __global__ __launch_bounds__(256) void tri_base_kernel(const TriItem *__restrict
 #pragma unroll
         for (int q = 0; q < 16; q++) {
             const int c = wave + 4 * q;
-            v[q] = it.D[(int64_t)(o + rr) + (int64_t)(o + min(c, b - 1)) * s];
+            v[q] = gptr(it.D)[(int64_t)(o + rr) + (int64_t)(o + min(c, b - 1)) * s];
         }
 #pragma unroll
         for (int q = 0; q < 16; q++) {
@@ -150,7 +150,7 @@ __global__ __launch_bounds__(256) void tri_base_kernel(const TriItem *__restrict
     tri_round<2>(sm, lane, wave);
     tri_round<3>(sm, lane, wave);
     __syncthreads();
-    double *Linv = it.Linv, *Uinv = it.Uinv;
+    SELINV_GLOBAL double *Linv = gptr_w(it.Linv), *Uinv = gptr_w(it.Uinv);
     {
         const int r = lane;
 #pragma unroll
@@ -188,16 +188,16 @@ template <typename T>
 __global__ __launch_bounds__(256) void extract_kernel(ExtractArgs a) {
     const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (p >= a.nnz) return;
-    const int64_t loc = a.loc[p];
+    const int64_t loc = gptr(a.loc)[p];
     const int64_t kind = loc >> 60, off = loc & ((int64_t(1) << 60) - 1);
     double v;
     if (kind == 0)
-        v = a.Zd[off];
+        v = gptr(a.Zd)[off];
     else if (kind == 1)
-        v = (double)((const T *)a.ZL)[off];
+        v = (double)gptr((const T *)a.ZL)[off];
     else
-        v = (double)((const T *)a.ZU)[off];
-    a.out[p] = v;
+        v = (double)gptr((const T *)a.ZU)[off];
+    gptr_w(a.out)[p] = v;
 }
 
 // ---------------------------------------------------------------------------

@@ -78,9 +78,9 @@ __global__ __launch_bounds__(256) void sweep_kernel(const PersistArgs a) {
         if (tk.type == PT_GATHER)
             gather_tile<T>(a.mats[tk.mat], tk.K, tk.i0, tk.i1, sm.t);
         else if (tk.type == PT_STEP35)
-            gemm_tile<MODE, 64, 64, T, T>(a.probs[tk.prob], tk.i0, tk.i1, sm.g);
+            gemm_tile<MODE, 64, 64, T, T, false>(a.probs[tk.prob], tk.i0, tk.i1, sm.g);
         else
-            gemm_tile<MODE, 64, 64, T, double>(a.probs[tk.prob], tk.i0, tk.i1, sm.g);
+            gemm_tile<MODE, 64, 64, T, double, true>(a.probs[tk.prob], tk.i0, tk.i1, sm.g);
         __syncthreads();  // every thread's stores of this task are complete
         if (threadIdx.x == 0) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -110,13 +110,13 @@ __global__ __launch_bounds__(256) void small_kernel(const MatDev *__restrict__ m
     };
     __shared__ Shared sm;
     const SmallItem it = items[blockIdx.x];
-    const SnRec r = mats[it.mat].sn[it.K];
-    if (r.cl > 0 && r.cu > 0) gather_tile<T>(mats[it.mat], it.K, 0, 0, sm.t);
+    const SELINV_GLOBAL SnRec *sn = gptr(mats[it.mat].sn);
+    if (sn[it.K].cl > 0 && sn[it.K].cu > 0) gather_tile<T>(mats[it.mat], it.K, 0, 0, sm.t);
     __syncthreads();
-    if (it.pzu >= 0) gemm_tile<MODE, 64, 64, T, T>(probs[it.pzu], 0, 0, sm.g);
-    if (it.pzl >= 0) gemm_tile<MODE, 64, 64, T, T>(probs[it.pzl], 0, 0, sm.g);
+    if (it.pzu >= 0) gemm_tile<MODE, 64, 64, T, T, false>(probs[it.pzu], 0, 0, sm.g);
+    if (it.pzl >= 0) gemm_tile<MODE, 64, 64, T, T, false>(probs[it.pzl], 0, 0, sm.g);
     __syncthreads();
-    if (it.pg4 >= 0) gemm_tile<MODE, 64, 64, T, double>(probs[it.pg4], 0, 0, sm.g);
+    if (it.pg4 >= 0) gemm_tile<MODE, 64, 64, T, double, true>(probs[it.pg4], 0, 0, sm.g);
 }
 
 hipError_t launch_small(int mode, const MatDev *mats, const GemmProb *probs, const SmallItem *items, int count,

@@ -209,8 +209,11 @@ int add_prob(std::vector<GemmProb> &probs, const void *A, int opA, int lda,
              double alpha, double beta, Extents *ext = nullptr, int ein = 8, int eout = 8) {
     if (M <= 0 || N <= 0) return 0;
     if (ext) {
-        if (opA == 0) ext->check(A, M, K, lda, ein); else ext->check(A, K, M, lda, ein);
-        if (opB == 0) ext->check(B, K, N, ldb, ein); else ext->check(B, N, K, ldb, ein);
+        if (K > 0) {
+            if (opA == 0) ext->check(A, M, K, lda, ein); else ext->check(A, K, M, lda, ein);
+            if (opB == 0) ext->check(B, K, N, ldb, ein); else ext->check(B, N, K, ldb, ein);
+        }
+        if (K < 0) ext->violations++;
         ext->check(C, M, N, ldc, eout);
         if (Cin) ext->check(Cin, M, N, ldcin, eout);
         if (lda < (opA == 0 ? M : K) || ldb < (opB == 0 ? K : N) || ldc < M) ext->violations++;

@@ -9,6 +9,21 @@
 
 namespace selinv {
 
+// Global-memory views of generic pointers.  Pointers read from records in
+// memory are generic (flat) to the compiler; flat loads also count against
+// the LDS wait counter, so a wait for LDS data would wait for every global
+// load in flight.  Casting to the global address space gives global loads and
+// stores that keep the two counters apart.
+#define SELINV_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ const SELINV_GLOBAL T *gptr(const T *p) {
+    return (const SELINV_GLOBAL T *)p;
+}
+template <typename T>
+__device__ __forceinline__ SELINV_GLOBAL T *gptr_w(T *p) {
+    return (SELINV_GLOBAL T *)p;
+}
+
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
@@ -51,22 +66,55 @@ struct Smem<CMP_BF16X3, BM, BN, BK> {
 };
 
 // One BM x BN output tile of C = alpha op(A) op(B) + beta Cin, computed by
-// the 256 threads of the calling workgroup (see gemm.hip for the design).
-template <int MODE, int BM, int BN, typename TA, typename TC, int BK = Mode<MODE>::BK>
-__device__ __forceinline__ void gemm_tile(const GemmProb &p, const int m0, const int n0,
-                                          Smem<MODE, BM, BN, BK> &sm) {
+// the 256 threads of the calling workgroup (see gemm.hip for the design),
+// for fixed operand forms OPA, OPB (0: N, 1: T).
+// Each thread owns LA elements of every A chunk and LB of every B chunk; their
+// addresses are formed once (rows clamped into the operand) and advanced by a
+// uniform step per chunk, so that the loop issues its loads without per
+// element address arithmetic.  Only the last, partial chunk clamps k.  Values
+// outside the operands are loaded from a clamped address and replaced by zero
+// when staged into LDS, so that no load is tied to a branch.
+// CIN: the problem may carry an input matrix (beta Cin); without it Cin is
+// ignored and its registers are not reserved.
+template <int MODE, int BM, int BN, typename TA, typename TC, bool CIN, int BK, int OPA, int OPB>
+__device__ __forceinline__ void gemm_tile_op(const GemmProb &p, const int m0, const int n0,
+                                             Smem<MODE, BM, BN, BK> &sm) {
     typedef typename Mode<MODE>::T T;
     typedef typename Mode<MODE>::Acc Acc;
     static_assert(MODE != CMP_BF16X3 || BK % 32 == 0, "split-BF16 chunks are multiples of 32");
+    static_assert(256 % BM == 0 && 256 % BN == 0 && 256 % BK == 0, "thread-to-element maps assume divisors of 256");
     constexpr int WM = BM / 2, WN = BN / 2, TM = WM / 16, TN = WN / 16;
     constexpr int LA = BM * BK / 256, LB = BN * BK / 256;
-    const TA *__restrict__ A = (const TA *)p.A;
-    const TA *__restrict__ B = (const TA *)p.B;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     const int M = p.M, N = p.N, K = p.K;
-    const int opA = p.opA, opB = p.opB;
     const int64_t lda = p.lda, ldb = p.ldb;
+
+    // (row, k) of element t of this thread's share of an A chunk, (k, col) of B;
+    // the contiguous dimension of the operand runs along consecutive threads
+    auto ai = [&](int t) { return OPA == 0 ? tid % BM : tid / BK + t * (256 / BK); };
+    auto ak = [&](int t) { return OPA == 0 ? tid / BM + t * (256 / BM) : tid % BK; };
+    auto bj = [&](int t) { return OPB == 0 ? tid / BK + t * (256 / BK) : tid % BN; };
+    auto bk = [&](int t) { return OPB == 0 ? tid % BK : tid / BN + t * (256 / BN); };
+    const int64_t ksa = OPA == 0 ? lda : 1;  // address step per unit of k
+    const int64_t ksb = OPB == 0 ? 1 : ldb;
+
+    const SELINV_GLOBAL TA *pa[LA];
+    const SELINV_GLOBAL TA *pb[LB];
+    {
+        const SELINV_GLOBAL TA *A = gptr((const TA *)p.A);
+        const SELINV_GLOBAL TA *B = gptr((const TA *)p.B);
+#pragma unroll
+        for (int t = 0; t < LA; t++) {
+            const int64_t r = min(m0 + ai(t), M - 1);
+            pa[t] = A + (OPA == 0 ? r : r * lda) + ak(t) * ksa;
+        }
+#pragma unroll
+        for (int t = 0; t < LB; t++) {
+            const int64_t c = min(n0 + bj(t), N - 1);
+            pb[t] = B + (OPB == 0 ? c * ldb : c) + bk(t) * ksb;
+        }
+    }
 
     Acc acc[TM][TN];
 #pragma unroll
@@ -74,71 +122,46 @@ __device__ __forceinline__ void gemm_tile(const GemmProb &p, const int m0, const
 #pragma unroll
         for (int j = 0; j < TN; j++) acc[i][j] = Acc{0, 0, 0, 0};
 
-    T ra[LA], rb[LB];
-    // element t of this thread's share of a chunk: (row in tile, k in chunk)
-    auto a_idx = [&](int t, int &i, int &k) {
-        const int e = tid + 256 * t;
-        if (opA == 0) {
-            i = e % BM;
-            k = e / BM;
+    TA ra[LA], rb[LB];
+    auto gload = [&](int c) {
+        const int k0 = c * BK;
+        if (k0 + BK <= K) {
+#pragma unroll
+            for (int t = 0; t < LA; t++) ra[t] = pa[t][k0 * ksa];
+#pragma unroll
+            for (int t = 0; t < LB; t++) rb[t] = pb[t][k0 * ksb];
         } else {
-            k = e % BK;
-            i = e / BK;
+            // last, partial chunk: k clamped into the operand
+#pragma unroll
+            for (int t = 0; t < LA; t++) ra[t] = pa[t][(int64_t)(min(k0 + ak(t), K - 1) - ak(t)) * ksa];
+#pragma unroll
+            for (int t = 0; t < LB; t++) rb[t] = pb[t][(int64_t)(min(k0 + bk(t), K - 1) - bk(t)) * ksb];
         }
     };
-    auto b_idx = [&](int t, int &j, int &k) {
-        const int e = tid + 256 * t;
-        if (opB == 0) {
-            k = e % BK;
-            j = e / BK;
-        } else {
-            j = e % BN;
-            k = e / BN;
-        }
-    };
-    auto gload = [&](int k0) {
+    auto sstore = [&](int buf, int c) {
+        const int k0 = c * BK;
 #pragma unroll
         for (int t = 0; t < LA; t++) {
-            int i, k;
-            a_idx(t, i, k);
-            const int gi = m0 + i, gk = k0 + k;
-            T v = 0;
-            if (gi < M && gk < K) v = (T)(opA == 0 ? A[gi + gk * lda] : A[gk + gi * lda]);
-            ra[t] = v;
-        }
-#pragma unroll
-        for (int t = 0; t < LB; t++) {
-            int j, k;
-            b_idx(t, j, k);
-            const int gj = n0 + j, gk = k0 + k;
-            T v = 0;
-            if (gj < N && gk < K) v = (T)(opB == 0 ? B[gk + gj * ldb] : B[gj + gk * ldb]);
-            rb[t] = v;
-        }
-    };
-    auto sstore = [&](int buf) {
-#pragma unroll
-        for (int t = 0; t < LA; t++) {
-            int i, k;
-            a_idx(t, i, k);
+            const int i = ai(t), k = ak(t);
+            const T v = (m0 + i < M && k0 + k < K) ? (T)ra[t] : (T)0;
             if constexpr (MODE == CMP_BF16X3) {
-                const __bf16 h = (__bf16)ra[t];
+                const __bf16 h = (__bf16)v;
                 sm.ah[buf][i][k] = h;
-                sm.al[buf][i][k] = (__bf16)(ra[t] - (float)h);
+                sm.al[buf][i][k] = (__bf16)(v - (float)h);
             } else {
-                sm.a[buf][k][i] = ra[t];
+                sm.a[buf][k][i] = v;
             }
         }
 #pragma unroll
         for (int t = 0; t < LB; t++) {
-            int j, k;
-            b_idx(t, j, k);
+            const int j = bj(t), k = bk(t);
+            const T v = (n0 + j < N && k0 + k < K) ? (T)rb[t] : (T)0;
             if constexpr (MODE == CMP_BF16X3) {
-                const __bf16 h = (__bf16)rb[t];
+                const __bf16 h = (__bf16)v;
                 sm.bh[buf][j][k] = h;
-                sm.bl[buf][j][k] = (__bf16)(rb[t] - (float)h);
+                sm.bl[buf][j][k] = (__bf16)(v - (float)h);
             } else {
-                sm.b[buf][k][j] = rb[t];
+                sm.b[buf][k][j] = v;
             }
         }
     };
@@ -191,42 +214,80 @@ __device__ __forceinline__ void gemm_tile(const GemmProb &p, const int m0, const
         }
     };
 
-    gload(0);
-    sstore(0);
+    // K == 0 (C = beta Cin): no chunk, no operand read
+    const int nch = (K + BK - 1) / BK;
+    if (nch > 0) {
+        gload(0);
+        sstore(0, 0);
+    }
     __syncthreads();
-    int buf = 0;
-    for (int k0 = 0; k0 < K; k0 += BK) {
-        const bool more = k0 + BK < K;
-        if (more) gload(k0 + BK);
+    for (int c = 0; c < nch; c++) {
+        const int buf = c & 1;
+        const bool more = c + 1 < nch;
+        if (more) gload(c + 1);
         compute(buf);
-        if (more) sstore(buf ^ 1);
+        if (more) sstore(buf ^ 1, c + 1);
         __syncthreads();
-        buf ^= 1;
     }
 
-    TC *__restrict__ C = (TC *)p.C;
-    const TC *__restrict__ Cin = (const TC *)p.Cin;
+    SELINV_GLOBAL TC *__restrict__ C = gptr_w((TC *)p.C);
+    const SELINV_GLOBAL TC *__restrict__ Cin = gptr((const TC *)p.Cin);
     const int64_t ldc = p.ldc, ldcin = p.ldcin;
     const double alpha = p.alpha, beta = p.beta;
+    // rows of the 16x16 result held by this lane: v_mfma_f64_16x16x4
+    // interleaves the four row groups (row = lane/16 + 4v); the f32 and bf16
+    // forms keep them contiguous (row = 4 (lane/16) + v)
+    auto row_n = [&](int j, int v) {
+        const int nr = (MODE == CMP_F64) ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v;
+        return n0 + wn * WN + j * 16 + nr;
+    };
+    const bool has_cin = CIN && p.Cin != nullptr;
 #pragma unroll
-    for (int i = 0; i < TM; i++)
+    for (int i = 0; i < TM; i++) {
+        // the Cin loads of one row of 16x16 tiles in flight together
+        // (clamped addresses)
+        double cin[TN][4];
+        if (has_cin) {
 #pragma unroll
-        for (int j = 0; j < TN; j++) {
-            const int gm = m0 + wm * WM + i * 16 + (lane & 15);
-            if (gm >= M) continue;
+            for (int j = 0; j < TN; j++)
+#pragma unroll
+                for (int v = 0; v < 4; v++) {
+                    const int64_t gm = min(m0 + wm * WM + i * 16 + (lane & 15), M - 1);
+                    const int64_t gn = min(row_n(j, v), N - 1);
+                    cin[j][v] = (double)Cin[gm + gn * ldcin];
+                }
+        }
+        const int gm = m0 + wm * WM + i * 16 + (lane & 15);
+        if (gm >= M) continue;
+#pragma unroll
+        for (int j = 0; j < TN; j++)
 #pragma unroll
             for (int v = 0; v < 4; v++) {
-                // rows of the 16x16 result held by this lane: v_mfma_f64_16x16x4
-                // interleaves the four row groups (row = lane/16 + 4v); the f32
-                // and bf16 forms keep them contiguous (row = 4 (lane/16) + v)
-                const int nr = (MODE == CMP_F64) ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v;
-                const int gn = n0 + wn * WN + j * 16 + nr;
+                const int gn = row_n(j, v);
                 if (gn >= N) continue;
                 double r = alpha * (double)acc[i][j][v];
-                if (Cin) r += beta * (double)Cin[gm + gn * ldcin];
-                C[gm + gn * ldc] = (TC)r;
+                if (has_cin) r += beta * cin[j][v];
+                C[gm + (int64_t)gn * ldc] = (TC)r;
             }
-        }
+    }
+}
+
+// Dispatch on the operand forms of the problem (uniform across the
+// workgroup).
+template <int MODE, int BM, int BN, typename TA, typename TC, bool CIN, int BK = Mode<MODE>::BK>
+__device__ __forceinline__ void gemm_tile(const GemmProb &p, const int m0, const int n0,
+                                          Smem<MODE, BM, BN, BK> &sm) {
+    if (p.opA == 0) {
+        if (p.opB == 0)
+            gemm_tile_op<MODE, BM, BN, TA, TC, CIN, BK, 0, 0>(p, m0, n0, sm);
+        else
+            gemm_tile_op<MODE, BM, BN, TA, TC, CIN, BK, 0, 1>(p, m0, n0, sm);
+    } else {
+        if (p.opB == 0)
+            gemm_tile_op<MODE, BM, BN, TA, TC, CIN, BK, 1, 0>(p, m0, n0, sm);
+        else
+            gemm_tile_op<MODE, BM, BN, TA, TC, CIN, BK, 1, 1>(p, m0, n0, sm);
+    }
 }
 
 // LDS of one gather tile
@@ -239,46 +300,66 @@ struct GatherSmem {
 
 // One 64x64 tile (rows a0.., columns b0..) of G_K = A^{-T}(R_L(K), R_U(K)),
 // gathered by the 256 threads of the calling workgroup (see kernels.hip).
+// Every load goes through a global-memory view and is issued unconditionally
+// (clamped to a valid index, the unused value discarded), so that a thread's
+// loads of one stage are all in flight together.
 template <typename T>
 __device__ __forceinline__ void gather_tile(const MatDev &M, const int K, const int a0, const int b0,
                                             GatherSmem<T> &sm) {
-    const SnRec sk = M.sn[K];
     T(&tileS)[64][65] = sm.tileS;
     int32_t *rowR = sm.rowR, *rowI = sm.rowI, *colJ = sm.colJ;
     int64_t *rowUp = sm.rowUp, *rowUoff = sm.rowUoff, *colDiag = sm.colDiag, *colLow = sm.colLow,
             *colLoff = sm.colLoff;
+    const SELINV_GLOBAL SnRec *sn = gptr(M.sn);
+    const int32_t sk_cl = sn[K].cl, sk_cu = sn[K].cu;
+    const int64_t sk_rl_off = sn[K].rl_off, sk_ru_off = sn[K].ru_off, sk_g_off = sn[K].g_off;
+    const SELINV_GLOBAL int32_t *supof = gptr(M.supof);
     const int tid = threadIdx.x;
-    const int na = min(64, sk.cl - a0), nb = min(64, sk.cu - b0);
+    const int na = min(64, sk_cl - a0), nb = min(64, sk_cu - b0);  // both >= 1
     if (tid < 64) {
+        // row a0 + tid of G: its row index r of A, supernode I, and where row
+        // r of U(I, R_U(I)) starts
+        const int t = min(tid, na - 1);
+        const int64_t a = sk_rl_off + a0 + t;
+        const int32_t r = gptr(M.rl)[a];
+        const int64_t uo = gptr(M.u_rowoff)[a];
+        const int32_t I = supof[r];
+        const int32_t si_f = sn[I].f, si_cu = sn[I].cu;
+        const int64_t si_off_u = sn[I].off_u;
         if (tid < na) {
-            const int64_t a = sk.rl_off + a0 + tid;
-            const int32_t r = M.rl[a];
-            const int32_t I = M.supof[r];
-            const SnRec si = M.sn[I];
             rowR[tid] = r;
             rowI[tid] = I;
-            rowUp[tid] = si.off_u + (int64_t)(r - si.f) * si.cu;
-            rowUoff[tid] = M.u_rowoff[a] + b0;
+            rowUp[tid] = si_off_u + (int64_t)(r - si_f) * si_cu;
+            rowUoff[tid] = uo + b0;
         }
     } else if (tid < 128) {
-        const int t = tid - 64;
-        if (t < nb) {
-            const int64_t b = sk.ru_off + b0 + t;
-            const int32_t c = M.ru[b];
-            const int32_t J = M.supof[c];
-            const SnRec sj = M.sn[J];
+        // column b0 + t of G: supernode J of its column c, and where column c
+        // starts in the diagonal block and in the L panel of J
+        const int t = min(tid - 64, nb - 1);
+        const int64_t b = sk_ru_off + b0 + t;
+        const int32_t c = gptr(M.ru)[b];
+        const int64_t lo = gptr(M.l_coloff)[b];
+        const int32_t J = supof[c];
+        const int32_t sj_f = sn[J].f, sj_s = sn[J].s, sj_cl = sn[J].cl;
+        const int64_t sj_off_d = sn[J].off_d, sj_off_l = sn[J].off_l;
+        if (tid - 64 < nb) {
             colJ[t] = J;
-            colDiag[t] = sj.off_d + (int64_t)(c - sj.f) * sj.s - sj.f;
-            colLow[t] = sj.off_l + (int64_t)(c - sj.f) * sj.cl;
-            colLoff[t] = M.l_coloff[b] + a0;
+            colDiag[t] = sj_off_d + (int64_t)(c - sj_f) * sj_s - sj_f;
+            colLow[t] = sj_off_l + (int64_t)(c - sj_f) * sj_cl;
+            colLoff[t] = lo + a0;
         }
     }
     __syncthreads();
-    const T *ZL = (const T *)M.ZL;
-    const T *ZU = (const T *)M.ZU;
-    // Each thread owns 16 entries of the tile.  Loads are batched: first every
-    // relative index, then every source value, so that a thread waits for two
-    // memory round trips rather than two per entry.
+    const SELINV_GLOBAL T *ZL = gptr((const T *)M.ZL);
+    const SELINV_GLOBAL T *ZU = gptr((const T *)M.ZU);
+    const SELINV_GLOBAL double *Zd = gptr(M.Zd);
+    const SELINV_GLOBAL int32_t *mapL = gptr(M.mapL);
+    const SELINV_GLOBAL int32_t *mapU = gptr(M.mapU);
+    // Each thread owns 16 entries of the tile.  Stage 1 reads the relative
+    // positions, stage 2 the source values; a thread waits for two memory
+    // round trips per side.  Entries outside the tile or of another kind read
+    // element 0 of the array instead (every device array holds at least one
+    // element) and discard it, so that no load sits behind a branch.
     constexpr int PER = 64 * 64 / 256;
     {
         // diagonal and L-side sources, threads along the rows of G (contiguous)
@@ -297,12 +378,14 @@ __device__ __forceinline__ void gather_tile(const MatDev &M, const int K, const 
 #pragma unroll
         for (int t = 0; t < PER; t++) {
             const int e = tid + 256 * t, ia = e & 63, ib = e >> 6;
-            mi[t] = kind[t] == 2 ? M.mapL[colLoff[ib] + ia] : 0;
+            mi[t] = mapL[kind[t] == 2 ? colLoff[ib] + ia : 0];
         }
 #pragma unroll
         for (int t = 0; t < PER; t++) {
             const int e = tid + 256 * t, ia = e & 63, ib = e >> 6;
-            val[t] = kind[t] == 1 ? (T)M.Zd[colDiag[ib] + rowR[ia]] : kind[t] == 2 ? ZL[colLow[ib] + mi[t]] : (T)0;
+            const double vd = Zd[kind[t] == 1 ? colDiag[ib] + rowR[ia] : 0];
+            const T vl = ZL[kind[t] == 2 ? colLow[ib] + mi[t] : 0];
+            val[t] = kind[t] == 1 ? (T)vd : vl;
         }
 #pragma unroll
         for (int t = 0; t < PER; t++) {
@@ -323,12 +406,12 @@ __device__ __forceinline__ void gather_tile(const MatDev &M, const int K, const 
 #pragma unroll
         for (int t = 0; t < PER; t++) {
             const int e = tid + 256 * t, ib = e & 63, ia = e >> 6;
-            mi[t] = up[t] ? M.mapU[rowUoff[ia] + ib] : 0;
+            mi[t] = mapU[up[t] ? rowUoff[ia] + ib : 0];
         }
 #pragma unroll
         for (int t = 0; t < PER; t++) {
             const int e = tid + 256 * t, ia = e >> 6;
-            val[t] = up[t] ? ZU[rowUp[ia] + mi[t]] : (T)0;
+            val[t] = ZU[up[t] ? rowUp[ia] + mi[t] : 0];
         }
 #pragma unroll
         for (int t = 0; t < PER; t++) {
@@ -337,10 +420,10 @@ __device__ __forceinline__ void gather_tile(const MatDev &M, const int K, const 
         }
     }
     __syncthreads();
-    T *G = (T *)M.G + sk.g_off;
+    SELINV_GLOBAL T *G = gptr_w((T *)M.G + sk_g_off);
     for (int e = tid; e < 64 * 64; e += 256) {
         const int ia = e & 63, ib = e >> 6;
-        if (ia < na && ib < nb) G[(a0 + ia) + (int64_t)(b0 + ib) * sk.cl] = tileS[ib][ia];
+        if (ia < na && ib < nb) G[(a0 + ia) + (int64_t)(b0 + ib) * sk_cl] = tileS[ib][ia];
     }
 }
 
