@@ -207,7 +207,7 @@ selinv_status selinv_timings(selinv_handle h, double *ms, int32_t count);
  * supernodes, [1] widest supernode; for the launches of the large supernodes
  * [2] flops of steps 3+5, [3] flops of step 4, [4] entries of G gathered, [5]
  * gather tiles, [6] product tiles of steps 3+5, [7] of step 4, [8] and [9] the
- * output tile edge (64 or 128) of those two product launches; for the fused
+ * output tile edge (32, 64 or 128) of those two product launches; for the fused
  * small-supernode launch [10] supernodes, [11] flops of steps 3-5, [12]
  * entries of G gathered. */
 selinv_status selinv_level_stats(selinv_handle h, int32_t level, double *stats);

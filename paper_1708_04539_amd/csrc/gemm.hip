@@ -6,9 +6,9 @@
 //
 // One launch covers a list of output tiles drawn from many problems of
 // different shapes (all supernodes of one level, of every matrix of a batch).
-// Tile BM x BN (128x128 or 64x64) per workgroup of 256 threads = 4 wavefronts
-// in a 2x2 arrangement, each wavefront owning a (BM/2)x(BN/2) block made of
-// 16x16 MFMA tiles.  The k loop is software pipelined: the next k-chunk is
+// Tile BM x BN (128x128, 64x64 or 32x32) per workgroup of 256 threads = 4
+// wavefronts in a 2x2 arrangement, each wavefront owning a (BM/2)x(BN/2)
+// block made of 16x16 MFMA tiles.  The k loop is software pipelined: the next k-chunk is
 // loaded from global memory into registers while the current one is consumed
 // from LDS, and LDS is double buffered (one barrier per chunk).
 //
@@ -47,14 +47,16 @@ template <int MODE, typename TA, typename TC, int ROLE>
 static void launch_mode(int tile, const GemmProb *probs, const GemmTile *tiles, int ntiles, hipStream_t st) {
     if (tile == GEMM_TILE_128)
         hipLaunchKernelGGL((gemm_v2<MODE, 128, 128, TA, TC, ROLE>), dim3(ntiles), dim3(256), 0, st, probs, tiles);
-    else
+    else if (tile == GEMM_TILE_64)
         hipLaunchKernelGGL((gemm_v2<MODE, 64, 64, TA, TC, ROLE>), dim3(ntiles), dim3(256), 0, st, probs, tiles);
+    else
+        hipLaunchKernelGGL((gemm_v2<MODE, 32, 32, TA, TC, ROLE>), dim3(ntiles), dim3(256), 0, st, probs, tiles);
 }
 
 hipError_t launch_gemm(int role, int mode, int tile, const GemmProb *probs, const GemmTile *tiles, int ntiles,
                        hipStream_t st) {
     if (ntiles <= 0) return hipSuccess;
-    if (tile != GEMM_TILE_64 && tile != GEMM_TILE_128) return hipErrorInvalidValue;
+    if (tile != GEMM_TILE_32 && tile != GEMM_TILE_64 && tile != GEMM_TILE_128) return hipErrorInvalidValue;
     switch (role) {
         case GEMM_PRO_F64:  // FP64 in and out
             launch_mode<CMP_F64, double, double, 0>(tile, probs, tiles, ntiles, st);

@@ -31,7 +31,8 @@ namespace selinv {
 //   1. the 16x16 diagonal blocks, by substitution: wavefront w takes block w;
 //      lane c < 16 forms column c of (L_ww)^{-1} and lane 16 + c column c of
 //      (U_ww^T)^{-1} = row c of (U_ww)^{-1}, the same forward recurrence for
-//      both (the L diagonal is 1);
+//      both (the L diagonal is 1; U's diagonal enters through reciprocals
+//      formed once per block);
 //   2. the off-diagonal 16x16 blocks by distance d = 1, 2, 3 from the
 //      diagonal, on v_mfma_f64_16x16x4 (X = L^{-1}, Y = U^{-1}):
 //        X_ij = -X_ii (sum_{k=j}^{i-1} L_ik X_kj)      (i = j + d)
@@ -47,6 +48,7 @@ struct TriSmem {
     double Ds[64][65];     // Ds[c][r] = D(o + r, o + c), identity-padded
     double Xs[64][65];     // Xs[c][r]: r > c: L^{-1}(r, c); r <= c: U^{-1}(r, c)
     double Ts[4][16][17];  // per-wavefront 16x16 intermediate
+    double rd[64];         // 1 / U(c, c)
 };
 
 typedef double v4d_t __attribute__((ext_vector_type(4)));
@@ -121,7 +123,9 @@ __global__ __launch_bounds__(256) void tri_base_kernel(const TriItem *__restrict
 #pragma unroll
         for (int q = 0; q < 16; q++) {
             const int c = wave + 4 * q;
-            sm.Ds[c][r] = (r < b && c < b) ? v[q] : (r == c ? 1.0 : 0.0);
+            const double d = (r < b && c < b) ? v[q] : (r == c ? 1.0 : 0.0);
+            sm.Ds[c][r] = d;
+            if (r == c) sm.rd[c] = 1.0 / d;
         }
     }
     __syncthreads();
@@ -133,7 +137,7 @@ __global__ __launch_bounds__(256) void tri_base_kernel(const TriItem *__restrict
         for (int r = 0; r < 16; r++) x[r] = r == c ? 1.0 : 0.0;
 #pragma unroll
         for (int k = 0; k < 16; k++) {
-            if (up) x[k] = x[k] / sm.Ds[base + k][base + k];
+            if (up) x[k] = x[k] * sm.rd[base + k];
 #pragma unroll
             for (int r = k + 1; r < 16; r++)
                 x[r] = fma(-(up ? sm.Ds[base + r][base + k] : sm.Ds[base + k][base + r]), x[k], x[r]);

@@ -14,7 +14,7 @@ constexpr int TRI_MAX_S = 1024;
 // (TriItem.j0 = first row/column of the sub-block)
 hipError_t launch_tri_base(const TriItem *items, int count, hipStream_t st);
 // output tile of the grouped GEMM
-enum : int { GEMM_TILE_64 = 64, GEMM_TILE_128 = 128 };
+enum : int { GEMM_TILE_32 = 32, GEMM_TILE_64 = 64, GEMM_TILE_128 = 128 };
 
 // launch sites of the grouped GEMM (each is its own kernel symbol in profiles)
 enum : int {
@@ -24,8 +24,8 @@ enum : int {
     GEMM_STEP4 = 3        // step 4, accumulated into the FP64 diagonal block
 };
 
-// mode: arithmetic for GEMM_STEP35 / GEMM_STEP4 (CMP_*); tile: GEMM_TILE_64 or
-// GEMM_TILE_128 (the tile list must use the same size)
+// mode: arithmetic for GEMM_STEP35 / GEMM_STEP4 (CMP_*); tile: GEMM_TILE_32,
+// GEMM_TILE_64 or GEMM_TILE_128 (the tile list must use the same size)
 hipError_t launch_gemm(int role, int mode, int tile, const GemmProb *probs, const GemmTile *tiles, int ntiles,
                        hipStream_t st);
 hipError_t launch_gather(int f64, const MatDev *mats, const GatherTile *tiles, int ntiles, hipStream_t st);

@@ -49,8 +49,19 @@ struct Sweep {
     GemmProb *d_probs = nullptr;
     GemmTile *d_tiles = nullptr;
     GatherTile *d_gt = nullptr;
-    Range tri, norm, dt;
-    std::vector<Range> tri_rounds;  // pairs (T products, X products) per doubling round
+    // Diagonal-block inversion, normalisation and diagonal initialisation, in
+    // two parts: pro[0] for the supernodes of the levels above `split`,
+    // pro[1] for the rest.  In an unprofiled run pro[1] goes to a side stream
+    // forked from the run's stream and joined before level `split`, so that
+    // it overlaps the sweep of the upper levels, which leave most of the
+    // device idle.  split = 0: everything in pro[0], no fork.
+    struct Prologue {
+        Range tri, norm, dt;
+        std::vector<Range> tri_rounds;  // pairs (T products, X products) per doubling round
+    } pro[2];
+    int split = 0;
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     std::vector<Range> small, gat, g35, g4;
     SmallItem *d_small = nullptr;
     std::vector<double> lev_flops35, lev_flops4, lev_gather_elems;  // launches of the large supernodes
@@ -70,6 +81,9 @@ struct Sweep {
     ~Sweep() {
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (graph) (void)hipGraphDestroy(graph);
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+        if (ev_join) (void)hipEventDestroy(ev_join);
+        if (side) (void)hipStreamDestroy(side);
         (void)hipFree(d_mats);
         (void)hipFree(d_tri);
         (void)hipFree(d_probs);
@@ -163,16 +177,30 @@ selinv_status ensure_prec(selinv_handle h, int prec) {
     return SELINV_OK;
 }
 
+// launches with fewer 64x64 tiles than this use 32x32 tiles; with at least
+// kTile128From 128x128 tiles, 128x128 (measured on MI355X: the FP64 and FP32
+// products run faster on 64x64 tiles at every size of these workloads, the
+// split-BF16 products on 128x128 tiles once a launch has a few waves of them)
+constexpr double kTile32Below = 512;
+// levels at least this wide (in supernodes) start the part of the prologue
+// that runs beside the sweep of the levels above
+constexpr int kSplitWidth = 64;
+constexpr double kTile128From = 192;
+
 void add_tiles(std::vector<GemmTile> &tiles, int prob, int M, int N, int T) {
     for (int n0 = 0; n0 < N; n0 += T)
         for (int m0 = 0; m0 < M; m0 += T) tiles.push_back(GemmTile{prob, m0, n0, 0});
 }
 
-// Tiles of one GEMM launch over problems [first, probs.size()).  128x128
-// tiles when they still give a few waves of work over the 256 compute units
-// and waste little more of their area than 64x64 tiles would; 64x64
-// otherwise (small supernodes near the leaves).
-void emit_launch(const std::vector<GemmProb> &probs, size_t first, std::vector<GemmTile> &tiles, Range &r) {
+// Tiles of one GEMM launch over problems [first, probs.size()).  The output
+// tile is the largest that still gives the launch about two workgroups per
+// compute unit: a workgroup runs the whole k range of its tile, so a launch
+// with few tiles is bound by the length of that chain, and smaller tiles
+// spread it over more compute units.  128x128 tiles (allow128) only for
+// launches large enough to fill the device a few times over and wasting
+// little of their area.
+void emit_launch(const std::vector<GemmProb> &probs, size_t first, std::vector<GemmTile> &tiles, Range &r,
+                 bool allow128 = false) {
     double area = 0, t128 = 0, t64 = 0;
     for (size_t q = first; q < probs.size(); q++) {
         const double M = probs[q].M, N = probs[q].N;
@@ -181,7 +209,9 @@ void emit_launch(const std::vector<GemmProb> &probs, size_t first, std::vector<G
         t64 += std::ceil(M / 64) * std::ceil(N / 64);
     }
     r.tile = GEMM_TILE_64;
-    if (t128 > 0 && t128 >= 192 && area / (t128 * 128 * 128) >= 0.75 * area / (t64 * 64 * 64))
+    if (t64 < kTile32Below)
+        r.tile = GEMM_TILE_32;
+    else if (allow128 && t128 >= kTile128From && area / (t128 * 128 * 128) >= 0.75 * area / (t64 * 64 * 64))
         r.tile = GEMM_TILE_128;
     r.off = tiles.size();
     for (size_t q = first; q < probs.size(); q++) add_tiles(tiles, (int)q, probs[q].M, probs[q].N, r.tile);
@@ -303,87 +333,127 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, int sweep_mo
         mats.push_back(m);
         depth = std::max(depth, h->P.nlevels);
     }
-    // diagonal-block inversion: 64x64 diagonal sub-blocks, then recursive
-    // doubling.  Round h joins neighbouring inverted blocks A (h x h, at o) and
-    // B (h' x h', at o + h) of every supernode wider than h:
-    //   L: X21 = -B^{-1} (C A^{-1}),   C = L(o+h.., o..)
-    //   U: X12 = -A^{-1} (C B^{-1}),   C = U(o.., o+h..)
-    // the inner products go to scratch (tl / tu) in a first launch, the outer
-    // ones into L^{-1} / U^{-1} in a second.
-    for (auto h : hs)
-        for (int32_t K = 0; K < h->P.ns; K++) {
-            const SnRec &r = h->sn[K];
-            for (int j0 = 0; j0 < r.s; j0 += 64)
-                tri.push_back(TriItem{h->d_diag + r.off_d, h->d_Linv + r.off_d, h->d_Uinv + r.off_d, r.s, j0});
-        }
-    S->tri.count = (int)tri.size();
-    for (int hb = 64;; hb *= 2) {
-        bool any = false;
+    // Split of the prologue: the first level (below the root) that holds at
+    // least kSplitWidth supernodes over the batch starts pro[1].
+    {
+        std::vector<int> width(depth, 0);
         for (auto h : hs)
-            for (const SnRec &r : h->sn) any |= r.s > hb;
-        if (!any) break;
-        for (int part = 0; part < 2; part++) {
-            size_t first0 = probs.size();
-            for (auto h : hs)
-                for (const SnRec &r : h->sn) {
-                    if (r.s <= hb) continue;
-                    const int64_t s_ = r.s;
-                    const double *D = h->d_diag + r.off_d;
-                    double *Li = h->d_Linv + r.off_d, *Ui = h->d_Uinv + r.off_d;
-                    for (int o = 0; o + hb < r.s; o += 2 * hb) {
-                        const int hp = std::min(hb, r.s - o - hb);
-                        double *TL = h->d_tl + r.off_d + (int64_t)o * hb;
-                        double *TU = h->d_tu + r.off_d + (int64_t)o * hb;
-                        const int64_t oo = o + (int64_t)o * s_, ob = (o + hb) + (int64_t)(o + hb) * s_;
-                        const int64_t lo_off = (o + hb) + (int64_t)o * s_, up_off = o + (int64_t)(o + hb) * s_;
-                        if (part == 0) {
-                            add_prob(probs, D + lo_off, 0, r.s, Li + oo, 0, r.s, TL, hp, nullptr, 1, hp, hb, hb, 1.0,
-                                     0.0, &X, 8, 8);
-                            add_prob(probs, D + up_off, 0, r.s, Ui + ob, 0, r.s, TU, hb, nullptr, 1, hb, hp, hp, 1.0,
-                                     0.0, &X, 8, 8);
-                        } else {
-                            add_prob(probs, Li + ob, 0, r.s, TL, 0, hp, Li + lo_off, r.s, nullptr, 1, hp, hb, hp, -1.0,
-                                     0.0, &X, 8, 8);
-                            add_prob(probs, Ui + oo, 0, r.s, TU, 0, hb, Ui + up_off, r.s, nullptr, 1, hb, hp, hb, -1.0,
-                                     0.0, &X, 8, 8);
+            for (int d = 0; d < h->P.nlevels; d++) width[d] += (int)h->P.levels[d].size();
+        S->split = 0;
+        for (int d = 1; d < depth; d++)
+            if (width[d] >= kSplitWidth) {
+                S->split = d;
+                break;
+            }
+    }
+    std::vector<std::vector<char>> part(hs.size());
+    for (size_t mi = 0; mi < hs.size(); mi++) {
+        part[mi].assign(hs[mi]->P.ns, 0);
+        for (int d = 0; d < hs[mi]->P.nlevels; d++)
+            for (int32_t K : hs[mi]->P.levels[d]) part[mi][K] = S->split > 0 && d >= S->split;
+    }
+    for (int pp = 0; pp < 2; pp++) {
+        Sweep::Prologue &PR = S->pro[pp];
+        // diagonal-block inversion: 64x64 diagonal sub-blocks, then recursive
+        // doubling.  Round h joins neighbouring inverted blocks A (h x h, at o)
+        // and B (h' x h', at o + h) of every supernode wider than h:
+        //   L: X21 = -B^{-1} (C A^{-1}),   C = L(o+h.., o..)
+        //   U: X12 = -A^{-1} (C B^{-1}),   C = U(o.., o+h..)
+        // the inner products go to scratch (tl / tu) in a first launch, the
+        // outer ones into L^{-1} / U^{-1} in a second.
+        PR.tri.off = tri.size();
+        for (size_t mi = 0; mi < hs.size(); mi++) {
+            selinv_handle h = hs[mi];
+            for (int32_t K = 0; K < h->P.ns; K++) {
+                if (part[mi][K] != pp) continue;
+                const SnRec &r = h->sn[K];
+                for (int j0 = 0; j0 < r.s; j0 += 64)
+                    tri.push_back(TriItem{h->d_diag + r.off_d, h->d_Linv + r.off_d, h->d_Uinv + r.off_d, r.s, j0});
+            }
+        }
+        PR.tri.count = (int)(tri.size() - PR.tri.off);
+        for (int hb = 64;; hb *= 2) {
+            bool any = false;
+            for (size_t mi = 0; mi < hs.size(); mi++)
+                for (int32_t K = 0; K < hs[mi]->P.ns; K++) any |= part[mi][K] == pp && hs[mi]->sn[K].s > hb;
+            if (!any) break;
+            for (int half = 0; half < 2; half++) {
+                size_t first0 = probs.size();
+                for (size_t mi = 0; mi < hs.size(); mi++) {
+                    selinv_handle h = hs[mi];
+                    for (int32_t K = 0; K < h->P.ns; K++) {
+                        const SnRec &r = h->sn[K];
+                        if (part[mi][K] != pp || r.s <= hb) continue;
+                        const int64_t s_ = r.s;
+                        const double *D = h->d_diag + r.off_d;
+                        double *Li = h->d_Linv + r.off_d, *Ui = h->d_Uinv + r.off_d;
+                        for (int o = 0; o + hb < r.s; o += 2 * hb) {
+                            const int hp = std::min(hb, r.s - o - hb);
+                            double *TL = h->d_tl + r.off_d + (int64_t)o * hb;
+                            double *TU = h->d_tu + r.off_d + (int64_t)o * hb;
+                            const int64_t oo = o + (int64_t)o * s_, ob = (o + hb) + (int64_t)(o + hb) * s_;
+                            const int64_t lo_off = (o + hb) + (int64_t)o * s_, up_off = o + (int64_t)(o + hb) * s_;
+                            if (half == 0) {
+                                add_prob(probs, D + lo_off, 0, r.s, Li + oo, 0, r.s, TL, hp, nullptr, 1, hp, hb, hb,
+                                         1.0, 0.0, &X, 8, 8);
+                                add_prob(probs, D + up_off, 0, r.s, Ui + ob, 0, r.s, TU, hb, nullptr, 1, hb, hp, hp,
+                                         1.0, 0.0, &X, 8, 8);
+                            } else {
+                                add_prob(probs, Li + ob, 0, r.s, TL, 0, hp, Li + lo_off, r.s, nullptr, 1, hp, hb, hp,
+                                         -1.0, 0.0, &X, 8, 8);
+                                add_prob(probs, Ui + oo, 0, r.s, TU, 0, hb, Ui + up_off, r.s, nullptr, 1, hb, hp, hb,
+                                         -1.0, 0.0, &X, 8, 8);
+                            }
                         }
                     }
                 }
-            Range rr;
-            emit_launch(probs, first0, tiles, rr);
-            S->tri_rounds.push_back(rr);
+                Range rr;
+                emit_launch(probs, first0, tiles, rr);
+                PR.tri_rounds.push_back(rr);
+            }
         }
+        // normalisation (FP64 arithmetic, output in the run's precision)
+        size_t first = probs.size();
+        for (size_t mi = 0; mi < hs.size(); mi++) {
+            selinv_handle h = hs[mi];
+            const PrecBufs &b = h->pb[prec];
+            for (int32_t K = 0; K < h->P.ns; K++) {
+                if (part[mi][K] != pp) continue;
+                const SnRec &r = h->sn[K];
+                char *Lh = (char *)b.Lh + r.off_l * e;
+                char *Uh = (char *)b.Uh + r.off_u * e;
+                add_prob(probs, h->d_lpan + r.off_l, 0, r.cl, h->d_Linv + r.off_d, 0, r.s, Lh, r.cl, nullptr, 1, r.cl,
+                         r.s, r.s, 1.0, 0.0, &X, 8, e);
+                add_prob(probs, h->d_upan + r.off_u, 0, r.cu, h->d_Uinv + r.off_d, 1, r.s, Uh, r.cu, nullptr, 1, r.cu,
+                         r.s, r.s, 1.0, 0.0, &X, 8, e);
+            }
+        }
+        // In the FP64 form the normalisation and the diagonal initialisation
+        // run on the same kernel and share one launch; the mixed forms write
+        // FP32 normalised panels and need a second kernel for the FP64
+        // diagonal.
+        if (prec != SELINV_FP64) {
+            emit_launch(probs, first, tiles, PR.norm);
+            first = probs.size();
+        }
+        for (size_t mi = 0; mi < hs.size(); mi++) {
+            selinv_handle h = hs[mi];
+            const PrecBufs &b = h->pb[prec];
+            for (int32_t K = 0; K < h->P.ns; K++) {
+                if (part[mi][K] != pp) continue;
+                const SnRec &r = h->sn[K];
+                add_prob(probs, h->d_Linv + r.off_d, 1, r.s, h->d_Uinv + r.off_d, 1, r.s, b.Zd + r.off_d, r.s,
+                         nullptr, 1, r.s, r.s, r.s, 1.0, 0.0, &X, 8, 8);
+            }
+        }
+        emit_launch(probs, first, tiles, prec == SELINV_FP64 ? PR.norm : PR.dt);
     }
-    // normalisation (FP64 arithmetic, output in the run's precision)
+    if (S->split > 0) {
+        HIPCHK(err, hipStreamCreateWithFlags(&S->side, hipStreamNonBlocking), "create side stream");
+        HIPCHK(err, hipEventCreateWithFlags(&S->ev_fork, hipEventDisableTiming), "create event");
+        HIPCHK(err, hipEventCreateWithFlags(&S->ev_join, hipEventDisableTiming), "create event");
+    }
     size_t first = probs.size();
-    for (auto h : hs) {
-        const PrecBufs &b = h->pb[prec];
-        for (int32_t K = 0; K < h->P.ns; K++) {
-            const SnRec &r = h->sn[K];
-            char *Lh = (char *)b.Lh + r.off_l * e;
-            char *Uh = (char *)b.Uh + r.off_u * e;
-            add_prob(probs, h->d_lpan + r.off_l, 0, r.cl, h->d_Linv + r.off_d, 0, r.s, Lh,
-                                      r.cl, nullptr, 1, r.cl, r.s, r.s, 1.0, 0.0, &X, 8, e);
-            add_prob(probs, h->d_upan + r.off_u, 0, r.cu, h->d_Uinv + r.off_d, 1, r.s, Uh,
-                                      r.cu, nullptr, 1, r.cu, r.s, r.s, 1.0, 0.0, &X, 8, e);
-        }
-    }
-    // In the FP64 form the normalisation and the diagonal initialisation run
-    // on the same kernel and share one launch; the mixed forms write FP32
-    // normalised panels and need a second kernel for the FP64 diagonal.
-    if (prec != SELINV_FP64) {
-        emit_launch(probs, first, tiles, S->norm);
-        first = probs.size();
-    }
-    for (auto h : hs) {
-        const PrecBufs &b = h->pb[prec];
-        for (int32_t K = 0; K < h->P.ns; K++) {
-            const SnRec &r = h->sn[K];
-            add_prob(probs, h->d_Linv + r.off_d, 1, r.s, h->d_Uinv + r.off_d, 1, r.s,
-                                    b.Zd + r.off_d, r.s, nullptr, 1, r.s, r.s, r.s, 1.0, 0.0, &X, 8, 8);
-        }
-    }
-    emit_launch(probs, first, tiles, prec == SELINV_FP64 ? S->norm : S->dt);
     // supernode ids over the whole batch, and the product problems of each
     std::vector<int32_t> gbase(hs.size() + 1, 0);
     for (size_t mi = 0; mi < hs.size(); mi++) gbase[mi + 1] = gbase[mi] + hs[mi]->P.ns;
@@ -401,10 +471,20 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, int sweep_mo
     S->lev_small_elems.assign(depth, 0);
     S->lev_nsup.assign(depth, 0);
     S->lev_maxs.assign(depth, 0);
-    // a supernode whose gather and three products are single 64x64 tiles is
-    // handled whole by one workgroup of the fused small-supernode kernel
-    auto is_small = [](const SnRec &r) { return r.s <= 64 && r.cl <= 64 && r.cu <= 64; };
+    // A supernode whose gather and three products are single 64x64 tiles is
+    // handled whole by one workgroup of the fused small-supernode kernel, on
+    // the levels where every supernode is of that kind: the fused launch then
+    // replaces the three per-phase launches of the level.
+    auto small_dims = [](const SnRec &r) { return r.s <= 64 && r.cl <= 64 && r.cu <= 64; };
+    std::vector<char> level_small(depth, 1);
+    for (size_t mi = 0; mi < hs.size(); mi++)
+        for (int d = 0; d < hs[mi]->P.nlevels; d++)
+            for (int32_t K : hs[mi]->P.levels[d])
+                if (!small_dims(hs[mi]->sn[K])) level_small[d] = 0;
+    int cur_level = 0;
+    auto is_small = [&](const SnRec &r) { return level_small[cur_level] && small_dims(r); };
     for (int d = 0; d < depth; d++) {
+        cur_level = d;
         S->gat[d].off = gts.size();
         for (size_t mi = 0; mi < hs.size(); mi++) {
             selinv_handle h = hs[mi];
@@ -451,7 +531,7 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, int sweep_mo
                     (pass == 0 ? S->lev_flops35[d] : S->lev_small_flops[d]) += 4.0 * r.s * (double)r.cl * r.cu;
                 }
             }
-            if (pass == 0) emit_launch(probs, first, tiles, S->g35[d]);
+            if (pass == 0) emit_launch(probs, first, tiles, S->g35[d], mode_of(prec) == CMP_BF16X3);
         }
         // step 4
         for (int pass = 0; pass < 2; pass++) {
@@ -474,7 +554,7 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, int sweep_mo
                     (pass == 0 ? S->lev_flops4[d] : S->lev_small_flops[d]) += 2.0 * r.s * (double)r.s * r.cu;
                 }
             }
-            if (pass == 0) emit_launch(probs, first, tiles, S->g4[d]);
+            if (pass == 0) emit_launch(probs, first, tiles, S->g4[d], mode_of(prec) == CMP_BF16X3);
         }
         S->small[d].off = smalls.size();
         for (size_t mi = 0; mi < hs.size(); mi++) {
@@ -615,15 +695,42 @@ hipError_t launch_sweep(const Sweep &S, hipStream_t st, std::vector<hipEvent_t> 
     auto mark = [&](int i) {
         if (ev) (void)hipEventRecord((*ev)[i], st);
     };
+    // prologue parts: diagonal-block inversion (base blocks and doubling
+    // rounds), normalisation, diagonal initialisation
+    auto tri_part = [&](const Sweep::Prologue &P, hipStream_t s) -> hipError_t {
+        hipError_t e2;
+        if ((e2 = launch_tri_base(S.d_tri + P.tri.off, P.tri.count, s))) return e2;
+        for (const Range &r : P.tri_rounds)
+            if ((e2 = launch_gemm(GEMM_PRO_F64, CMP_F64, r.tile, S.d_probs, S.d_tiles + r.off, r.count, s)))
+                return e2;
+        return hipSuccess;
+    };
+    auto norm_part = [&](const Sweep::Prologue &P, hipStream_t s) -> hipError_t {
+        return launch_gemm(f64 ? GEMM_PRO_F64 : GEMM_PRO_F32OUT, CMP_F64, P.norm.tile, S.d_probs,
+                           S.d_tiles + P.norm.off, P.norm.count, s);
+    };
+    auto dt_part = [&](const Sweep::Prologue &P, hipStream_t s) -> hipError_t {
+        return launch_gemm(GEMM_PRO_F64, CMP_F64, P.dt.tile, S.d_probs, S.d_tiles + P.dt.off, P.dt.count, s);
+    };
+    const bool fork = S.split > 0 && ev == nullptr;
+    if (fork) {
+        if ((e = hipEventRecord(S.ev_fork, st))) return e;
+        if ((e = hipStreamWaitEvent(S.side, S.ev_fork, 0))) return e;
+        if ((e = tri_part(S.pro[1], S.side))) return e;
+        if ((e = norm_part(S.pro[1], S.side))) return e;
+        if ((e = dt_part(S.pro[1], S.side))) return e;
+        if ((e = hipEventRecord(S.ev_join, S.side))) return e;
+    }
+    const int nparts = (S.split > 0 && !fork) ? 2 : 1;
     mark(0);
-    if ((e = launch_tri_base(S.d_tri, S.tri.count, st))) return e;
-    for (const Range &r : S.tri_rounds)
-        if ((e = launch_gemm(GEMM_PRO_F64, CMP_F64, r.tile, S.d_probs, S.d_tiles + r.off, r.count, st))) return e;
+    for (int q = 0; q < nparts; q++)
+        if ((e = tri_part(S.pro[q], st))) return e;
     mark(1);
-    if ((e = launch_gemm(f64 ? GEMM_PRO_F64 : GEMM_PRO_F32OUT, CMP_F64, S.norm.tile, S.d_probs,
-                         S.d_tiles + S.norm.off, S.norm.count, st))) return e;
+    for (int q = 0; q < nparts; q++)
+        if ((e = norm_part(S.pro[q], st))) return e;
     mark(2);
-    if ((e = launch_gemm(GEMM_PRO_F64, CMP_F64, S.dt.tile, S.d_probs, S.d_tiles + S.dt.off, S.dt.count, st))) return e;
+    for (int q = 0; q < nparts; q++)
+        if ((e = dt_part(S.pro[q], st))) return e;
     mark(3);
     if (S.persistent) {
         PersistArgs a;
@@ -635,11 +742,13 @@ hipError_t launch_sweep(const Sweep &S, hipStream_t st, std::vector<hipEvent_t> 
         a.err = S.d_cnt + S.ncnt + 1;
         a.mats = S.d_mats;
         a.probs = S.d_probs;
+        if (fork && (e = hipStreamWaitEvent(st, S.ev_join, 0))) return e;
         if ((e = launch_persist(mode, a, S.ncnt, S.grid, st))) return e;
         for (size_t d = 0; d < 4 * S.gat.size(); d++) mark(4 + d);
         return hipSuccess;
     }
     for (size_t d = 0; d < S.gat.size(); d++) {
+        if (fork && (int)d == S.split && (e = hipStreamWaitEvent(st, S.ev_join, 0))) return e;
         if ((e = launch_small(mode, S.d_mats, S.d_probs, S.d_small + S.small[d].off, S.small[d].count, st)))
             return e;
         mark(4 + 4 * d);
