@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--sweep", default="auto", choices=["auto", "levels", "persistent"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="bound on the oracle's CPU time")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (for scaling HBM counters) and exit")
     return ap.parse_args()
 
 
@@ -152,6 +154,61 @@ def roofline(ph, prec):
             "mean_launch_ms": ms, "flops_per_launch": work}
 
 
+def source_digest():
+    """SHA-256 over the library's kernel and runtime sources (sorted by name)."""
+    import hashlib
+    d = hashlib.sha256()
+    src = os.path.join(ROOT, "paper_1708_04539_amd", "csrc")
+    for name in sorted(os.listdir(src)):
+        if name.endswith((".hip", ".hpp", ".cpp")):
+            d.update(name.encode())
+            with open(os.path.join(src, name), "rb") as f:
+                d.update(f.read())
+    return d.hexdigest()
+
+
+def load_traffic(config, prec, kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    profiles/traffic_<config>_<prec>.md (FETCH_SIZE and WRITE_SIZE per
+    dispatch, scaled by a plain copy of known size).  None when there is no
+    summary for this kernel or the sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{config}_{prec}.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("- ") and ": " in line:
+                k, v = line[2:].split(": ", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    try:
+        if vals.get("kernel") != kernel or vals.get("source_sha256") != source_digest():
+            return None
+        return float(vals["fetch_bytes_per_launch"]) + float(vals["write_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration(mib):
+    """A plain device-to-device copy of `mib` MiB, timed; the reference for
+    scaling the FETCH_SIZE / WRITE_SIZE counters of the sweep kernels."""
+    import torch
+    n = mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "ms": ms,
+                      "GBps_read_plus_write": 2 * n * 8 / ms / 1e6}))
+
+
 def cpu_baseline(w, budget_s):
     import numpy as np
     import oracle
@@ -174,6 +231,9 @@ def cpu_baseline(w, budget_s):
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design note, "
@@ -215,6 +275,9 @@ def main():
 
     ph = phase_profile(s, prec, stream)
     roof = roofline(ph, prec)
+    traffic = load_traffic(args.config, prec, roof["kernel"])
+    roof["traffic"] = traffic
+    roof["traffic_unit"] = "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)"
 
     res = {
         "metric": "selinv GFLOP/s & ms/matrix, mixed vs FP64 on 1 MI355X at stated max rel err",
