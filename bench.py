@@ -121,7 +121,7 @@ def phase_profile(s, prec, stream, reps=5):
 KERNEL_SYMBOL = {
     # (class, precision, tile) -> kernel symbol as rocprofv3 prints it
     "gemm35": "selinv::gemm_v2<{mode}, {t}, {t}, {T}, {T}, 1>",
-    "gemm4": "selinv::gemm_v2<{mode}, {t}, {t}, {T}, double, 2>",
+    "gemm4": "selinv::step4_gather<{mode}, {t}, {t}, {T}>",
     "gather": "selinv::gather_kernel<{T}>",
     "small": "selinv::small_kernel<{mode}>",
 }

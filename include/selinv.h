@@ -197,19 +197,23 @@ selinv_status selinv_check_plan(selinv_handle h, int64_t *mismatches);
  * normalisation (and, in the FP64 form, the diagonal initialisation), ms[2]
  * diagonal initialisation of the mixed forms, then for every level d
  * ms[3+4d] fused steps 3-5 of the level's small supernodes (s, |R_L|,
- * |R_U| <= 64), ms[4+4d] gather of the others, ms[5+4d] their products of
- * steps 3 and 5, ms[6+4d] their product of step 4.  count = number of doubles
- * the caller provides (3 + 4 * nlevels covers all). */
+ * |R_U| <= 64), ms[4+4d] gather of the others (0 when it runs in the step-4
+ * launch of level d-1), ms[5+4d] their products of steps 3 and 5, ms[6+4d]
+ * their product of step 4 together with the gather of level d+1 when that is
+ * fused into it.  count = number of doubles the caller provides (3 + 4 *
+ * nlevels covers all). */
 selinv_status selinv_set_profiling(selinv_handle h, int32_t on);
 selinv_status selinv_timings(selinv_handle h, double *ms, int32_t count);
 
-/* Work of one level of the last run's sweep (stats: 13 doubles): [0]
+/* Work of one level of the last run's sweep (stats: 14 doubles): [0]
  * supernodes, [1] widest supernode; for the launches of the large supernodes
  * [2] flops of steps 3+5, [3] flops of step 4, [4] entries of G gathered, [5]
  * gather tiles, [6] product tiles of steps 3+5, [7] of step 4, [8] and [9] the
  * output tile edge (32, 64 or 128) of those two product launches; for the fused
  * small-supernode launch [10] supernodes, [11] flops of steps 3-5, [12]
- * entries of G gathered. */
+ * entries of G gathered; [13] 1 when the level's gather tiles run in the
+ * step-4 launch of the level above (the parent's step-4 product then writes
+ * its diagonal block into the children's G), so that [5] is 0. */
 selinv_status selinv_level_stats(selinv_handle h, int32_t level, double *stats);
 
 /* Message of the last failure on handle h; with h == NULL, of the last failed

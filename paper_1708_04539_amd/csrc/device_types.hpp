@@ -25,11 +25,21 @@ struct MatDev {
     const void *ZL;    // A^{-T}(R_L, K) panels, FP64 or FP32
     const void *ZU;    // A^{-T}(K, R_U)^T panels, FP64 or FP32
     void *G;           // gather workspace, FP64 or FP32
+    // children of every supernode (kids[kids_ptr[P] .. kids_ptr[P+1])), and
+    // for a child K of P the positions of P's columns in R_L(K) and R_U(K):
+    // push_pos[push_off[K] + r] = a with R_L(K)[a] = first(P) + r (or -1),
+    // push_pos[push_off[K] + s_P + c] = b with R_U(K)[b] = first(P) + c (or -1)
+    const int32_t *kids_ptr, *kids;
+    const int64_t *push_off;
+    const int32_t *push_pos;
 };
 
-// gather: tile of G_K rows [a0, a0+64) x columns [b0, b0+64)
+// gather: tile of G_K rows [a0, a0+64) x columns [b0, b0+64); entries from
+// the diagonal block of supernode `skip` (the parent, when its step-4 product
+// pushes them, see GemmProb) are left to that product; -1: none skipped
 struct GatherTile {
     int32_t mat, K, a0, b0;
+    int32_t skip, pad;
 };
 
 // C = alpha * op(A) op(B) + beta * Cin, column-major, op = N (0) or T (1)
@@ -41,7 +51,10 @@ struct GemmProb {
     int32_t M, N, K;
     int32_t lda, ldb, ldc, ldcin;
     int32_t opA, opB;
-    int32_t pad;
+    // step-4 product of supernode push_sn of matrix push_mat (-1: none): the
+    // final entries of A^{-T}(P,P) are also written into G of P's children,
+    // whose gather skips them
+    int32_t push_sn, push_mat;
     double alpha, beta;
 };
 

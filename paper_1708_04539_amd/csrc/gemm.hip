@@ -34,11 +34,22 @@ namespace selinv {
 // ROLE only names the launch site in profiles (0: triangular inversion,
 // normalisation and diagonal initialisation; 1: products of steps 3 and 5;
 // 2: product of step 4); the code is the same.
+// Workgroups are dispatched to the 8 XCDs round robin (workgroup b to XCD
+// b mod 8), and each XCD has its own L2.  The tile list is ordered row-block
+// major, so tiles that share a strip of op(A) are neighbours; the remap gives
+// each XCD one contiguous range of the list, so that such tiles run on the
+// same XCD at about the same time and share the strip in its L2.
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+    constexpr int X = 8;
+    const int q = n / X, r = n % X, x = b % X, i = b / X;
+    return x * q + min(x, r) + i;
+}
+
 template <int MODE, int BM, int BN, typename TA, typename TC, int ROLE>
 __global__ __launch_bounds__(256) void gemm_v2(const GemmProb *__restrict__ probs,
                                                const GemmTile *__restrict__ tiles) {
     __shared__ Smem<MODE, BM, BN> sm;
-    const GemmTile tl = tiles[blockIdx.x];
+    const GemmTile tl = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     // only the step-4 product accumulates into an input matrix
     gemm_tile<MODE, BM, BN, TA, TC, ROLE == 2>(probs[tl.prob], tl.m0, tl.n0, sm);
 }
@@ -51,6 +62,60 @@ static void launch_mode(int tile, const GemmProb *probs, const GemmTile *tiles, 
         hipLaunchKernelGGL((gemm_v2<MODE, 64, 64, TA, TC, ROLE>), dim3(ntiles), dim3(256), 0, st, probs, tiles);
     else
         hipLaunchKernelGGL((gemm_v2<MODE, 32, 32, TA, TC, ROLE>), dim3(ntiles), dim3(256), 0, st, probs, tiles);
+}
+
+// Step-4 products of one level (pushing A^{-T}(P,P) into the children's G)
+// and, in the same launch, the gather tiles of the next level (which skip
+// those entries): workgroups [0, ntiles) run product tiles, the rest gather
+// tiles.  The two sets write disjoint entries of G.
+template <int MODE, int BM, int BN, typename TA>
+__global__ __launch_bounds__(256) void step4_gather(const GemmProb *__restrict__ probs,
+                                                    const GemmTile *__restrict__ tiles, int ntiles,
+                                                    const MatDev *__restrict__ mats,
+                                                    const GatherTile *__restrict__ gtiles) {
+    union Shared {
+        Smem<MODE, BM, BN> g;
+        GatherSmem<TA> t;
+    };
+    __shared__ Shared sm;
+    const int b = blockIdx.x;
+    if (b < ntiles) {
+        const GemmTile tl = tiles[xcd_tile(b, ntiles)];
+        gemm_tile<MODE, BM, BN, TA, double, true, true>(probs[tl.prob], tl.m0, tl.n0, sm.g, mats);
+    } else {
+        const GatherTile gt = gtiles[b - ntiles];
+        gather_tile<TA>(mats[gt.mat], gt.K, gt.a0, gt.b0, sm.t, gt.skip);
+    }
+}
+
+template <int MODE, typename TA>
+static void launch_s4g(int tile, const GemmProb *probs, const GemmTile *tiles, int ntiles, const MatDev *mats,
+                       const GatherTile *gtiles, int ngtiles, hipStream_t st) {
+    const dim3 grid(ntiles + ngtiles);
+    if (tile == GEMM_TILE_128)
+        hipLaunchKernelGGL((step4_gather<MODE, 128, 128, TA>), grid, dim3(256), 0, st, probs, tiles, ntiles, mats,
+                           gtiles);
+    else if (tile == GEMM_TILE_64)
+        hipLaunchKernelGGL((step4_gather<MODE, 64, 64, TA>), grid, dim3(256), 0, st, probs, tiles, ntiles, mats,
+                           gtiles);
+    else
+        hipLaunchKernelGGL((step4_gather<MODE, 32, 32, TA>), grid, dim3(256), 0, st, probs, tiles, ntiles, mats,
+                           gtiles);
+}
+
+hipError_t launch_step4_gather(int mode, int tile, const GemmProb *probs, const GemmTile *tiles, int ntiles,
+                               const MatDev *mats, const GatherTile *gtiles, int ngtiles, hipStream_t st) {
+    if (ntiles + ngtiles <= 0) return hipSuccess;
+    if (tile != GEMM_TILE_32 && tile != GEMM_TILE_64 && tile != GEMM_TILE_128) return hipErrorInvalidValue;
+    if (mode == CMP_F64)
+        launch_s4g<CMP_F64, double>(tile, probs, tiles, ntiles, mats, gtiles, ngtiles, st);
+    else if (mode == CMP_F32)
+        launch_s4g<CMP_F32, float>(tile, probs, tiles, ntiles, mats, gtiles, ngtiles, st);
+    else if (mode == CMP_BF16X3)
+        launch_s4g<CMP_BF16X3, float>(tile, probs, tiles, ntiles, mats, gtiles, ngtiles, st);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
 }
 
 hipError_t launch_gemm(int role, int mode, int tile, const GemmProb *probs, const GemmTile *tiles, int ntiles,

@@ -182,7 +182,7 @@ __global__ __launch_bounds__(256) void gather_kernel(const MatDev *__restrict__ 
                                                      const GatherTile *__restrict__ tiles) {
     __shared__ GatherSmem<T> sm;
     const GatherTile tl = tiles[blockIdx.x];
-    gather_tile<T>(mats[tl.mat], tl.K, tl.a0, tl.b0, sm);
+    gather_tile<T>(mats[tl.mat], tl.K, tl.a0, tl.b0, sm, tl.skip);
 }
 
 // ---------------------------------------------------------------------------

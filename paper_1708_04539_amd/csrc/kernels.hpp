@@ -29,6 +29,10 @@ enum : int {
 hipError_t launch_gemm(int role, int mode, int tile, const GemmProb *probs, const GemmTile *tiles, int ntiles,
                        hipStream_t st);
 hipError_t launch_gather(int f64, const MatDev *mats, const GatherTile *tiles, int ntiles, hipStream_t st);
+// step-4 product tiles of one level (pushing into the children's G) and the
+// next level's gather tiles in one launch (gemm.hip)
+hipError_t launch_step4_gather(int mode, int tile, const GemmProb *probs, const GemmTile *tiles, int ntiles,
+                               const MatDev *mats, const GatherTile *gtiles, int ngtiles, hipStream_t st);
 // gather + steps 3/5 + step 4 of small supernodes, one workgroup each (persist.hip)
 hipError_t launch_small(int mode, const MatDev *mats, const GemmProb *probs, const SmallItem *items, int count,
                         hipStream_t st);

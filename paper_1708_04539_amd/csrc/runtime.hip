@@ -63,6 +63,10 @@ struct Sweep {
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     std::vector<Range> small, gat, g35, g4;
+    // gather tiles of level d + 1 launched with the step-4 products of level
+    // d (fused[d + 1]); those products push A^{-T}(P,P) into the children's G
+    std::vector<Range> g4gat;
+    std::vector<char> fused;
     SmallItem *d_small = nullptr;
     std::vector<double> lev_flops35, lev_flops4, lev_gather_elems;  // launches of the large supernodes
     std::vector<double> lev_small_flops, lev_small_elems;          // the fused small-supernode launch
@@ -119,6 +123,12 @@ struct selinv_handle_s {
     SnRec *d_sn = nullptr;
     int32_t *d_supof = nullptr, *d_rl = nullptr, *d_ru = nullptr, *d_mapL = nullptr, *d_mapU = nullptr;
     int64_t *d_lcol = nullptr, *d_urow = nullptr, *d_aloc = nullptr;
+    // children lists and positions of the parent's columns in each child's
+    // R_L / R_U (see MatDev), for the push of A^{-T}(P,P) into the children's G
+    std::vector<int32_t> kids_ptr, kids, push_pos;
+    std::vector<int64_t> push_off;
+    int32_t *d_kids_ptr = nullptr, *d_kids = nullptr, *d_push_pos = nullptr;
+    int64_t *d_push_off = nullptr;
     PrecBufs pb[NPREC];
     std::unique_ptr<Sweep> sweep[NPREC];
     int last_prec = -1;
@@ -187,9 +197,11 @@ constexpr double kTile32Below = 512;
 constexpr int kSplitWidth = 64;
 constexpr double kTile128From = 192;
 
+// row-block major: the tiles of one strip of op(A) are neighbours in the
+// list (the GEMM kernel keeps neighbours on one XCD)
 void add_tiles(std::vector<GemmTile> &tiles, int prob, int M, int N, int T) {
-    for (int n0 = 0; n0 < N; n0 += T)
-        for (int m0 = 0; m0 < M; m0 += T) tiles.push_back(GemmTile{prob, m0, n0, 0});
+    for (int m0 = 0; m0 < M; m0 += T)
+        for (int n0 = 0; n0 < N; n0 += T) tiles.push_back(GemmTile{prob, m0, n0, 0});
 }
 
 // Tiles of one GEMM launch over problems [first, probs.size()).  The output
@@ -262,7 +274,8 @@ int add_prob(std::vector<GemmProb> &probs, const void *A, int opA, int lda,
     p.ldcin = std::max(ldcin, 1);
     p.opA = opA;
     p.opB = opB;
-    p.pad = 0;
+    p.push_sn = -1;
+    p.push_mat = -1;
     p.alpha = alpha;
     p.beta = beta;
     probs.push_back(p);
@@ -326,6 +339,10 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, int sweep_mo
         m.u_rowoff = h->d_urow;
         m.mapL = h->d_mapL;
         m.mapU = h->d_mapU;
+        m.kids_ptr = h->d_kids_ptr;
+        m.kids = h->d_kids;
+        m.push_off = h->d_push_off;
+        m.push_pos = h->d_push_pos;
         m.Zd = b.Zd;
         m.ZL = b.ZL;
         m.ZU = b.ZU;
@@ -483,6 +500,13 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, int sweep_mo
                 if (!small_dims(hs[mi]->sn[K])) level_small[d] = 0;
     int cur_level = 0;
     auto is_small = [&](const SnRec &r) { return level_small[cur_level] && small_dims(r); };
+    // The gather of a level runs in the step-4 launch of the level above when
+    // both use the per-phase launches: the parent's step-4 product writes its
+    // final diagonal block into the children's G, the gather tiles fill the
+    // rest.  One launch fewer per level.
+    S->fused.assign(depth, 0);
+    for (int d = 1; d < depth; d++) S->fused[d] = !level_small[d - 1] && !level_small[d];
+    S->g4gat.resize(depth);
     for (int d = 0; d < depth; d++) {
         cur_level = d;
         S->gat[d].off = gts.size();
@@ -492,8 +516,10 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, int sweep_mo
             for (int32_t K : h->P.levels[d]) {
                 const SnRec &r = h->sn[K];
                 if (!is_small(r)) {
-                    for (int b0 = 0; b0 < r.cu; b0 += 64)
-                        for (int a0 = 0; a0 < r.cl; a0 += 64) gts.push_back(GatherTile{(int32_t)mi, K, a0, b0});
+                    if (!S->fused[d])
+                        for (int b0 = 0; b0 < r.cu; b0 += 64)
+                            for (int a0 = 0; a0 < r.cl; a0 += 64)
+                                gts.push_back(GatherTile{(int32_t)mi, K, a0, b0, -1, 0});
                     S->lev_gather_elems[d] += (double)r.cl * r.cu;
                 } else {
                     S->lev_small_elems[d] += (double)r.cl * r.cu;
@@ -556,6 +582,30 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, int sweep_mo
             }
             if (pass == 0) emit_launch(probs, first, tiles, S->g4[d], mode_of(prec) == CMP_BF16X3);
         }
+        S->g4gat[d].off = gts.size();
+        if (d + 1 < depth && S->fused[d + 1]) {
+            for (size_t mi = 0; mi < hs.size(); mi++) {
+                selinv_handle h = hs[mi];
+                if (d + 1 >= h->P.nlevels) continue;
+                for (int32_t K : h->P.levels[d + 1]) {
+                    const SnRec &r = h->sn[K];
+                    const int32_t Pa = h->P.sparent[K];
+                    const int pg = Pa >= 0 ? prob_g4[gbase[mi] + Pa] : -1;
+                    // a parent without a step-4 product keeps its initial
+                    // diagonal block, which the gather reads as usual
+                    int32_t skip = -1;
+                    if (pg >= 0) {
+                        probs[pg].push_sn = Pa;
+                        probs[pg].push_mat = (int32_t)mi;
+                        skip = Pa;
+                    }
+                    for (int b0 = 0; b0 < r.cu; b0 += 64)
+                        for (int a0 = 0; a0 < r.cl; a0 += 64)
+                            gts.push_back(GatherTile{(int32_t)mi, K, a0, b0, skip, 0});
+                }
+            }
+        }
+        S->g4gat[d].count = (int)(gts.size() - S->g4gat[d].off);
         S->small[d].off = smalls.size();
         for (size_t mi = 0; mi < hs.size(); mi++) {
             selinv_handle h = hs[mi];
@@ -712,15 +762,9 @@ hipError_t launch_sweep(const Sweep &S, hipStream_t st, std::vector<hipEvent_t> 
     auto dt_part = [&](const Sweep::Prologue &P, hipStream_t s) -> hipError_t {
         return launch_gemm(GEMM_PRO_F64, CMP_F64, P.dt.tile, S.d_probs, S.d_tiles + P.dt.off, P.dt.count, s);
     };
+    // The side part is forked after the main part, so that the main part
+    // (needed first) does not share the device with it.
     const bool fork = S.split > 0 && ev == nullptr;
-    if (fork) {
-        if ((e = hipEventRecord(S.ev_fork, st))) return e;
-        if ((e = hipStreamWaitEvent(S.side, S.ev_fork, 0))) return e;
-        if ((e = tri_part(S.pro[1], S.side))) return e;
-        if ((e = norm_part(S.pro[1], S.side))) return e;
-        if ((e = dt_part(S.pro[1], S.side))) return e;
-        if ((e = hipEventRecord(S.ev_join, S.side))) return e;
-    }
     const int nparts = (S.split > 0 && !fork) ? 2 : 1;
     mark(0);
     for (int q = 0; q < nparts; q++)
@@ -732,6 +776,14 @@ hipError_t launch_sweep(const Sweep &S, hipStream_t st, std::vector<hipEvent_t> 
     for (int q = 0; q < nparts; q++)
         if ((e = dt_part(S.pro[q], st))) return e;
     mark(3);
+    if (fork) {
+        if ((e = hipEventRecord(S.ev_fork, st))) return e;
+        if ((e = hipStreamWaitEvent(S.side, S.ev_fork, 0))) return e;
+        if ((e = tri_part(S.pro[1], S.side))) return e;
+        if ((e = norm_part(S.pro[1], S.side))) return e;
+        if ((e = dt_part(S.pro[1], S.side))) return e;
+        if ((e = hipEventRecord(S.ev_join, S.side))) return e;
+    }
     if (S.persistent) {
         PersistArgs a;
         a.tasks = S.d_ptasks;
@@ -757,14 +809,52 @@ hipError_t launch_sweep(const Sweep &S, hipStream_t st, std::vector<hipEvent_t> 
         if ((e = launch_gemm(GEMM_STEP35, mode, S.g35[d].tile, S.d_probs, S.d_tiles + S.g35[d].off,
                              S.g35[d].count, st))) return e;
         mark(6 + 4 * d);
-        if ((e = launch_gemm(GEMM_STEP4, mode, S.g4[d].tile, S.d_probs, S.d_tiles + S.g4[d].off, S.g4[d].count,
-                             st))) return e;
+        if ((e = launch_step4_gather(mode, S.g4[d].tile, S.d_probs, S.d_tiles + S.g4[d].off, S.g4[d].count,
+                                     S.d_mats, S.d_gt + S.g4gat[d].off, S.g4gat[d].count, st)))
+            return e;
         mark(7 + 4 * d);
     }
     return hipSuccess;
 }
 
 bool valid_prec(int p) { return p >= 0 && p < NPREC; }
+
+// Children of every supernode, and for each child K of P the positions of
+// P's columns first(P) + r in R_L(K) and R_U(K) (-1 where absent).  Both
+// lists are sorted, so one merge walk each.
+void build_push_maps(const Plan &P, std::vector<int32_t> &kids_ptr, std::vector<int32_t> &kids,
+                     std::vector<int64_t> &push_off, std::vector<int32_t> &push_pos) {
+    kids_ptr.assign(P.ns + 1, 0);
+    for (int32_t K = 0; K < P.ns; K++)
+        if (P.sparent[K] >= 0) kids_ptr[P.sparent[K] + 1]++;
+    for (int32_t K = 0; K < P.ns; K++) kids_ptr[K + 1] += kids_ptr[K];
+    kids.assign(kids_ptr[P.ns], 0);
+    std::vector<int32_t> fill(kids_ptr.begin(), kids_ptr.end() - 1);
+    for (int32_t K = 0; K < P.ns; K++)
+        if (P.sparent[K] >= 0) kids[fill[P.sparent[K]]++] = K;
+    push_off.assign(P.ns, -1);
+    int64_t tot = 0;
+    for (int32_t K = 0; K < P.ns; K++)
+        if (P.sparent[K] >= 0) {
+            push_off[K] = tot;
+            tot += 2 * (int64_t)P.width(P.sparent[K]);
+        }
+    push_pos.assign(tot, -1);
+    for (int32_t K = 0; K < P.ns; K++) {
+        const int32_t Pa = P.sparent[K];
+        if (Pa < 0) continue;
+        const int32_t f = P.xsup[Pa], sP = P.width(Pa);
+        int32_t *posL = push_pos.data() + push_off[K], *posU = posL + sP;
+        for (int64_t a = P.rl_ptr[K]; a < P.rl_ptr[K + 1]; a++) {
+            const int32_t r = P.rl[a] - f;
+            if (r >= 0 && r < sP) posL[r] = (int32_t)(a - P.rl_ptr[K]);
+        }
+        for (int64_t b = P.ru_ptr[K]; b < P.ru_ptr[K + 1]; b++) {
+            const int32_t c = P.ru[b] - f;
+            if (c >= 0 && c < sP) posU[c] = (int32_t)(b - P.ru_ptr[K]);
+        }
+    }
+}
 
 }  // namespace
 
@@ -834,6 +924,13 @@ selinv_status selinv_analyze(int64_t n, const int64_t *colptr, const int32_t *ro
         r.g_off = h->g_elems;
         h->g_elems += (int64_t)r.cl * r.cu;
     }
+    try {
+        build_push_maps(P, h->kids_ptr, h->kids, h->push_off, h->push_pos);
+    } catch (const std::bad_alloc &) {
+        g_analyze_err = "host allocation failed in analyze";
+        delete h;
+        return SELINV_E_NOMEM;
+    }
     *out = h;
     return SELINV_OK;
 }
@@ -875,6 +972,10 @@ selinv_status selinv_factor(selinv_handle h, const double *values) {
         HIPCHK(h->err, upload(&h->d_lcol, P.l_coloff), "upload l_coloff");
         HIPCHK(h->err, upload(&h->d_urow, P.u_rowoff), "upload u_rowoff");
         HIPCHK(h->err, upload(&h->d_aloc, P.a_loc), "upload a_loc");
+        HIPCHK(h->err, upload(&h->d_kids_ptr, h->kids_ptr), "upload children");
+        HIPCHK(h->err, upload(&h->d_kids, h->kids), "upload children");
+        HIPCHK(h->err, upload(&h->d_push_off, h->push_off), "upload push maps");
+        HIPCHK(h->err, upload(&h->d_push_pos, h->push_pos), "upload push maps");
     }
     if (P.tot_d) HIPCHK(h->err, hipMemcpy(h->d_diag, F.d.data(), P.tot_d * 8, hipMemcpyHostToDevice), "H2D diag");
     if (P.tot_l) HIPCHK(h->err, hipMemcpy(h->d_lpan, F.l.data(), P.tot_l * 8, hipMemcpyHostToDevice), "H2D lpan");
@@ -1029,6 +1130,7 @@ selinv_status selinv_level_stats(selinv_handle h, int32_t level, double *stats) 
     stats[10] = S.small[level].count;
     stats[11] = S.lev_small_flops[level];
     stats[12] = S.lev_small_elems[level];
+    stats[13] = S.fused[level];
     return SELINV_OK;
 }
 
@@ -1167,6 +1269,35 @@ selinv_status selinv_structure(selinv_handle h, int32_t *perm_out, int32_t *xsup
 selinv_status selinv_check_plan(selinv_handle h, int64_t *mismatches) {
     if (!h || !mismatches) return SELINV_E_INVALID_ARG;
     *mismatches = check_gather_maps(h->P, h->err);
+    // push maps: every position of a parent column found in a child's R_L /
+    // R_U holds that column, and every such column has a position
+    const Plan &P = h->P;
+    int64_t bad = 0;
+    for (int32_t K = 0; K < P.ns; K++) {
+        const int32_t Pa = P.sparent[K];
+        if (Pa < 0) continue;
+        const int32_t f = P.xsup[Pa], sP = P.width(Pa);
+        const int32_t *posL = h->push_pos.data() + h->push_off[K], *posU = posL + sP;
+        int64_t inL = 0, inU = 0;
+        for (int64_t a = P.rl_ptr[K]; a < P.rl_ptr[K + 1]; a++) inL += P.rl[a] >= f && P.rl[a] < f + sP;
+        for (int64_t b = P.ru_ptr[K]; b < P.ru_ptr[K + 1]; b++) inU += P.ru[b] >= f && P.ru[b] < f + sP;
+        for (int32_t r = 0; r < sP; r++) {
+            if (posL[r] >= 0) {
+                inL--;
+                bad += posL[r] >= P.cl(K) || P.rl[P.rl_ptr[K] + posL[r]] != f + r;
+            }
+            if (posU[r] >= 0) {
+                inU--;
+                bad += posU[r] >= P.cu(K) || P.ru[P.ru_ptr[K] + posU[r]] != f + r;
+            }
+        }
+        bad += (inL != 0) + (inU != 0);
+    }
+    for (int32_t Q = 0; Q < P.ns; Q++)
+        for (int32_t q = h->kids_ptr[Q]; q < h->kids_ptr[Q + 1]; q++) bad += P.sparent[h->kids[q]] != Q;
+    bad += h->kids_ptr[P.ns] != (int32_t)std::count_if(P.sparent.begin(), P.sparent.end(), [](int32_t x) { return x >= 0; });
+    if (bad && h->err.empty()) h->err = "push maps inconsistent with R_L / R_U";
+    *mismatches += bad;
     return SELINV_OK;
 }
 
@@ -1206,7 +1337,8 @@ void selinv_destroy(selinv_handle h) {
     for (void *q : {(void *)h->d_diag, (void *)h->d_lpan, (void *)h->d_upan, (void *)h->d_Linv, (void *)h->d_Uinv,
                     (void *)h->d_tl, (void *)h->d_tu,
                     (void *)h->d_sn, (void *)h->d_supof, (void *)h->d_rl, (void *)h->d_ru, (void *)h->d_mapL,
-                    (void *)h->d_mapU, (void *)h->d_lcol, (void *)h->d_urow, (void *)h->d_aloc})
+                    (void *)h->d_mapU, (void *)h->d_lcol, (void *)h->d_urow, (void *)h->d_aloc,
+                    (void *)h->d_kids_ptr, (void *)h->d_kids, (void *)h->d_push_off, (void *)h->d_push_pos})
         (void)hipFree(q);
     for (auto e : h->events) (void)hipEventDestroy(e);
     if (h->own_stream) (void)hipStreamDestroy(h->own_stream);

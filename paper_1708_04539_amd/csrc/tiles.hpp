@@ -76,9 +76,13 @@ struct Smem<CMP_BF16X3, BM, BN, BK> {
 // when staged into LDS, so that no load is tied to a branch.
 // CIN: the problem may carry an input matrix (beta Cin); without it Cin is
 // ignored and its registers are not reserved.
-template <int MODE, int BM, int BN, typename TA, typename TC, bool CIN, int BK, int OPA, int OPB>
+// PUSH: a step-4 product with push_sn >= 0 also writes its final entries of
+// A^{-T}(P,P) into G of each child of P (converted to the storage type TG,
+// as the gather would), so that the children's gather can run beside it.
+template <int MODE, int BM, int BN, typename TA, typename TC, bool CIN, int BK, int OPA, int OPB, bool PUSH,
+          typename TG>
 __device__ __forceinline__ void gemm_tile_op(const GemmProb &p, const int m0, const int n0,
-                                             Smem<MODE, BM, BN, BK> &sm) {
+                                             Smem<MODE, BM, BN, BK> &sm, const MatDev *mats) {
     typedef typename Mode<MODE>::T T;
     typedef typename Mode<MODE>::Acc Acc;
     static_assert(MODE != CMP_BF16X3 || BK % 32 == 0, "split-BF16 chunks are multiples of 32");
@@ -268,25 +272,61 @@ __device__ __forceinline__ void gemm_tile_op(const GemmProb &p, const int m0, co
                 double r = alpha * (double)acc[i][j][v];
                 if (has_cin) r += beta * cin[j][v];
                 C[gm + (int64_t)gn * ldc] = (TC)r;
+                if constexpr (PUSH) acc[i][j][v] = (TC)r;  // the stored value, for the push below
             }
+    }
+    if constexpr (PUSH) {
+        if (p.push_sn >= 0) {
+            const MatDev &Md = mats[p.push_mat];
+            const SELINV_GLOBAL SnRec *sn = gptr(Md.sn);
+            const SELINV_GLOBAL int32_t *kp = gptr(Md.kids_ptr);
+            const SELINV_GLOBAL int32_t *kids = gptr(Md.kids);
+            const int P = p.push_sn, sP = M;  // A^{-T}(P,P) is M x M
+            const int q1 = kp[P + 1];
+            for (int q = kp[P]; q < q1; q++) {
+                const int32_t K = kids[q];
+                const SELINV_GLOBAL int32_t *posL = gptr(Md.push_pos) + gptr(Md.push_off)[K];
+                const SELINV_GLOBAL int32_t *posU = posL + sP;
+                const int64_t clK = sn[K].cl;
+                SELINV_GLOBAL TG *G = gptr_w((TG *)Md.G) + sn[K].g_off;
+#pragma unroll
+                for (int i = 0; i < TM; i++) {
+                    const int gm = m0 + wm * WM + i * 16 + (lane & 15);
+                    if (gm >= M) continue;
+                    const int a = posL[gm];
+                    if (a < 0) continue;
+#pragma unroll
+                    for (int j = 0; j < TN; j++)
+#pragma unroll
+                        for (int v = 0; v < 4; v++) {
+                            const int gn = row_n(j, v);
+                            if (gn >= N) continue;
+                            const int b = posU[gn];
+                            if (b >= 0) G[a + b * clK] = (TG)acc[i][j][v];
+                        }
+                }
+            }
+        }
     }
 }
 
 // Dispatch on the operand forms of the problem (uniform across the
 // workgroup).
-template <int MODE, int BM, int BN, typename TA, typename TC, bool CIN, int BK = Mode<MODE>::BK>
+template <int MODE, int BM, int BN, typename TA, typename TC, bool CIN, bool PUSH = false,
+          int BK = Mode<MODE>::BK>
 __device__ __forceinline__ void gemm_tile(const GemmProb &p, const int m0, const int n0,
-                                          Smem<MODE, BM, BN, BK> &sm) {
+                                          Smem<MODE, BM, BN, BK> &sm, const MatDev *mats = nullptr) {
+    typedef typename Mode<MODE>::T TG;
     if (p.opA == 0) {
         if (p.opB == 0)
-            gemm_tile_op<MODE, BM, BN, TA, TC, CIN, BK, 0, 0>(p, m0, n0, sm);
+            gemm_tile_op<MODE, BM, BN, TA, TC, CIN, BK, 0, 0, PUSH, TG>(p, m0, n0, sm, mats);
         else
-            gemm_tile_op<MODE, BM, BN, TA, TC, CIN, BK, 0, 1>(p, m0, n0, sm);
+            gemm_tile_op<MODE, BM, BN, TA, TC, CIN, BK, 0, 1, PUSH, TG>(p, m0, n0, sm, mats);
     } else {
         if (p.opB == 0)
-            gemm_tile_op<MODE, BM, BN, TA, TC, CIN, BK, 1, 0>(p, m0, n0, sm);
+            gemm_tile_op<MODE, BM, BN, TA, TC, CIN, BK, 1, 0, PUSH, TG>(p, m0, n0, sm, mats);
         else
-            gemm_tile_op<MODE, BM, BN, TA, TC, CIN, BK, 1, 1>(p, m0, n0, sm);
+            gemm_tile_op<MODE, BM, BN, TA, TC, CIN, BK, 1, 1, PUSH, TG>(p, m0, n0, sm, mats);
     }
 }
 
@@ -305,7 +345,7 @@ struct GatherSmem {
 // loads of one stage are all in flight together.
 template <typename T>
 __device__ __forceinline__ void gather_tile(const MatDev &M, const int K, const int a0, const int b0,
-                                            GatherSmem<T> &sm) {
+                                            GatherSmem<T> &sm, const int skip = -1) {
     T(&tileS)[64][65] = sm.tileS;
     int32_t *rowR = sm.rowR, *rowI = sm.rowI, *colJ = sm.colJ;
     int64_t *rowUp = sm.rowUp, *rowUoff = sm.rowUoff, *colDiag = sm.colDiag, *colLow = sm.colLow,
@@ -372,7 +412,7 @@ __device__ __forceinline__ void gather_tile(const MatDev &M, const int K, const 
             kind[t] = 0;
             if (ia < na && ib < nb) {
                 const int32_t I = rowI[ia], J = colJ[ib];
-                kind[t] = I == J ? 1 : (I > J ? 2 : 0);
+                kind[t] = I == J ? (I == skip ? 0 : 1) : (I > J ? 2 : 0);
             }
         }
 #pragma unroll
@@ -423,7 +463,9 @@ __device__ __forceinline__ void gather_tile(const MatDev &M, const int K, const 
     SELINV_GLOBAL T *G = gptr_w((T *)M.G + sk_g_off);
     for (int e = tid; e < 64 * 64; e += 256) {
         const int ia = e & 63, ib = e >> 6;
-        if (ia < na && ib < nb) G[(a0 + ia) + (int64_t)(b0 + ib) * sk_cl] = tileS[ib][ia];
+        // entries of the skipped diagonal block are written by its owner
+        if (ia < na && ib < nb && !(rowI[ia] == skip && colJ[ib] == skip))
+            G[(a0 + ia) + (int64_t)(b0 + ib) * sk_cl] = tileS[ib][ia];
     }
 }
 

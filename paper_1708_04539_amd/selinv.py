@@ -225,10 +225,10 @@ class SelInv:
         return out
 
     def level_stats(self, level):
-        out = np.zeros(13, np.float64)
+        out = np.zeros(14, np.float64)
         self._check(_lib.selinv_level_stats(self._h, int(level), _p(out, C.c_double)), "level_stats")
         keys = ["nsup", "max_s", "flops35", "flops4", "gather_elems", "gather_tiles", "tiles35", "tiles4",
-                "tile35", "tile4", "small_count", "small_flops", "small_elems"]
+                "tile35", "tile4", "small_count", "small_flops", "small_elems", "gather_fused"]
         return dict(zip(keys, out.tolist()))
 
     @property

@@ -114,3 +114,30 @@ def test_error_paths(si):
     with pytest.raises(si.SelinvError) as e:
         s.run(7)
     assert e.value.status == "INVALID_ARG"
+
+
+@pytest.mark.parametrize("name", ["c0", "c1", "c3", "random", "tridiag"])
+def test_plan_and_push_maps_consistent(si, name):
+    """Gather maps, extraction locations and the maps that let a parent's
+    step-4 product write its diagonal block into its children's G all agree
+    with R_L / R_U (host-side check, no device needed)."""
+    from workloads import tridiag_csc
+    if name == "c0":
+        w = config_c0()
+        args = (w.n, w.colptr, w.rowind, w.perm, w.max_super, w.relax, w.pad_pct)
+    elif name == "c1":
+        w = config_c1()
+        args = (w.n, w.colptr, w.rowind, w.perm, w.max_super, w.relax, w.pad_pct)
+    elif name == "c3":
+        w = config_c3(count=2)[1]
+        args = (w.n, w.colptr, w.rowind, w.perm, w.max_super, w.relax, w.pad_pct)
+    elif name == "random":
+        cp, ri, v, _ = random_sparse(300, 0.02, 5, symmetric_pattern=False)
+        args = (300, cp, ri, np.random.default_rng(5).permutation(300).astype(np.int32), 7, 3, 5)
+    else:
+        n = 200
+        cp, ri, v = tridiag_csc(-np.ones(n - 1), 2 * np.ones(n), -np.ones(n - 1))
+        args = (n, cp, ri, None, 16, 0, 0)
+    s = si.SelInv(*args)
+    assert s.check_plan() == 0
+    s.close()
