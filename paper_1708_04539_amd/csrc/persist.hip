@@ -95,28 +95,164 @@ __global__ __launch_bounds__(256) void sweep_kernel(const PersistArgs a) {
 }
 
 // Small supernodes (c_L, c_U, s <= 64): one workgroup does the whole of
-// Algorithm 1 steps 3-5 for one supernode -- gather G_K (one tile), then the
-// step-3 and step-5 products, then the step-4 product -- so that the deep
-// levels of the tree cost one launch instead of three.  G_K and the step-3
-// result are written to global memory and read back by the same workgroup
-// after a barrier (workgroup-scope ordering suffices).
+// Algorithm 1 steps 3-5 for one supernode, so that a level of them costs one
+// launch instead of three.
+//   0. each wavefront owns one block of 16 columns (of the s columns of the
+//      three results) and loads its columns of Lhat and Uhat straight from
+//      global memory into registers, before anything else: those loads are
+//      in flight during the gather;
+//   1. gather G_K (one tile) into LDS; it never goes to global memory;
+//   2. the step-3 product -G^T Lhat and the step-5 product -G Uhat^T, 16x16
+//      output tiles, op(A) from the LDS copy of G; the step-3 result is also
+//      kept in LDS;
+//   3. the step-4 product from that LDS copy and the Uhat registers.
+// When s < 49 several wavefronts share a column block and split its row
+// blocks.  Products run on v_mfma_*_16x16x4 with the k order and operand
+// roles of the grouped GEMM, so FP64 and FP32 results are bitwise those of the
+// per-phase launches; the split-BF16 form runs these small products in FP32.
+template <typename T>
+struct SmallSmem {
+    GatherSmem<T> g;
+    T zu[64][65];  // zu[b][j] = A^{-T}(K, R_U)^T (b, j)
+};
+
+template <typename T>
+struct SmallMfma;
+template <>
+struct SmallMfma<double> {
+    typedef v4d Acc;
+    static __device__ __forceinline__ Acc step(double b, double a, Acc c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(b, a, c, 0, 0, 0);
+    }
+    // column of the 16x16 result held in item v of lane l
+    static __device__ __forceinline__ int col(int l, int v) { return (l >> 4) + 4 * v; }
+};
+template <>
+struct SmallMfma<float> {
+    typedef v4f Acc;
+    static __device__ __forceinline__ Acc step(float b, float a, Acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(b, a, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int col(int l, int v) { return 4 * (l >> 4) + v; }
+};
+
+// op(B)(k, n0 + lane % 16) for k = 4 q + lane / 16, q < 16, from a K x N
+// column-major operand (clamped addresses; zero outside)
+template <typename T>
+__device__ __forceinline__ void small_loadB(T (&bv)[16], const T *Bp, int64_t ldb, int N, int K, int n0) {
+    const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+    if (!Bp || K <= 0) {
+#pragma unroll
+        for (int q = 0; q < 16; q++) bv[q] = (T)0;
+        return;
+    }
+    const SELINV_GLOBAL T *B = gptr(Bp);
+    const int n = n0 + li;
+    const int64_t nc = min(n, N - 1);
+#pragma unroll
+    for (int q = 0; q < 16; q++) bv[q] = B[min(4 * q + lk, K - 1) + nc * ldb];
+#pragma unroll
+    for (int q = 0; q < 16; q++) bv[q] = (n < N && 4 * q + lk < K) ? bv[q] : (T)0;
+}
+
+// One 16x16 tile (rows m0..) of op(A) op(B): op(A)(m, k) from getA (LDS),
+// op(B) from the registers of small_loadB, k < K <= 64.
+template <typename T, typename GetA>
+__device__ __forceinline__ typename SmallMfma<T>::Acc small_tile(GetA getA, const T (&bv)[16], int M, int K,
+                                                                 int m0) {
+    typedef typename SmallMfma<T>::Acc Acc;
+    const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+    Acc acc = {0, 0, 0, 0};
+    const int m = m0 + li;
+#pragma unroll
+    for (int q = 0; q < 16; q++) {
+        if (4 * q >= K) break;
+        const int k = 4 * q + lk;
+        const T a = (m < M && k < K) ? getA(m, k) : (T)0;
+        acc = SmallMfma<T>::step(bv[q], a, acc);
+    }
+    return acc;
+}
+
 template <int MODE>
 __global__ __launch_bounds__(256) void small_kernel(const MatDev *__restrict__ mats, const GemmProb *__restrict__ probs,
                                                     const SmallItem *__restrict__ items) {
     typedef typename Mode<MODE>::T T;
-    union Shared {
-        Smem<MODE, 64, 64> g;
-        GatherSmem<T> t;
-    };
-    __shared__ Shared sm;
+    typedef SmallMfma<T> MF;
+    __shared__ SmallSmem<T> sm;
     const SmallItem it = items[blockIdx.x];
     const SELINV_GLOBAL SnRec *sn = gptr(mats[it.mat].sn);
-    if (sn[it.K].cl > 0 && sn[it.K].cu > 0) gather_tile<T>(mats[it.mat], it.K, 0, 0, sm.t);
+    const int s = sn[it.K].s, cl = sn[it.K].cl, cu = sn[it.K].cu;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, li = lane & 15;
+    // column block of this wavefront, and its share of the row blocks
+    const int ns = (s + 15) / 16, per = 4 / ns;  // wavefronts per column block
+    const bool active = wave < ns * per;
+    const int n0 = 16 * (wave % ns), mfirst = wave / ns;
+    const GemmProb *pzu = it.pzu >= 0 ? &probs[it.pzu] : nullptr;
+    const GemmProb *pzl = it.pzl >= 0 ? &probs[it.pzl] : nullptr;
+    const GemmProb *pg4 = it.pg4 >= 0 ? &probs[it.pg4] : nullptr;
+    T bL[16], bU[16];
+    small_loadB<T>(bL, pzu ? (const T *)pzu->B : nullptr, pzu ? pzu->ldb : 1, s, cl, n0);
+    const GemmProb *pu = pzl ? pzl : pg4;  // Uhat: op(B) of steps 5 and 4
+    small_loadB<T>(bU, pu ? (const T *)pu->B : nullptr, pu ? pu->ldb : 1, s, cu, n0);
+
+    if (cl > 0 && cu > 0) gather_tile<T, false>(mats[it.mat], it.K, 0, 0, sm.g);
     __syncthreads();
-    if (it.pzu >= 0) gemm_tile<MODE, 64, 64, T, T, false>(probs[it.pzu], 0, 0, sm.g);
-    if (it.pzl >= 0) gemm_tile<MODE, 64, 64, T, T, false>(probs[it.pzl], 0, 0, sm.g);
+    const T(&G)[64][65] = sm.g.tileS;  // G[b][a] = G_K(a, b)
+    if (active) {
+        const int n = n0 + 0;  // first column of the block; lanes add MF::col
+        // step 3: A^{-T}(K,R_U)^T = -G^T Lhat (cu x s)
+        if (pzu) {
+            SELINV_GLOBAL T *C = gptr_w((T *)pzu->C);
+            for (int mb = mfirst; 16 * mb < cu; mb += per) {
+                const typename MF::Acc acc = small_tile<T>([&](int m, int k) { return G[m][k]; }, bL, cu, cl, 16 * mb);
+                const int m = 16 * mb + li;
+#pragma unroll
+                for (int v = 0; v < 4; v++) {
+                    const int c = n + MF::col(lane, v);
+                    if (m >= cu || c >= s) continue;
+                    const T r = (T)(pzu->alpha * (double)acc[v]);
+                    C[m + (int64_t)c * pzu->ldc] = r;
+                    sm.zu[m][c] = r;
+                }
+            }
+        }
+        // step 5: A^{-T}(R_L,K) = -G Uhat^T (cl x s)
+        if (pzl) {
+            SELINV_GLOBAL T *C = gptr_w((T *)pzl->C);
+            for (int mb = mfirst; 16 * mb < cl; mb += per) {
+                const typename MF::Acc acc = small_tile<T>([&](int m, int k) { return G[k][m]; }, bU, cl, cu, 16 * mb);
+                const int m = 16 * mb + li;
+#pragma unroll
+                for (int v = 0; v < 4; v++) {
+                    const int c = n + MF::col(lane, v);
+                    if (m >= cl || c >= s) continue;
+                    C[m + (int64_t)c * pzl->ldc] = (T)(pzl->alpha * (double)acc[v]);
+                }
+            }
+        }
+    }
     __syncthreads();
-    if (it.pg4 >= 0) gemm_tile<MODE, 64, 64, T, double, true>(probs[it.pg4], 0, 0, sm.g);
+    // step 4: A^{-T}(K,K) -= A^{-T}(K,R_U) Uhat^T (FP64 accumulation)
+    if (active && pg4) {
+        SELINV_GLOBAL double *C = gptr_w((double *)pg4->C);
+        for (int mb = mfirst; 16 * mb < s; mb += per) {
+            const typename MF::Acc acc =
+                small_tile<T>([&](int m, int k) { return sm.zu[k][m]; }, bU, s, cu, 16 * mb);
+            const int m = 16 * mb + li;
+            double cin[4];
+#pragma unroll
+            for (int v = 0; v < 4; v++) cin[v] = C[min(m, s - 1) + (int64_t)min(n0 + MF::col(lane, v), s - 1) * pg4->ldc];
+#pragma unroll
+            for (int v = 0; v < 4; v++) {
+                const int c = n0 + MF::col(lane, v);
+                if (m >= s || c >= s) continue;
+                double r = pg4->alpha * (double)acc[v];
+                r += pg4->beta * cin[v];
+                C[m + (int64_t)c * pg4->ldc] = r;
+            }
+        }
+    }
 }
 
 hipError_t launch_small(int mode, const MatDev *mats, const GemmProb *probs, const SmallItem *items, int count,

@@ -343,7 +343,8 @@ struct GatherSmem {
 // Every load goes through a global-memory view and is issued unconditionally
 // (clamped to a valid index, the unused value discarded), so that a thread's
 // loads of one stage are all in flight together.
-template <typename T>
+// STORE = false leaves the tile in LDS only (sm.tileS[b][a] = G(a0+a, b0+b)).
+template <typename T, bool STORE = true>
 __device__ __forceinline__ void gather_tile(const MatDev &M, const int K, const int a0, const int b0,
                                             GatherSmem<T> &sm, const int skip = -1) {
     T(&tileS)[64][65] = sm.tileS;
@@ -460,6 +461,7 @@ __device__ __forceinline__ void gather_tile(const MatDev &M, const int K, const 
         }
     }
     __syncthreads();
+    if constexpr (!STORE) return;
     SELINV_GLOBAL T *G = gptr_w((T *)M.G + sk_g_off);
     for (int e = tid; e < 64 * 64; e += 256) {
         const int ia = e & 63, ib = e >> 6;

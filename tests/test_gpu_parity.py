@@ -303,11 +303,16 @@ def test_persistent_sweep_matches_level_sweep_c1(si, c1_pair, prec):
     s.set_sweep_mode("persistent")
     s.run(prec)
     assert s.sweep_is_persistent(prec) == 1
-    assert np.array_equal(s.get_selected(), ref)
+    # FP64 and FP32: the same products in the same k order, bitwise equal.
+    # Split-BF16: the fused small-supernode launches of the level sweep run
+    # their products in FP32, the persistent sweep in split-BF16.
+    same = (lambda x: np.array_equal(x, ref)) if prec != "mixed_bf16x3" else \
+        (lambda x: np.abs(x - ref).max() <= TOL[prec] * np.abs(ref).max())
+    assert same(s.get_selected())
     st = torch.cuda.Stream()
     for rep in range(3):
         s.run(prec, stream=st, graph=True)
-        assert np.array_equal(s.get_selected(), ref), rep
+        assert same(s.get_selected()), rep
     s.set_sweep_mode("auto")
 
 
