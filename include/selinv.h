@@ -21,9 +21,9 @@
  *     structurally present; otherwise SELINV_E_BAD_PATTERN.
  *   * perm[new] = old (perm = NULL means the natural order); the permuted
  *     matrix is At[a][b] = A[perm[a]][perm[b]].  Not a permutation:
- *     SELINV_E_BAD_PERM.  The library may replace perm by a postorder of the
- *     elimination tree of At + At^T; this changes neither the fill nor any
- *     result.
+ *     SELINV_E_BAD_PERM.  The symmetrized analysis may replace perm by a
+ *     postorder of the elimination tree of At + At^T; this changes neither
+ *     the fill nor any result.  The exact analysis keeps perm as given.
  *   * Every input array is copied; the caller may free it on return.  The
  *     handle owns all host and device memory until selinv_destroy().
  *   * Device memory is allocated with hipMalloc on the device that is current
@@ -73,6 +73,24 @@ typedef enum {
     SELINV_MIXED_BF16X3 = 2
 } selinv_precision;
 
+/* Symbolic analysis forms (section 2: the method needs no structural
+ * symmetrization; its block row and column sets R_L(K) and R_U(K) may differ).
+ *   SELINV_SYMBOLIC_SYMMETRIZED : pattern of At + At^T (R_L = R_U), elimination
+ *       tree postorder, relaxed supernodes (relax, pad_pct below).
+ *   SELINV_SYMBOLIC_EXACT : the exact pattern of the unpivoted L and U of At,
+ *       no symmetrization: supernodes are runs of consecutive columns of L
+ *       with L(j, j-1) != 0 and equal structure below row j (fundamental
+ *       supernodes of L), cut every max_super columns; R_L(K) and R_U(K) are
+ *       the row set of L(:, K) and the column set of U(K, :) beyond K, closed
+ *       under the block fill R_L(K) x R_U(K) of every earlier supernode, so
+ *       that Theorem 1 holds blockwise.  relax and pad_pct are ignored and the
+ *       ordering is used as given.  Sweeps of such handles run level by level
+ *       (the persistent form needs the symmetrized analysis). */
+typedef enum {
+    SELINV_SYMBOLIC_SYMMETRIZED = 0,
+    SELINV_SYMBOLIC_EXACT = 1
+} selinv_symbolic;
+
 /* Supernode partition rules (paper section 2, paragraph on supernodes:
  * relaxed supernodes with a maximal width).
  *   max_super : widest supernode; wider ones are cut into consecutive pieces
@@ -86,12 +104,14 @@ typedef enum {
  *               cnt = off-diagonal count of a column of L) stays at most
  *               pad_pct percent of s (cnt(j) + s).  0 gives fundamental
  *               supernodes; values are clamped to [0, 100].
+ *   symbolic  : a selinv_symbolic value (other values: SELINV_E_INVALID_ARG).
  * Padded entries are stored explicitly; their values are still exact entries
- * of A^{-1}. */
+ * of A^{-1}.  opts = NULL: all fields 0. */
 typedef struct {
     int32_t max_super;
     int32_t relax;
     int32_t pad_pct;
+    int32_t symbolic;
 } selinv_analyze_opts;
 
 typedef struct {
@@ -108,12 +128,16 @@ typedef struct {
     double bytes_min_fp32; /* same with FP32 off-diagonal blocks                 */
     double max_gemm_flops;  /* flops of the largest single supernode product    */
     int32_t max_gemm_m, max_gemm_n, max_gemm_k; /* its shape                    */
+    int32_t symbolic;   /* selinv_symbolic form of the analysis                  */
+    int64_t nnz_l, nnz_u; /* stored entries of the off-diagonal blocks of L, U   */
 } selinv_info;
 
-/* Symbolic analysis (host only).  Builds the elimination tree of At + At^T,
- * the supernode partition, the block row/column sets R_L(K), R_U(K) of
- * Algorithm 1, the level sets of the supernodal tree (root at level 0) and
- * the relative-index maps used by the gather. */
+/* Symbolic analysis (host only).  Builds the supernode partition, the block
+ * row/column sets R_L(K), R_U(K) of Algorithm 1 (from At + At^T or from the
+ * exact pattern, see selinv_symbolic), the level sets of the supernodal
+ * dependency graph (level(K) = 0 if R_L(K) and R_U(K) are empty, else one
+ * more than the deepest supernode they touch; roots at level 0) and the
+ * relative-index maps used by the gather. */
 selinv_status selinv_analyze(int64_t n, const int64_t *colptr, const int32_t *rowind,
                              const int32_t *perm, const selinv_analyze_opts *opts,
                              selinv_handle *out);

@@ -1,6 +1,9 @@
 // analyze.cpp -- symbolic analysis for supernodal selected inversion.
 //
-// Steps (all on the host, O(|L|) time):
+// Two forms (paper, section 2: the method itself needs no structural
+// symmetrization, R_L(K) and R_U(K) may differ).
+//
+// Symmetrized form (all on the host, O(|L|) time):
 //   1. validate the CSC pattern and the ordering;
 //   2. adjacency of At + At^T (At = P A P^T);
 //   3. elimination tree by Liu's path-compressed ancestor walk;
@@ -13,10 +16,19 @@
 //      padding estimate stays within `pad_pct` percent; cuts every
 //      `max_super` columns;
 //   7. supernodal symbolic factorisation: R(K) = adjacency of K's columns
-//      beyond K, merged with R(C) of every child supernode C;  R_L = R_U = R
-//      for the structurally symmetric pattern used here;
-//   8. levels of the supernodal tree (root at level 0: Algorithm 1 walks
-//      K = N..1, and every supernode on one level depends only on
+//      beyond K, merged with R(C) of every child supernode C;  R_L = R_U = R.
+//
+// Exact form (no symmetrization, ordering kept as given):
+//   2'. lower and upper parts of the pattern of At;
+//   3'. the exact structure of the unpivoted L and U, condensed on the fly
+//       into fundamental supernodes of L, with symmetric pruning;
+//   6'. those supernodes cut every `max_super` columns;
+//   7'. R_L(K), R_U(K) from At and the block fill R_L(K') x R_U(K') of the
+//       earlier supernodes K' (blockwise pruned the same way).
+//
+// Both forms then:
+//   8. levels of the supernodal dependency graph (root at level 0: Algorithm
+//      1 walks K = N..1, and every supernode on one level depends only on
 //      shallower ones -- section on inter-supernode parallelism);
 //   9. storage offsets, relative-index maps of the gather (Theorem 1: every
 //      entry of A^{-T}(R_L(K), R_U(K)) lies in an ancestor's block), storage
@@ -152,58 +164,301 @@ void column_counts(int64_t n, const std::vector<int64_t> &ptr, const std::vector
     }
 }
 
-}  // namespace
-
-selinv_status analyze(Plan &P, int64_t n, const int64_t *colptr, const int32_t *rowind,
-                      const int32_t *perm, int32_t max_super, int32_t relax, int32_t pad_pct,
-                      std::string &err) {
-    if (n < 1 || !colptr || !rowind) {
-        err = "n must be >= 1 and colptr/rowind non-null";
-        return SELINV_E_INVALID_ARG;
-    }
-    if (n >= (int64_t(1) << 31) - 1) {
-        err = "n exceeds the int32 index range";
-        return SELINV_E_INVALID_ARG;
-    }
-    if (colptr[0] != 0) {
-        err = "colptr[0] != 0";
-        return SELINV_E_BAD_PATTERN;
-    }
-    for (int64_t j = 0; j < n; j++) {
-        if (colptr[j + 1] < colptr[j]) {
-            err = "colptr decreases";
-            return SELINV_E_BAD_PATTERN;
-        }
-        bool diag = false;
+// Lower and upper parts of the permuted pattern: the rows r > k of column k
+// of At and the columns c > k of row k, each list sorted.
+void split_pattern(int64_t n, const int64_t *colptr, const int32_t *rowind, const std::vector<int32_t> &q,
+                   std::vector<int64_t> &lptr, std::vector<int32_t> &lidx, std::vector<int64_t> &uptr,
+                   std::vector<int32_t> &uidx) {
+    lptr.assign(n + 1, 0);
+    uptr.assign(n + 1, 0);
+    for (int64_t j = 0; j < n; j++)
         for (int64_t k = colptr[j]; k < colptr[j + 1]; k++) {
-            int32_t r = rowind[k];
-            if (r < 0 || r >= n || (k > colptr[j] && rowind[k - 1] >= r)) {
-                err = "row indices out of range, unsorted or duplicated in column " + std::to_string(j);
-                return SELINV_E_BAD_PATTERN;
-            }
-            diag |= r == j;
+            const int32_t r = q[rowind[k]], c = q[j];
+            if (r > c) lptr[c + 1]++;
+            if (r < c) uptr[r + 1]++;
         }
-        if (!diag) {
-            err = "missing diagonal entry in column " + std::to_string(j);
-            return SELINV_E_BAD_PATTERN;
-        }
-    }
-    P.n = n;
-    P.nnz_a = colptr[n];
-    P.a_colptr.assign(colptr, colptr + n + 1);
-    P.a_rowind.assign(rowind, rowind + P.nnz_a);
-    P.p.resize(n);
-    P.q.assign(n, -1);
     for (int64_t i = 0; i < n; i++) {
-        int32_t v = perm ? perm[i] : (int32_t)i;
-        if (v < 0 || v >= n || P.q[v] >= 0) {
-            err = "perm is not a permutation";
-            return SELINV_E_BAD_PERM;
-        }
-        P.p[i] = v;
-        P.q[v] = (int32_t)i;
+        lptr[i + 1] += lptr[i];
+        uptr[i + 1] += uptr[i];
     }
+    lidx.resize(lptr[n]);
+    uidx.resize(uptr[n]);
+    std::vector<int64_t> lpos(lptr.begin(), lptr.end() - 1), upos(uptr.begin(), uptr.end() - 1);
+    for (int64_t j = 0; j < n; j++)
+        for (int64_t k = colptr[j]; k < colptr[j + 1]; k++) {
+            const int32_t r = q[rowind[k]], c = q[j];
+            if (r > c) lidx[lpos[c]++] = r;
+            if (r < c) uidx[upos[r]++] = c;
+        }
+    for (int64_t i = 0; i < n; i++) {
+        std::sort(lidx.begin() + lptr[i], lidx.begin() + lptr[i + 1]);
+        std::sort(uidx.begin() + uptr[i], uidx.begin() + uptr[i + 1]);
+    }
+}
 
+// One singly linked list of ids per slot (a column, a row or a supernode).
+struct SlotLists {
+    std::vector<int64_t> head, next;
+    std::vector<int32_t> val;
+    void init(int64_t slots) {
+        head.assign(slots, -1);
+        next.clear();
+        val.clear();
+    }
+    void push(int64_t slot, int32_t v) {
+        next.push_back(head[slot]);
+        val.push_back(v);
+        head[slot] = (int64_t)val.size() - 1;
+    }
+};
+
+// First value present in both sorted lists (key() maps an entry to the value
+// compared), or `none`.
+template <typename Key>
+int32_t first_common(const int32_t *a, int64_t na, const int32_t *b, int64_t nb, Key key, int32_t none) {
+    for (int64_t x = 0, y = 0; x < na && y < nb;) {
+        const int32_t ka = key(a[x]), kb = key(b[y]);
+        if (ka == kb) return ka;
+        if (ka < kb) x++; else y++;
+    }
+    return none;
+}
+
+// Starts of the fundamental supernodes of L for the exact (unsymmetrized)
+// pattern: column j joins column j-1 when L(j, j-1) != 0 and both columns
+// have the same rows below j.
+//
+// Gaussian elimination without pivoting gives (the fill rule):
+//   rows of L(:, k) below k    = At(k+1:, k)  u  U L(k+1:, j) over the pivots
+//                                j < k with U(j, k) != 0,
+//   columns of U(k, :) past k  = At(k, k+1:)  u  U U(j, k+1:) over the pivots
+//                                j < k with L(k, j) != 0.
+// Columns are processed in order and kept condensed: inside a run of
+// columns that joined, every column has the same rows FL below the run and,
+// since L(i, i-1) != 0 there, row i of U covers row i-1 of U past i.  So the
+// pivots of a finished run J act on later columns exactly as its last pivot
+// does: column m in FU(J) (the columns of U past the run, last row) receives
+// FL(J) beyond m, row m in FL(J) receives FU(J) beyond m.  The run still
+// open acts on the next column through its last pivot k-1 alone.  Symmetric
+// pruning: once m lies in both FL(J) and FU(J), pivot m has received all of
+// FL(J) and FU(J) beyond it and carries them on to every later column and
+// row that J would reach, so the pushes of J stop at that m.
+void fundamental_starts(int64_t n, const std::vector<int64_t> &lptr, const std::vector<int32_t> &lidx,
+                        const std::vector<int64_t> &uptr, const std::vector<int32_t> &uidx,
+                        std::vector<int32_t> &starts) {
+    std::vector<int64_t> fl_ptr(1, 0), fu_ptr(1, 0);
+    std::vector<int32_t> fl, fu;
+    SlotLists toL, toU;  // finished runs whose FL a column (FU a row) receives
+    toL.init(n);
+    toU.init(n);
+    std::vector<int32_t> markL(n, -1), markU(n, -1), prevL, prevU, curL, curU;
+    starts.clear();
+    int32_t nruns = 0;
+    auto finish = [&](int64_t l) {  // the run ending at column l; prevL/prevU are its FL/FU
+        const int32_t J = nruns++;
+        fl.insert(fl.end(), prevL.begin(), prevL.end());
+        fu.insert(fu.end(), prevU.begin(), prevU.end());
+        fl_ptr.push_back((int64_t)fl.size());
+        fu_ptr.push_back((int64_t)fu.size());
+        const int32_t stop = first_common(prevL.data(), (int64_t)prevL.size(), prevU.data(),
+                                          (int64_t)prevU.size(), [](int32_t x) { return x; }, INT32_MAX);
+        // column and row l + 1 have taken pivot l already (as the open run)
+        for (int32_t m : prevU) {
+            if (m > stop) break;
+            if (m > l + 1) toL.push(m, J);
+        }
+        for (int32_t m : prevL) {
+            if (m > stop) break;
+            if (m > l + 1) toU.push(m, J);
+        }
+    };
+    for (int64_t k = 0; k < n; k++) {
+        const int32_t k32 = (int32_t)k;
+        curL.clear();
+        curU.clear();
+        auto addL = [&](int32_t r) {
+            if (markL[r] != k32) {
+                markL[r] = k32;
+                curL.push_back(r);
+            }
+        };
+        auto addU = [&](int32_t c) {
+            if (markU[c] != k32) {
+                markU[c] = k32;
+                curU.push_back(c);
+            }
+        };
+        for (int64_t t = lptr[k]; t < lptr[k + 1]; t++) addL(lidx[t]);
+        for (int64_t t = uptr[k]; t < uptr[k + 1]; t++) addU(uidx[t]);
+        for (int64_t e = toL.head[k]; e >= 0; e = toL.next[e]) {
+            const int32_t J = toL.val[e];
+            const int32_t *b = fl.data() + fl_ptr[J], *en = fl.data() + fl_ptr[J + 1];
+            for (const int32_t *it = std::upper_bound(b, en, k32); it < en; it++) addL(*it);
+        }
+        for (int64_t e = toU.head[k]; e >= 0; e = toU.next[e]) {
+            const int32_t J = toU.val[e];
+            const int32_t *b = fu.data() + fu_ptr[J], *en = fu.data() + fu_ptr[J + 1];
+            for (const int32_t *it = std::upper_bound(b, en, k32); it < en; it++) addU(*it);
+        }
+        // pivot k - 1 of the open run
+        const bool l_sub = k > 0 && std::binary_search(prevL.begin(), prevL.end(), k32);  // L(k, k-1) != 0
+        const bool u_sub = k > 0 && std::binary_search(prevU.begin(), prevU.end(), k32);  // U(k-1, k) != 0
+        const auto pl = std::upper_bound(prevL.begin(), prevL.end(), k32);
+        const auto pu = std::upper_bound(prevU.begin(), prevU.end(), k32);
+        if (u_sub)
+            for (auto it = pl; it != prevL.end(); ++it) addL(*it);
+        if (l_sub)
+            for (auto it = pu; it != prevU.end(); ++it) addU(*it);
+        std::sort(curL.begin(), curL.end());
+        std::sort(curU.begin(), curU.end());
+        const bool join = l_sub && (size_t)(prevL.end() - pl) == curL.size() && std::equal(pl, prevL.end(), curL.begin());
+        if (!join) {
+            if (k > 0) finish(k - 1);
+            starts.push_back(k32);
+        }
+        std::swap(prevL, curL);
+        std::swap(prevU, curU);
+    }
+}
+
+// R_L(K) and R_U(K) of the exact form for the partition in P.xsup: the rows
+// of At below K in the columns of K and the columns of At right of K in the
+// rows of K, plus the block fill of every earlier supernode K': the entries
+// R_L(K') x R_U(K') put the rows of R_L(K') beyond J into R_L(J) for every
+// supernode J that R_U(K') meets, and the columns of R_U(K') beyond I into
+// R_U(I) for every I that R_L(K') meets.  Every entry of L+U that elimination
+// by blocks touches is then in the pattern (the closure the gather relies
+// on).  Blockwise symmetric pruning: the first supernode S met by both
+// R_L(K') and R_U(K') receives both sets beyond it, and its own fill carries
+// them on to every later supernode, so K' pushes to supernodes up to S only.
+void exact_block_sets(Plan &P, const std::vector<int64_t> &lptr, const std::vector<int32_t> &lidx,
+                      const std::vector<int64_t> &uptr, const std::vector<int32_t> &uidx) {
+    const int32_t ns = P.ns;
+    SlotLists toL, toU;
+    toL.init(ns);
+    toU.init(ns);
+    P.rl_ptr.assign(ns + 1, 0);
+    P.ru_ptr.assign(ns + 1, 0);
+    P.rl.clear();
+    P.ru.clear();
+    std::vector<int32_t> markL(P.n, -1), markU(P.n, -1), RL, RU;
+    for (int32_t K = 0; K < ns; K++) {
+        const int32_t f = P.xsup[K], l = P.xsup[K + 1] - 1;
+        RL.clear();
+        RU.clear();
+        auto addL = [&](int32_t r) {
+            if (markL[r] != K) {
+                markL[r] = K;
+                RL.push_back(r);
+            }
+        };
+        auto addU = [&](int32_t c) {
+            if (markU[c] != K) {
+                markU[c] = K;
+                RU.push_back(c);
+            }
+        };
+        for (int32_t j = f; j <= l; j++) {
+            for (int64_t t = lptr[j]; t < lptr[j + 1]; t++)
+                if (lidx[t] > l) addL(lidx[t]);
+            for (int64_t t = uptr[j]; t < uptr[j + 1]; t++)
+                if (uidx[t] > l) addU(uidx[t]);
+        }
+        for (int64_t e = toL.head[K]; e >= 0; e = toL.next[e]) {
+            const int32_t Q = toL.val[e];
+            const int32_t *b = P.rl.data() + P.rl_ptr[Q], *en = P.rl.data() + P.rl_ptr[Q + 1];
+            for (const int32_t *it = std::upper_bound(b, en, l); it < en; it++) addL(*it);
+        }
+        for (int64_t e = toU.head[K]; e >= 0; e = toU.next[e]) {
+            const int32_t Q = toU.val[e];
+            const int32_t *b = P.ru.data() + P.ru_ptr[Q], *en = P.ru.data() + P.ru_ptr[Q + 1];
+            for (const int32_t *it = std::upper_bound(b, en, l); it < en; it++) addU(*it);
+        }
+        std::sort(RL.begin(), RL.end());
+        std::sort(RU.begin(), RU.end());
+        P.rl.insert(P.rl.end(), RL.begin(), RL.end());
+        P.ru.insert(P.ru.end(), RU.begin(), RU.end());
+        P.rl_ptr[K + 1] = (int64_t)P.rl.size();
+        P.ru_ptr[K + 1] = (int64_t)P.ru.size();
+        const int32_t *sup = P.supof.data();
+        const int32_t stop = first_common(RL.data(), (int64_t)RL.size(), RU.data(), (int64_t)RU.size(),
+                                          [sup](int32_t x) { return sup[x]; }, INT32_MAX);
+        int32_t last = -1;
+        for (int32_t c : RU) {
+            const int32_t J = sup[c];
+            if (J > stop) break;
+            if (J != last) toL.push(J, K);
+            last = J;
+        }
+        last = -1;
+        for (int32_t r : RL) {
+            const int32_t I = sup[r];
+            if (I > stop) break;
+            if (I != last) toU.push(I, K);
+            last = I;
+        }
+    }
+}
+
+// xsup from the starts of the unsplit supernodes (ending with n): each is cut
+// into pieces of max_super columns from its first column on.
+void cut_partition(Plan &P, const std::vector<int32_t> &starts, int32_t max_super) {
+    P.xsup.clear();
+    for (size_t t = 0; t + 1 < starts.size(); t++) {
+        const int32_t f = starts[t], e = starts[t + 1];
+        const int32_t step = max_super > 0 ? max_super : (e - f);
+        for (int32_t c = f; c < e; c += step) P.xsup.push_back(c);
+    }
+    P.xsup.push_back((int32_t)P.n);
+    P.ns = (int32_t)P.xsup.size() - 1;
+    P.supof.resize(P.n);
+    for (int32_t K = 0; K < P.ns; K++)
+        for (int32_t c = P.xsup[K]; c < P.xsup[K + 1]; c++) P.supof[c] = K;
+}
+
+// Levels of the supernodal dependency graph, processed from the last
+// supernode: level(K) = 0 if R_L(K) u R_U(K) is empty, else 1 + the deepest
+// level among the supernodes it meets (all later than K).  The blocks of
+// A^{-T} that the gather of K reads belong to those supernodes, and the
+// left-looking factorisation of K reads exactly the supernodes whose sets
+// meet K, so both run level by level.  sparent(K) is the first supernode met
+// on level(K) - 1; one_top(K) tells whether it is the only one.
+void dependency_levels(Plan &P) {
+    const int32_t ns = P.ns;
+    P.level.assign(ns, 0);
+    P.sparent.assign(ns, -1);
+    P.one_top.assign(ns, 1);
+    std::vector<int32_t> blk;
+    for (int32_t K = ns - 1; K >= 0; K--) {
+        blk.clear();
+        for (int64_t a = P.rl_ptr[K]; a < P.rl_ptr[K + 1]; a++) {
+            const int32_t J = P.supof[P.rl[a]];
+            if (blk.empty() || blk.back() != J) blk.push_back(J);
+        }
+        for (int64_t b = P.ru_ptr[K]; b < P.ru_ptr[K + 1]; b++) {
+            const int32_t J = P.supof[P.ru[b]];
+            if (blk.empty() || blk.back() != J) blk.push_back(J);
+        }
+        std::sort(blk.begin(), blk.end());
+        blk.erase(std::unique(blk.begin(), blk.end()), blk.end());
+        int32_t lev = 0;
+        for (int32_t J : blk) lev = std::max(lev, P.level[J] + 1);
+        P.level[K] = lev;
+        int top = 0;
+        for (int32_t J : blk)
+            if (P.level[J] == lev - 1 && top++ == 0) P.sparent[K] = J;
+        P.one_top[K] = top <= 1;
+    }
+    P.nlevels = 0;
+    for (int32_t K = 0; K < ns; K++) P.nlevels = std::max(P.nlevels, P.level[K] + 1);
+    P.levels.assign(P.nlevels, {});
+    for (int32_t K = 0; K < ns; K++) P.levels[P.level[K]].push_back(K);
+}
+
+// Symmetrized form: pattern of At + At^T, postordered elimination tree,
+// relaxed and capped supernodes, R_L = R_U.
+void symmetrized_sets(Plan &P, int64_t n, const int64_t *colptr, const int32_t *rowind, int32_t max_super,
+                      int32_t relax, int32_t pad_pct) {
     std::vector<int64_t> aptr;
     std::vector<int32_t> adj, parent, post;
     symmetric_adjacency(n, colptr, rowind, P.q, aptr, adj);
@@ -257,23 +512,12 @@ selinv_status analyze(Plan &P, int64_t n, const int64_t *colptr, const int32_t *
         run_sum += cnt[j];
     }
     starts.push_back((int32_t)n);
-    P.xsup.clear();
-    for (size_t t = 0; t + 1 < starts.size(); t++) {
-        int32_t f = starts[t], e = starts[t + 1];
-        int32_t step = max_super > 0 ? max_super : (e - f);
-        for (int32_t c = f; c < e; c += step) P.xsup.push_back(c);
-    }
-    P.xsup.push_back((int32_t)n);
-    P.ns = (int32_t)P.xsup.size() - 1;
-    P.supof.resize(n);
-    for (int32_t K = 0; K < P.ns; K++)
-        for (int32_t c = P.xsup[K]; c < P.xsup[K + 1]; c++) P.supof[c] = K;
+    cut_partition(P, starts, max_super);
 
     // ---- supernodal symbolic ------------------------------------------
     const int32_t ns = P.ns;
     P.rl_ptr.assign(ns + 1, 0);
     P.rl.clear();
-    P.sparent.assign(ns, -1);
     std::vector<std::vector<int32_t>> kids(ns);
     std::vector<int32_t> mark(n, -1), R;
     for (int32_t K = 0; K < ns; K++) {
@@ -298,24 +542,16 @@ selinv_status analyze(Plan &P, int64_t n, const int64_t *colptr, const int32_t *
         std::sort(R.begin(), R.end());
         P.rl.insert(P.rl.end(), R.begin(), R.end());
         P.rl_ptr[K + 1] = P.rl.size();
-        if (!R.empty()) {
-            P.sparent[K] = P.supof[R[0]];
-            kids[P.sparent[K]].push_back(K);
-        }
+        if (!R.empty()) kids[P.supof[R[0]]].push_back(K);
     }
     P.ru_ptr = P.rl_ptr;
     P.ru = P.rl;
+}
 
-    // ---- levels ---------------------------------------------------------
-    P.level.assign(ns, 0);
-    P.nlevels = 0;
-    for (int32_t K = ns - 1; K >= 0; K--) {
-        P.level[K] = P.sparent[K] < 0 ? 0 : P.level[P.sparent[K]] + 1;
-        P.nlevels = std::max(P.nlevels, P.level[K] + 1);
-    }
-    P.levels.assign(P.nlevels, {});
-    for (int32_t K = 0; K < ns; K++) P.levels[P.level[K]].push_back(K);
-
+// Storage offsets, accounting, gather maps and the location of every entry
+// of A, for the sets and levels in P.
+selinv_status finish_plan(Plan &P, int64_t n, const int64_t *colptr, const int32_t *rowind, std::string &err) {
+    const int32_t ns = P.ns;
     // ---- storage and accounting -----------------------------------------
     P.off_d.assign(ns + 1, 0);
     P.off_l.assign(ns + 1, 0);
@@ -411,6 +647,73 @@ selinv_status analyze(Plan &P, int64_t n, const int64_t *colptr, const int32_t *
             P.a_loc[k] = loc;
         }
     return SELINV_OK;
+}
+
+}  // namespace
+
+selinv_status analyze(Plan &P, int64_t n, const int64_t *colptr, const int32_t *rowind,
+                      const int32_t *perm, int32_t max_super, int32_t relax, int32_t pad_pct,
+                      int32_t symbolic, std::string &err) {
+    if (n < 1 || !colptr || !rowind) {
+        err = "n must be >= 1 and colptr/rowind non-null";
+        return SELINV_E_INVALID_ARG;
+    }
+    if (n >= (int64_t(1) << 31) - 1) {
+        err = "n exceeds the int32 index range";
+        return SELINV_E_INVALID_ARG;
+    }
+    if (colptr[0] != 0) {
+        err = "colptr[0] != 0";
+        return SELINV_E_BAD_PATTERN;
+    }
+    for (int64_t j = 0; j < n; j++) {
+        if (colptr[j + 1] < colptr[j]) {
+            err = "colptr decreases";
+            return SELINV_E_BAD_PATTERN;
+        }
+        bool diag = false;
+        for (int64_t k = colptr[j]; k < colptr[j + 1]; k++) {
+            int32_t r = rowind[k];
+            if (r < 0 || r >= n || (k > colptr[j] && rowind[k - 1] >= r)) {
+                err = "row indices out of range, unsorted or duplicated in column " + std::to_string(j);
+                return SELINV_E_BAD_PATTERN;
+            }
+            diag |= r == j;
+        }
+        if (!diag) {
+            err = "missing diagonal entry in column " + std::to_string(j);
+            return SELINV_E_BAD_PATTERN;
+        }
+    }
+    P.n = n;
+    P.nnz_a = colptr[n];
+    P.a_colptr.assign(colptr, colptr + n + 1);
+    P.a_rowind.assign(rowind, rowind + P.nnz_a);
+    P.p.resize(n);
+    P.q.assign(n, -1);
+    for (int64_t i = 0; i < n; i++) {
+        int32_t v = perm ? perm[i] : (int32_t)i;
+        if (v < 0 || v >= n || P.q[v] >= 0) {
+            err = "perm is not a permutation";
+            return SELINV_E_BAD_PERM;
+        }
+        P.p[i] = v;
+        P.q[v] = (int32_t)i;
+    }
+    P.symbolic = symbolic;
+    if (symbolic == SELINV_SYMBOLIC_EXACT) {
+        std::vector<int64_t> lptr, uptr;
+        std::vector<int32_t> lidx, uidx, starts;
+        split_pattern(n, colptr, rowind, P.q, lptr, lidx, uptr, uidx);
+        fundamental_starts(n, lptr, lidx, uptr, uidx, starts);
+        starts.push_back((int32_t)n);
+        cut_partition(P, starts, max_super);
+        exact_block_sets(P, lptr, lidx, uptr, uidx);
+    } else {
+        symmetrized_sets(P, n, colptr, rowind, max_super, relax, pad_pct);
+    }
+    dependency_levels(P);
+    return finish_plan(P, n, colptr, rowind, err);
 }
 
 // Recompute every source index of the gather exactly as the kernel does (from

@@ -34,8 +34,16 @@ struct Plan {
     std::vector<int32_t> xsup, supof;
     std::vector<int64_t> rl_ptr, ru_ptr;
     std::vector<int32_t> rl, ru;
-    std::vector<int32_t> sparent;  // supernodal elimination tree
-    std::vector<int32_t> level;    // depth, roots at 0
+    int32_t symbolic = SELINV_SYMBOLIC_SYMMETRIZED;
+    // level(K) = 1 + the deepest level among the supernodes touched by
+    // R_L(K) u R_U(K) (0 when both are empty); sparent(K) = the first of those
+    // supernodes on level(K) - 1 (-1 on level 0).  With the symmetrized
+    // analysis this is the supernodal elimination tree.
+    std::vector<int32_t> sparent;
+    std::vector<int32_t> level;
+    // one_top[K]: sparent(K) is the only supernode on level(K) - 1 that
+    // R_L(K) u R_U(K) touches (always true with the symmetrized analysis)
+    std::vector<char> one_top;
     int32_t nlevels = 0;
     std::vector<std::vector<int32_t>> levels;
     std::vector<int64_t> off_d, off_l, off_u;  // element offsets
@@ -62,7 +70,7 @@ struct Plan {
 
 selinv_status analyze(Plan &P, int64_t n, const int64_t *colptr, const int32_t *rowind,
                       const int32_t *perm, int32_t max_super, int32_t relax, int32_t pad_pct,
-                      std::string &err);
+                      int32_t symbolic, std::string &err);
 
 struct HostFactors {
     std::vector<double> d, l, u;

@@ -504,8 +504,14 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, int sweep_mo
     // both use the per-phase launches: the parent's step-4 product writes its
     // final diagonal block into the children's G, the gather tiles fill the
     // rest.  One launch fewer per level.
+    // Only where the parent is the one supernode of the level above that a
+    // child's sets meet (always so for the symmetrized analysis).
     S->fused.assign(depth, 0);
     for (int d = 1; d < depth; d++) S->fused[d] = !level_small[d - 1] && !level_small[d];
+    for (size_t mi = 0; mi < hs.size(); mi++)
+        for (int d = 1; d < hs[mi]->P.nlevels; d++)
+            for (int32_t K : hs[mi]->P.levels[d])
+                if (!hs[mi]->P.one_top[K]) S->fused[d] = 0;
     S->g4gat.resize(depth);
     for (int d = 0; d < depth; d++) {
         cur_level = d;
@@ -687,7 +693,17 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, int sweep_mo
             if (k.type == PT_STEP4 && last_zu[k.gid] > t) X.violations++;
         }
         const bool small = pt.size() <= 400000;
-        S->persistent = sweep_mode == SWEEP_PERSISTENT || (sweep_mode == SWEEP_AUTO && small && persist_auto(hs));
+        // the persistent kernel orders a supernode after its parent only;
+        // that covers every dependency when the sets come from the
+        // symmetrized pattern (they meet ancestors only)
+        bool tree_deps = true;
+        for (auto h : hs) tree_deps &= h->P.symbolic == SELINV_SYMBOLIC_SYMMETRIZED;
+        if (sweep_mode == SWEEP_PERSISTENT && !tree_deps) {
+            err = "the persistent sweep needs the symmetrized analysis";
+            return SELINV_E_INVALID_ARG;
+        }
+        S->persistent = tree_deps && (sweep_mode == SWEEP_PERSISTENT ||
+                                      (sweep_mode == SWEEP_AUTO && small && persist_auto(hs)));
         if (S->persistent) {
             if (pt.size() >= (size_t)INT32_MAX) {
                 err = "persistent task queue too long";
@@ -889,13 +905,19 @@ selinv_status selinv_analyze(int64_t n, const int64_t *colptr, const int32_t *ro
     *out = nullptr;
     selinv_handle h = new (std::nothrow) selinv_handle_s();
     if (!h) return SELINV_E_NOMEM;
+    const int32_t symbolic = opts ? opts->symbolic : SELINV_SYMBOLIC_SYMMETRIZED;
+    if (symbolic != SELINV_SYMBOLIC_SYMMETRIZED && symbolic != SELINV_SYMBOLIC_EXACT) {
+        g_analyze_err = "opts->symbolic must be SELINV_SYMBOLIC_SYMMETRIZED or SELINV_SYMBOLIC_EXACT";
+        delete h;
+        return SELINV_E_INVALID_ARG;
+    }
     int32_t cap = opts ? opts->max_super : 0;
     int32_t relax = opts ? std::max<int32_t>(0, opts->relax) : 0;
     int32_t pad = opts ? std::min<int32_t>(100, std::max<int32_t>(0, opts->pad_pct)) : 0;
     if (cap <= 0 || cap > TRI_MAX_S) cap = TRI_MAX_S;
     selinv_status st;
     try {
-        st = analyze(h->P, n, colptr, rowind, perm, cap, relax, pad, h->err);
+        st = analyze(h->P, n, colptr, rowind, perm, cap, relax, pad, symbolic, h->err);
     } catch (const std::bad_alloc &) {
         st = SELINV_E_NOMEM;
         h->err = "host allocation failed in analyze";
@@ -1296,7 +1318,21 @@ selinv_status selinv_check_plan(selinv_handle h, int64_t *mismatches) {
     for (int32_t Q = 0; Q < P.ns; Q++)
         for (int32_t q = h->kids_ptr[Q]; q < h->kids_ptr[Q + 1]; q++) bad += P.sparent[h->kids[q]] != Q;
     bad += h->kids_ptr[P.ns] != (int32_t)std::count_if(P.sparent.begin(), P.sparent.end(), [](int32_t x) { return x >= 0; });
-    if (bad && h->err.empty()) h->err = "push maps inconsistent with R_L / R_U";
+    // levels: every supernode met by R_L(K) u R_U(K) lies on a shallower
+    // level, sparent(K) on level(K) - 1, and with one_top(K) no other
+    // supernode met lies there
+    for (int32_t K = 0; K < P.ns; K++) {
+        const int32_t lev = P.level[K], Pa = P.sparent[K];
+        bad += (Pa >= 0) ? P.level[Pa] != lev - 1 : lev != 0;
+        auto visit = [&](int32_t x) {
+            const int32_t J = P.supof[x];
+            bad += P.level[J] >= lev;
+            bad += P.one_top[K] && P.level[J] == lev - 1 && J != Pa;
+        };
+        for (int64_t a = P.rl_ptr[K]; a < P.rl_ptr[K + 1]; a++) visit(P.rl[a]);
+        for (int64_t b = P.ru_ptr[K]; b < P.ru_ptr[K + 1]; b++) visit(P.ru[b]);
+    }
+    if (bad && h->err.empty()) h->err = "push maps or levels inconsistent with R_L / R_U";
     *mismatches += bad;
     return SELINV_OK;
 }
@@ -1319,6 +1355,9 @@ selinv_status selinv_query(selinv_handle h, selinv_info *info) {
     info->max_gemm_m = P.max_gemm_m;
     info->max_gemm_n = P.max_gemm_n;
     info->max_gemm_k = P.max_gemm_k;
+    info->symbolic = P.symbolic;
+    info->nnz_l = P.tot_l;
+    info->nnz_u = P.tot_u;
     return SELINV_OK;
 }
 

@@ -45,14 +45,18 @@ class Info(C.Structure):
                 ("nlevels", C.c_int32), ("max_s", C.c_int32), ("max_c", C.c_int32), ("flops", C.c_double),
                 ("flops_gemm", C.c_double), ("bytes_min_fp64", C.c_double), ("bytes_min_fp32", C.c_double),
                 ("max_gemm_flops", C.c_double), ("max_gemm_m", C.c_int32), ("max_gemm_n", C.c_int32),
-                ("max_gemm_k", C.c_int32)]
+                ("max_gemm_k", C.c_int32), ("symbolic", C.c_int32), ("nnz_l", C.c_int64), ("nnz_u", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class Opts(C.Structure):
-    _fields_ = [("max_super", C.c_int32), ("relax", C.c_int32), ("pad_pct", C.c_int32)]
+    _fields_ = [("max_super", C.c_int32), ("relax", C.c_int32), ("pad_pct", C.c_int32), ("symbolic", C.c_int32)]
+
+
+# analysis forms: pattern of At + At^T (R_L = R_U), or the exact pattern of L and U
+SYMBOLIC = {"symmetrized": 0, "exact": 1}
 
 
 def _load():
@@ -119,7 +123,7 @@ def _prec(p):
 class SelInv:
     """One matrix: analyze (construction) -> factor -> run -> get*/export."""
 
-    def __init__(self, n, colptr, rowind, perm=None, max_super=0, relax=0, pad_pct=0):
+    def __init__(self, n, colptr, rowind, perm=None, max_super=0, relax=0, pad_pct=0, symbolic="symmetrized"):
         self._h = C.c_void_p()
         self.n = int(n)
         self._colptr = np.ascontiguousarray(colptr, dtype=np.int64)
@@ -129,7 +133,8 @@ class SelInv:
         if perm is not None:
             self._perm = np.ascontiguousarray(perm, dtype=np.int32)
             pp = _p(self._perm, C.c_int32)
-        opts = Opts(int(max_super), int(relax), int(pad_pct))
+        sym = SYMBOLIC[symbolic] if isinstance(symbolic, str) else int(symbolic)
+        opts = Opts(int(max_super), int(relax), int(pad_pct), sym)
         rc = _lib.selinv_analyze(self.n, _p(self._colptr, C.c_int64), _p(self._rowind, C.c_int32), pp,
                                  C.byref(opts), C.byref(self._h))
         if rc:

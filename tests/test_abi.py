@@ -6,6 +6,7 @@ import os
 import re
 
 import numpy as np
+import scipy.sparse as sp
 import pytest
 
 from oracle import Oracle
@@ -141,3 +142,125 @@ def test_plan_and_push_maps_consistent(si, name):
     s = si.SelInv(*args)
     assert s.check_plan() == 0
     s.close()
+
+
+# --------------------------------------------------------------------------
+# exact (unsymmetrized) analysis: C_L != C_U
+# --------------------------------------------------------------------------
+STRUCT_KEYS = ["perm", "xsup", "rl_ptr", "rl", "ru_ptr", "ru"]
+
+
+def _exact_same_as_oracle(si, n, cp, ri, perm, cap):
+    """Partition and block sets of the library's exact analysis equal the
+    oracle's exact mode (dense boolean elimination), bit for bit."""
+    s = si.SelInv(n, cp, ri, perm, cap, 0, 0, symbolic="exact")
+    o = Oracle(n, cp, ri, perm, cap, 0, 1, 0)
+    a, b = s.structure(), o.structure()
+    for k in STRUCT_KEYS:
+        assert np.array_equal(a[k], b[k]), k
+    assert s.info["symbolic"] == 1
+    assert s.check_plan() == 0
+    return s, a
+
+
+def _unequal_sets(st):
+    ns = len(st["xsup"]) - 1
+    return sum(not np.array_equal(st["rl"][st["rl_ptr"][K]:st["rl_ptr"][K + 1]],
+                                  st["ru"][st["ru_ptr"][K]:st["ru_ptr"][K + 1]]) for K in range(ns))
+
+
+@pytest.mark.parametrize("seed,n,dens,cap", [(0, 300, 0.01, 8), (1, 300, 0.02, 4), (2, 300, 0.005, 64),
+                                             (3, 250, 0.03, 1), (4, 300, 0.01, 1024), (5, 1, 0.0, 3),
+                                             (6, 2, 0.5, 1), (7, 600, 0.004, 5)])
+def test_exact_analysis_matches_oracle_random(si, seed, n, dens, cap):
+    cp, ri, _, _ = random_sparse(n, dens, seed)
+    perm = np.random.default_rng(seed).permutation(n).astype(np.int32)
+    s, st = _exact_same_as_oracle(si, n, cp, ri, perm, cap)
+    if n >= 100:
+        assert _unequal_sets(st) > 0  # R_L(K) != R_U(K) really occurs
+        sym = si.SelInv(n, cp, ri, perm, cap, 0, 0)
+        assert s.info["nnz_lu"] < sym.info["nnz_lu"]
+
+
+@pytest.mark.parametrize("lower", [True, False])
+def test_exact_analysis_triangular(si, lower):
+    """The paper's extreme case: a triangular A has L = I (or U diagonal), so
+    one of the two block-set families is empty, while symmetrizing the
+    pattern fills both."""
+    n = 400
+    cp, ri, _, _ = random_sparse(n, 0.02, 11, lower_only=lower, upper_only=not lower)
+    s, st = _exact_same_as_oracle(si, n, cp, ri, None, 16)
+    assert s.info["nnz_u" if lower else "nnz_l"] == 0
+    assert s.info["nnz_l" if lower else "nnz_u"] > 0
+    sym = si.SelInv(n, cp, ri, None, 16, 0, 0)
+    assert sym.info["nnz_lu"] > 5 * s.info["nnz_lu"]
+
+
+@pytest.mark.parametrize("keep", [0.0, 0.25, 1.0])
+def test_exact_analysis_upwind_grid(si, keep):
+    from workloads import config_upwind
+    w = config_upwind((40, 40), "box", keep, 3, 32, 16)
+    s, st = _exact_same_as_oracle(si, w.n, w.colptr, w.rowind, w.perm, w.max_super)
+    if keep < 1.0:
+        assert _unequal_sets(st) > 0
+    else:  # every coupling kept: a structurally symmetric pattern
+        assert _unequal_sets(st) == 0
+
+
+def test_exact_analysis_symmetric_pattern_equal_sets(si):
+    """On a structurally symmetric pattern the exact L and U^T share their
+    structure, so R_L(K) = R_U(K) for every supernode."""
+    w = config_c0()
+    s, st = _exact_same_as_oracle(si, w.n, w.colptr, w.rowind, w.perm, w.max_super)
+    assert _unequal_sets(st) == 0
+
+
+def test_exact_analysis_covers_fig2b_factors(si):
+    """A = L U for factors with the block pattern of the paper's Fig. 2 (b):
+    the exact analysis of A (natural order) must hold every nonzero of L and
+    U in its block pattern (unpivoted LU of A reproduces exactly these
+    factors), and matches the oracle's exact mode."""
+    from fig2b import fig2b_factors
+    _, _, _, _, _, _, L, U = fig2b_factors()
+    A = L @ U
+    n = A.shape[0]
+    m = sp.csc_matrix(np.where(np.abs(A) > 0, A, 0.0))
+    m.sort_indices()
+    cp, ri = m.indptr.astype(np.int64), m.indices.astype(np.int32)
+    s, st = _exact_same_as_oracle(si, n, cp, ri, None, 8)
+    xs = st["xsup"]
+    sup = np.searchsorted(xs, np.arange(n), side="right") - 1
+    for r, c in zip(*np.nonzero(L + U)):
+        I, J = sup[r], sup[c]
+        if I == J:
+            continue
+        if I > J:
+            assert r in st["rl"][st["rl_ptr"][J]:st["rl_ptr"][J + 1]]
+        else:
+            assert c in st["ru"][st["ru_ptr"][I]:st["ru_ptr"][I + 1]]
+
+
+def test_exact_analysis_levels_and_fusion_flags(si):
+    """Every supernode met by R_L(K) u R_U(K) lies on a shallower level
+    (host check of the plan, including the parent / push maps)."""
+    from workloads import config_upwind
+    w = config_upwind((96, 96), "box", 0.25, 1, 64, 32)
+    s = si.SelInv(w.n, w.colptr, w.rowind, w.perm, w.max_super, w.relax, w.pad_pct, symbolic="exact")
+    assert s.check_plan() == 0
+    st = s.structure()
+    xs, lev = st["xsup"], st["level"]
+    sup = np.searchsorted(xs, np.arange(w.n), side="right") - 1
+    for K in range(len(xs) - 1):
+        R = np.concatenate([st["rl"][st["rl_ptr"][K]:st["rl_ptr"][K + 1]],
+                            st["ru"][st["ru_ptr"][K]:st["ru_ptr"][K + 1]]])
+        if R.size:
+            assert lev[K] == lev[sup[R]].max() + 1
+        else:
+            assert lev[K] == 0
+
+
+def test_exact_option_errors(si):
+    cp = np.array([0, 2, 4], np.int64)
+    with pytest.raises(si.SelinvError) as e:
+        si.SelInv(2, cp, np.array([0, 1, 0, 1], np.int32), symbolic=2)
+    assert e.value.status == "INVALID_ARG"

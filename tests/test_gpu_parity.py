@@ -371,3 +371,155 @@ def test_c1_profiled_run_and_level_work(si, c1_pair):
     assert abs(got - want) <= 1e-9 * want
     assert sum(l["small_count"] for l in lev) > 0
     s.set_sweep_mode("auto")
+
+
+# --------------------------------------------------------------------------
+# exact (unsymmetrized) analysis: C_L != C_U
+# --------------------------------------------------------------------------
+def lib_and_oracle_exact(si, n, cp, ri, v, perm, cap):
+    """Library with the exact analysis against the oracle's exact mode: the
+    same partition and block sets, so the computed supersets must agree."""
+    s = si.SelInv(n, cp, ri, perm, cap, 0, 0, symbolic="exact")
+    assert s.check_plan() == 0
+    s.factor(v)
+    o = Oracle(n, cp, ri, perm, cap, 0, 1, 0).factor(v).selinv()
+    return s, o
+
+
+EXACT_CASES = [  # n, density, seed, cap, triangle
+    (1, 0.0, 0, 1, None),
+    (2, 0.5, 1, 1, None),
+    (37, 0.08, 2, 5, None),
+    (300, 0.01, 3, 16, None),
+    (400, 0.02, 4, 70, "lower"),   # U(K, R_U) empty everywhere
+    (400, 0.02, 5, 64, "upper"),   # L(R_L, K) empty everywhere
+    (300, 0.3, 6, 300, None),
+    (700, 0.004, 7, 3, None),
+]
+
+
+@pytest.mark.parametrize("case", EXACT_CASES, ids=[f"n{c[0]}_cap{c[3]}_{c[4]}" for c in EXACT_CASES])
+@pytest.mark.parametrize("prec", ["fp64", "mixed_fp32"])
+def test_exact_random_ragged(si, case, prec):
+    n, dens, seed, cap, tri = case
+    say("exact random", case, prec)
+    cp, ri, v, _ = random_sparse(n, dens, seed, lower_only=tri == "lower", upper_only=tri == "upper")
+    perm = None if tri else np.random.default_rng(seed).permutation(n).astype(np.int32)
+    s, o = lib_and_oracle_exact(si, n, cp, ri, v, perm, cap)
+    s.run(prec)
+    compare_superset(s, o, TOL[prec])
+
+
+@pytest.fixture(scope="module", params=[0.0, 0.25])
+def upwind_pair(si, request):
+    from workloads import config_upwind
+    w = config_upwind((64, 64), "box", request.param, 3, 64, 32)
+    say("upwind 64x64 setup keep", request.param)
+    s, o = lib_and_oracle_exact(si, w.n, w.colptr, w.rowind, w.values, w.perm, w.max_super)
+    return w, s, o
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed_fp32", "mixed_bf16x3"])
+def test_exact_upwind_whole_superset(si, upwind_pair, prec):
+    w, s, o = upwind_pair
+    say("upwind 64x64", prec)
+    s.run(prec)
+    en, ed = compare_superset(s, o, TOL[prec])
+    say("upwind 64x64", prec, "err_norm", en, "err_diag", ed)
+
+
+def test_exact_fig2b_factors_dense_inverse(si):
+    """A = L U with the factor pattern of the paper's Fig. 2 (b), natural
+    order: every computed entry equals the dense inverse."""
+    import scipy.sparse as sp
+    from fig2b import fig2b_factors
+    say("fig2b")
+    _, _, _, _, _, _, L, U = fig2b_factors()
+    A = L @ U
+    n = A.shape[0]
+    m = sp.csc_matrix(A)
+    m.sort_indices()
+    cp, ri = m.indptr.astype(np.int64), m.indices.astype(np.int32)
+    s, o = lib_and_oracle_exact(si, n, cp, ri, m.data.astype(np.float64), None, 4)
+    s.run("fp64")
+    compare_superset(s, o, TOL["fp64"])
+    r, c, v = s.export()
+    inv = np.linalg.inv(A)
+    assert np.abs(v - inv[r, c]).max() / np.abs(inv).max() < 1e-11
+
+
+@pytest.fixture(scope="module")
+def u1_pair(si):
+    """Full-size upwind grid (n = 65536): the library's exact analysis against
+    the oracle's symmetrized one.  Both compute exact entries of A^{-1}, so the
+    selected entries and every entry of the two supersets' intersection must
+    agree."""
+    from workloads import config_u1
+    w = config_u1()
+    say("u1 setup")
+    s = si.SelInv(w.n, w.colptr, w.rowind, w.perm, w.max_super, w.relax, w.pad_pct, symbolic="exact")
+    assert s.check_plan() == 0
+    s.factor(w.values)
+    o = Oracle(w.n, w.colptr, w.rowind, w.perm, w.max_super, w.relax, 0, w.pad_pct).factor(w.values).selinv()
+    return w, s, o
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed_fp32", "mixed_bf16x3"])
+def test_u1_exact_vs_symmetrized_oracle(si, u1_pair, prec):
+    w, s, o = u1_pair
+    say("u1", prec)
+    s.run(prec)
+    sel, ref = s.get_selected(), o.get_selected()
+    cols = np.repeat(np.arange(w.n), np.diff(w.colptr))
+    en, ed = errs(sel, ref, w.rowind, cols)
+    r1, c1, v1 = s.export()
+    r2, c2, v2 = o.export()
+    k1 = r1.astype(np.int64) * w.n + c1
+    k2 = r2.astype(np.int64) * w.n + c2
+    common, i1, i2 = np.intersect1d(k1, k2, assume_unique=True, return_indices=True)
+    assert common.size > 0.9 * k1.size
+    en2, ed2 = errs(v1[i1], v2[i2], r1[i1], c1[i1])
+    rr, cr = identity_residuals(w, sel)
+    say("u1", prec, "selected", en, ed, "common", en2, ed2, "identity", rr, cr)
+    assert max(en, ed, en2, ed2) <= TOL[prec]
+    assert max(rr, cr) <= (1e-10 if prec == "fp64" else 1e-4)
+
+
+def test_u1_exact_graph_replay_and_sweep_forms(si, u1_pair):
+    import torch
+    w, s, o = u1_pair
+    say("u1 graph")
+    s.run("fp64")
+    ref = s.get_selected()
+    assert s.sweep_is_persistent("fp64") == 0  # auto: level sweep for exact plans
+    st = torch.cuda.Stream()
+    for rep in range(3):
+        s.run("fp64", stream=st, graph=True)
+        assert np.array_equal(s.get_selected(), ref), rep
+        torch.cuda.synchronize()
+        s.run("fp64")
+        assert np.array_equal(s.get_selected(), ref)
+    s.set_sweep_mode("persistent")
+    with pytest.raises(si.SelinvError) as e:
+        s.run("fp64")
+    assert e.value.status == "INVALID_ARG"
+    s.set_sweep_mode("auto")
+    s.run("fp64")
+    assert np.array_equal(s.get_selected(), ref)
+
+
+def test_exact_batch_matches_single_runs(si):
+    from workloads import config_upwind
+    ws = [config_upwind((48, 48), "box", 0.25, 10 + m, 64, 32) for m in range(3)]
+    say("exact batch")
+    mats = [si.SelInv(w.n, w.colptr, w.rowind, w.perm, w.max_super, w.relax, w.pad_pct,
+                      symbolic="exact").factor(w.values) for w in ws]
+    refs = []
+    for m in mats:
+        m.run("fp64")
+        refs.append(m.get_selected())
+    b = si.Batch(mats)
+    b.run("fp64")
+    for m, ref in zip(mats, refs):
+        assert np.array_equal(m.get_selected(), ref)
+    b.close()

@@ -150,7 +150,8 @@ def _assemble(n, rows, cols, vals, margin):
 
 
 def stencil_csc(dims, kind: str, value_mode: str, margin: float, seed=None,
-                asym: float = 0.3, delta: float = 0.0, jitter: float = 0.0):
+                asym: float = 0.3, delta: float = 0.0, jitter: float = 0.0,
+                keep: float = 0.0):
     """Assemble a grid stencil matrix.
 
     value_mode:
@@ -159,6 +160,13 @@ def stencil_csc(dims, kind: str, value_mode: str, margin: float, seed=None,
       'sym_perturbed': per unordered neighbour pair a symmetric weight
                     w ~ U[-1, 0], plus an independent eps ~ U[-delta, delta]
                     for each of the two ordered entries.
+      'upwind':     one-sided (first-order upwind) convection along the flow
+                    b = (1, 1/2, 1/4): row i couples to every upstream
+                    neighbour i+d (d.b < 0) with -(1 + asym) + U[-jitter,
+                    jitter], and to a downstream neighbour (d.b > 0) only with
+                    probability ``keep`` (seeded Bernoulli per entry), value
+                    -(1 - asym) + U[-jitter, jitter].  The pattern is not
+                    symmetric: keep = 0 gives a permuted triangular matrix.
     The diagonal is the row sum of |off-diagonals| plus ``margin`` (strict row
     diagonal dominance, so an unpivoted LU exists and is stable).
     """
@@ -188,6 +196,20 @@ def stencil_csc(dims, kind: str, value_mode: str, margin: float, seed=None,
             rows += [i, j]
             cols += [j, i]
             vals += [w + e_ij, w + e_ji]
+    elif value_mode == "upwind":
+        flow = (1.0, 0.5, 0.25)
+        for off in _offsets(ndim, kind):
+            i, j = _pairs(dims3, off)
+            down = sum(o * b for o, b in zip(off, flow)) > 0
+            if down:
+                take = rng.random(i.size) < keep
+                i, j = i[take], j[take]
+            v = np.full(i.size, -(1.0 - asym) if down else -(1.0 + asym))
+            if jitter:
+                v = v + rng.uniform(-jitter, jitter, size=i.size)
+            rows.append(i)
+            cols.append(j)
+            vals.append(v)
     else:
         raise ValueError(value_mode)
     return _assemble(n, rows, cols, vals, margin)
@@ -247,12 +269,36 @@ def config_c4() -> Workload:
                           delta=0.15)
 
 
+def config_upwind(dims=(64, 64), kind: str = "box", keep: float = 0.25, seed: int = 0,
+                  max_super: int = 128, leaf: int = 64) -> Workload:
+    """Structurally non-symmetric grid stencil (one-sided upwind couplings,
+    downstream ones kept with probability ``keep``), nested-dissection order."""
+    name = "u" + "x".join(str(d) for d in dims)
+    pts = {("star", 2): 5, ("box", 2): 9, ("star", 3): 7, ("box", 3): 27}[(kind, len(dims))]
+    return _grid_workload(name, tuple(dims), kind, "upwind", 0.1, seed, max_super, leaf,
+                          f"{len(dims)}D {'x'.join(str(d) for d in dims)} {pts}-point upwind "
+                          f"(downstream kept with p={keep}), n={int(np.prod(dims))}, cap {max_super}",
+                          keep=keep, jitter=0.05)
+
+
+def config_u1() -> Workload:
+    """2D 256x256 9-point upwind stencil, downstream couplings kept with p = 0.25:
+    the C1 grid and ordering with a structurally non-symmetric pattern."""
+    return config_upwind((256, 256), "box", 0.25, 0, 128, 64)
+
+
+def config_u4() -> Workload:
+    """3D 64^3 27-point upwind stencil, downstream couplings kept with p = 0.25:
+    the C4 grid and ordering with a structurally non-symmetric pattern."""
+    return config_upwind((64, 64, 64), "box", 0.25, 0, 512, 64)
+
+
 CONFIG_NAMES = ("c0", "c1", "c2", "c3", "c4")
 
 
 def get_config(name: str):
     return {"c0": config_c0, "c1": config_c1, "c2": config_c2, "c3": config_c3,
-            "c4": config_c4}[name]()
+            "c4": config_c4, "u1": config_u1, "u4": config_u4}[name]()
 
 
 # ----------------------------------------------------------------------------
