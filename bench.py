@@ -34,7 +34,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="c1", choices=["c0", "c1", "c2", "c4"])
+    ap.add_argument("--config", default="c1", choices=["c0", "c1", "c2", "c4", "u1", "u4"])
+    ap.add_argument("--symbolic", default=None, choices=["symmetrized", "exact"],
+                    help="analysis form (default: symmetrized for c*, exact for the upwind u* configs)")
     ap.add_argument("--precision", default=None, help="fp64 | mixed_fp32 | mixed_bf16x3 (default: per config)")
     ap.add_argument("--mixed", default="mixed_fp32", help="mixed form reported beside the main one")
     ap.add_argument("--no-graph", action="store_true")
@@ -51,6 +53,8 @@ WORKLOADS = {
     "c1": "2D 256x256 9-point asymmetric stencil, n=65536, ND, supernodes<=128",
     "c2": "3D 48^3 7-point asymmetric convection-diffusion, n=110592, ND, supernodes<=256",
     "c4": "3D 64^3 27-point asymmetric stencil, n=262144, ND, supernodes<=512",
+    "u1": "2D 256x256 9-point upwind stencil (non-symmetric pattern), n=65536, ND, supernodes<=128",
+    "u4": "3D 64^3 27-point upwind stencil (non-symmetric pattern), n=262144, ND, supernodes<=512",
 }
 
 
@@ -249,7 +253,8 @@ def main():
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()  # graphs cannot be captured on the legacy null stream
     t0 = time.perf_counter()
-    s = SelInv(w.n, w.colptr, w.rowind, w.perm, w.max_super, w.relax, w.pad_pct)
+    symbolic = args.symbolic or ("exact" if args.config.startswith("u") else "symmetrized")
+    s = SelInv(w.n, w.colptr, w.rowind, w.perm, w.max_super, w.relax, w.pad_pct, symbolic=symbolic)
     s.set_sweep_mode(args.sweep)
     t_an = time.perf_counter() - t0
     t0 = time.perf_counter()
@@ -294,6 +299,7 @@ def main():
         "dtype": "f64" if prec == "fp64" else ("f32" if prec == "mixed_fp32" else "bf16x3/f32"),
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.config], "n": w.n, "nnz": w.nnz, "precision": prec,
+                   "symbolic": symbolic, "nnz_lu": info["nnz_lu"],
                    "supernodes": info["nsuper"], "levels": info["nlevels"], "gflop": F / 1e9,
                    "hip_graph": graph, "sweep": "persistent" if s.sweep_is_persistent(prec) == 1 else "levels",
                    "parallelism": "single GPU"},
@@ -307,7 +313,7 @@ def main():
         res["mixed"] = mixed
         res["mixed_speedup_vs_main"] = ms / mixed["ms_per_matrix"]
 
-    if not args.no_cpu_baseline and args.config in ("c0", "c1"):
+    if not args.no_cpu_baseline and args.config in ("c0", "c1", "u1"):
         o, sel_ref, t_cpu, reps, threads = cpu_baseline(w, args.cpu_seconds)
         res["cpu_baseline"] = {"value": F / t_cpu / 1e9, "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
                                "sample": f"full matrix, oracle steps 2-6 (selected inversion + extraction), "

@@ -83,8 +83,15 @@ typedef enum {
  *       supernodes of L), cut every max_super columns; R_L(K) and R_U(K) are
  *       the row set of L(:, K) and the column set of U(K, :) beyond K, closed
  *       under the block fill R_L(K) x R_U(K) of every earlier supernode, so
- *       that Theorem 1 holds blockwise.  relax and pad_pct are ignored and the
- *       ordering is used as given.  Sweeps of such handles run level by level
+ *       that Theorem 1 holds blockwise.  The ordering is used as given.
+ *       relax > 0: every maximal subtree of the elimination tree of
+ *       At + At^T with at most relax columns that occupies a contiguous
+ *       column range becomes one supernode; pad_pct > 0: outside those, a
+ *       column also joins the run before it when it has that run's last
+ *       column as its only child and the padding estimate of the exact
+ *       counts stays within pad_pct percent (as for the symmetrized form,
+ *       with the rows of L and the columns of U counted separately).
+ *       relax = pad_pct = 0: the fundamental supernodes alone.  Sweeps of such handles run level by level
  *       (the persistent form needs the symmetrized analysis). */
 typedef enum {
     SELINV_SYMBOLIC_SYMMETRIZED = 0,

@@ -245,7 +245,9 @@ int32_t first_common(const int32_t *a, int64_t na, const int32_t *b, int64_t nb,
 // row that J would reach, so the pushes of J stop at that m.
 void fundamental_starts(int64_t n, const std::vector<int64_t> &lptr, const std::vector<int32_t> &lidx,
                         const std::vector<int64_t> &uptr, const std::vector<int32_t> &uidx,
-                        std::vector<int32_t> &starts) {
+                        std::vector<int32_t> &starts, std::vector<int64_t> &cntL, std::vector<int64_t> &cntU) {
+    cntL.assign(n, 0);
+    cntU.assign(n, 0);
     std::vector<int64_t> fl_ptr(1, 0), fu_ptr(1, 0);
     std::vector<int32_t> fl, fu;
     SlotLists toL, toU;  // finished runs whose FL a column (FU a row) receives
@@ -311,6 +313,8 @@ void fundamental_starts(int64_t n, const std::vector<int64_t> &lptr, const std::
             for (auto it = pu; it != prevU.end(); ++it) addU(*it);
         std::sort(curL.begin(), curL.end());
         std::sort(curU.begin(), curU.end());
+        cntL[k] = (int64_t)curL.size();
+        cntU[k] = (int64_t)curU.size();
         const bool join = l_sub && (size_t)(prevL.end() - pl) == curL.size() && std::equal(pl, prevL.end(), curL.begin());
         if (!join) {
             if (k > 0) finish(k - 1);
@@ -319,6 +323,68 @@ void fundamental_starts(int64_t n, const std::vector<int64_t> &lptr, const std::
         std::swap(prevL, curL);
         std::swap(prevU, curU);
     }
+}
+
+// Relaxation of the exact form (section 2: relaxed supernodes of nearly
+// identical columns).  Any partition into column ranges is valid, since the
+// block sets are closed under the block fill whatever the partition; merged
+// columns store explicit zeros.  On the elimination tree of At + At^T (in the
+// given order):
+//   * every maximal subtree with at most `relax` columns that occupies a
+//     contiguous column range becomes one supernode;
+//   * elsewhere column j stays joined to j-1 where the fundamental rule
+//     joined it, and also joins the run [f, j-1] when j-1 is the only child
+//     of j and the padding estimate of the exact counts (cntL: rows of L
+//     below the diagonal, cntU: columns of U past it), with s = j-f+1,
+//       Z = s cntL(j) - sum_t cntL(t) + s cntU(j) - sum_t cntU(t) + s(s-1),
+//     stays at most pad_pct percent of s (cntL(j) + cntU(j) + 2 s).
+void relax_exact(int64_t n, const int64_t *colptr, const int32_t *rowind, const std::vector<int32_t> &q,
+                 int32_t relax, int32_t pad_pct, const std::vector<int64_t> &cntL,
+                 const std::vector<int64_t> &cntU, std::vector<int32_t> &starts) {
+    std::vector<int64_t> aptr;
+    std::vector<int32_t> adj, parent;
+    symmetric_adjacency(n, colptr, rowind, q, aptr, adj);
+    etree(n, aptr, adj, parent);
+    std::vector<int64_t> size(n, 1);
+    std::vector<int32_t> lo(n), nkids(n, 0);  // lo: smallest column of the subtree
+    for (int64_t j = 0; j < n; j++) lo[j] = (int32_t)j;
+    for (int64_t j = 0; j < n; j++)
+        if (parent[j] >= 0) {
+            size[parent[j]] += size[j];
+            lo[parent[j]] = std::min(lo[parent[j]], lo[j]);
+            nkids[parent[j]]++;
+        }
+    auto ok = [&](int64_t v) { return size[v] <= relax && v - lo[v] + 1 == size[v]; };
+    std::vector<int32_t> root(n, -1);
+    for (int64_t v = 0; v < n; v++)
+        if (ok(v) && (parent[v] < 0 || !ok(parent[v])))
+            for (int64_t u = lo[v]; u <= v; u++) root[u] = (int32_t)v;
+    std::vector<char> fund_start(n + 1, 0);
+    for (int32_t j : starts) fund_start[j] = 1;
+    std::vector<int32_t> out;
+    int64_t first = 0, sumL = 0, sumU = 0;
+    for (int64_t j = 0; j < n; j++) {
+        bool join = false;
+        if (j > 0) {
+            if (root[j] >= 0 || root[j - 1] >= 0) {
+                join = root[j] >= 0 && root[j] == root[j - 1];
+            } else if (!fund_start[j]) {
+                join = true;
+            } else if (parent[j - 1] == j && nkids[j] == 1) {
+                const int64_t sz = j - first + 1;
+                const int64_t Z = sz * cntL[j] - (sumL + cntL[j]) + sz * cntU[j] - (sumU + cntU[j]) + sz * (sz - 1);
+                join = 100 * Z <= int64_t(pad_pct) * sz * (cntL[j] + cntU[j] + 2 * sz);
+            }
+        }
+        if (!join) {
+            out.push_back((int32_t)j);
+            first = j;
+            sumL = sumU = 0;
+        }
+        sumL += cntL[j];
+        sumU += cntU[j];
+    }
+    starts.swap(out);
 }
 
 // R_L(K) and R_U(K) of the exact form for the partition in P.xsup: the rows
@@ -704,8 +770,10 @@ selinv_status analyze(Plan &P, int64_t n, const int64_t *colptr, const int32_t *
     if (symbolic == SELINV_SYMBOLIC_EXACT) {
         std::vector<int64_t> lptr, uptr;
         std::vector<int32_t> lidx, uidx, starts;
+        std::vector<int64_t> cntL, cntU;
         split_pattern(n, colptr, rowind, P.q, lptr, lidx, uptr, uidx);
-        fundamental_starts(n, lptr, lidx, uptr, uidx, starts);
+        fundamental_starts(n, lptr, lidx, uptr, uidx, starts, cntL, cntU);
+        if (relax > 0 || pad_pct > 0) relax_exact(n, colptr, rowind, P.q, relax, pad_pct, cntL, cntU, starts);
         starts.push_back((int32_t)n);
         cut_partition(P, starts, max_super);
         exact_block_sets(P, lptr, lidx, uptr, uidx);

@@ -264,3 +264,22 @@ def test_exact_option_errors(si):
     with pytest.raises(si.SelinvError) as e:
         si.SelInv(2, cp, np.array([0, 1, 0, 1], np.int32), symbolic=2)
     assert e.value.status == "INVALID_ARG"
+
+
+def test_exact_relaxed_partition(si):
+    """Relaxation of the exact form (leaf subtrees, padded chains): any
+    column-range partition is closed by the block fill, so the plan stays
+    consistent; the relaxed form has far fewer supernodes and levels than the
+    fundamental one and still stores less than the symmetrized form."""
+    from workloads import config_upwind
+    w = config_upwind((96, 96), "box", 0.25, 2, 64, 32)
+    fund = si.SelInv(w.n, w.colptr, w.rowind, w.perm, w.max_super, 0, 0, symbolic="exact")
+    rel = si.SelInv(w.n, w.colptr, w.rowind, w.perm, w.max_super, w.relax, w.pad_pct, symbolic="exact")
+    sym = si.SelInv(w.n, w.colptr, w.rowind, w.perm, w.max_super, w.relax, 5)
+    assert rel.check_plan() == 0
+    assert rel.info["nsuper"] < fund.info["nsuper"] // 4
+    assert rel.info["nlevels"] < fund.info["nlevels"] // 2
+    assert fund.info["nnz_lu"] <= rel.info["nnz_lu"] < sym.info["nnz_lu"]
+    st = rel.structure()
+    assert np.array_equal(st["perm"], w.perm)  # the exact form keeps the ordering
+    assert _unequal_sets(st) > 0
