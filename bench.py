@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--mixed", default="mixed_fp32", help="mixed form reported beside the main one")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--sweep", default="auto", choices=["auto", "levels", "persistent"])
+    ap.add_argument("--no-tune", action="store_true", help="size policy instead of the autotuner's choices")
+    ap.add_argument("--tune-reps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="bound on the oracle's CPU time")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -265,6 +267,18 @@ def main():
     out = torch.empty(w.nnz, dtype=torch.float64, device="cuda")
     graph = not args.no_graph
 
+    # autotuner (setup, untimed): launch choices measured on this device
+    tuning = {"tuned": False}
+    precs = [prec] + ([args.mixed] if args.mixed and args.mixed != prec else [])
+    if not args.no_tune:
+        from paper_1708_04539_amd.autotune import describe
+        t0 = time.perf_counter()
+        for p in precs:
+            ms_pol, ms_tun = s.tune(p, args.tune_reps, stream)
+            tuning[p] = dict(describe(s.get_tuning(p)), ms_policy_graph=ms_pol, ms_tuned_graph=ms_tun)
+        tuning["tuned"] = True
+        tuning["tune_s"] = time.perf_counter() - t0
+
     dev_s, wall_s = timed_steps(s, prec, args.steps, args.warmup, graph, out, stream)
     ms = 1e3 * dev_s / args.steps
     value = F / (dev_s / args.steps) / 1e9
@@ -304,7 +318,8 @@ def main():
                    "hip_graph": graph, "sweep": "persistent" if s.sweep_is_persistent(prec) == 1 else "levels",
                    "parallelism": "single GPU"},
         "wall_s_timed": wall_s,
-        "setup_s": {"analyze": t_an, "factor_host_lu_and_h2d": t_fa},
+        "setup_s": {"analyze": t_an, "factor_host_lu_and_h2d": t_fa, "tune": tuning.get("tune_s", 0.0)},
+        "tuning": tuning,
         "phases_ms": {k: v for k, v in ph.items() if k.endswith("_ms")},
         "phase_note": "phases from HIP events around each launch class in separate eager runs",
         "roofline": roof,

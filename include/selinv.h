@@ -178,6 +178,47 @@ selinv_status selinv_run_graph(selinv_handle h, selinv_precision prec, void *str
  * handle.  selinv_sweep_is_persistent() tells which form the last built sweep
  * of that precision uses (-1: none built yet). */
 selinv_status selinv_set_sweep_mode(selinv_handle h, int32_t mode);
+
+/* Autotuner (the section on inter-supernode parallelism leaves the schedule
+ * of a level's supernodes to the implementation).  Measures the launch
+ * choices of the level sweep of one precision on the current device and on
+ * `stream`, and keeps the fastest for this handle:
+ *   - the output tile edge (32, 64 or 128) of every grouped-GEMM launch class:
+ *     the diagonal-block inversion rounds, the normalisation, the diagonal
+ *     initialisation, and per level the step-3/5 launch and the step-4
+ *     launch.  Each candidate edge runs over the whole sweep with per-launch
+ *     HIP events; every class keeps its fastest edge;
+ *   - per level made only of small supernodes, the fused small-supernode
+ *     launch or the per-phase launches;
+ *   - with the symmetrized analysis and sweep mode 0, the level sweep or the
+ *     persistent sweep.
+ * Each configuration runs reps + 1 times (the first untimed; 1 <= reps <=
+ * 100) and counts its fastest run: per-launch times from eager runs with
+ * events, whole-sweep comparisons from replays of the sweep's HIP graph.  When the measured choices are not faster
+ * than the built-in size policy, the policy is kept.  ms_policy and ms_tuned
+ * (nullable) receive the two sweep times.  Needs a factored handle; the runs
+ * leave the results of an ordinary run behind.  Batches use the size policy. */
+selinv_status selinv_tune(selinv_handle h, selinv_precision prec, int32_t reps, void *stream,
+                          double *ms_policy, double *ms_tuned);
+
+/* The tuning table of `prec` as int32 values:
+ *   [1, nlevels, sweep form (0: the handle's mode, 1: levels, 2: persistent),
+ *    tile of the inversion rounds, of the normalisation, of the diagonal
+ *    initialisation, then for every level d = 0 .. nlevels-1: tile of steps
+ *    3+5, tile of step 4, 1 if the level's small supernodes use the per-phase
+ *    launches],
+ * tile 0 meaning the size policy.  *count receives 6 + 3 nlevels (0 when the
+ * handle is untuned; nothing written); out = NULL queries the count;
+ * cap < count gives SELINV_E_INVALID_ARG. */
+selinv_status selinv_get_tuning(selinv_handle h, selinv_precision prec, int32_t *out, int32_t cap,
+                                int32_t *count);
+
+/* Installs a table of that layout (a cached one, say); count = 0 returns to
+ * the size policy.  A table that does not fit the handle (layout, level
+ * count, tile edges, or the persistent form with the exact analysis) gives
+ * SELINV_E_INVALID_ARG and changes nothing.  The work lists of `prec` are
+ * rebuilt at the next run. */
+selinv_status selinv_set_tuning(selinv_handle h, selinv_precision prec, const int32_t *in, int32_t count);
 int32_t selinv_sweep_is_persistent(selinv_handle h, selinv_precision prec);
 
 /* Batches: several factored handles processed by one level sweep, levels

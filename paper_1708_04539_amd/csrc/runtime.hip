@@ -102,6 +102,18 @@ struct Sweep {
 
 enum : int { SWEEP_AUTO = 0, SWEEP_LEVELS = 1, SWEEP_PERSISTENT = 2 };
 
+// Measured launch choices of one handle for one precision (selinv_tune): the
+// tile edge of every launch class of grouped GEMMs (0: the size policy of
+// emit_launch), per level whether a level made only of small supernodes
+// keeps the fused small-supernode launch, and the sweep form.
+struct Tuning {
+    bool set = false;
+    int tri = 0, norm = 0, dt = 0;  // prologue: doubling rounds, normalisation, diagonal init
+    std::vector<int> t35, t4;       // per level: steps 3+5, step 4 (+ the next level's gather)
+    std::vector<char> no_small;     // per level: 1 = per-phase launches for its small supernodes
+    int sweep = SWEEP_AUTO;         // SWEEP_LEVELS / SWEEP_PERSISTENT, or the handle's own mode
+};
+
 constexpr int NPREC = 3;
 
 inline int elem_bytes(int prec) { return prec == SELINV_FP64 ? 8 : 4; }
@@ -137,6 +149,7 @@ struct selinv_handle_s {
     hipStream_t own_stream = nullptr;
     bool profiling = false;
     int sweep_mode = SWEEP_AUTO;
+    Tuning tune[NPREC];
     std::vector<hipEvent_t> events;
     std::vector<double> times;
 };
@@ -212,7 +225,7 @@ void add_tiles(std::vector<GemmTile> &tiles, int prob, int M, int N, int T) {
 // launches large enough to fill the device a few times over and wasting
 // little of their area.
 void emit_launch(const std::vector<GemmProb> &probs, size_t first, std::vector<GemmTile> &tiles, Range &r,
-                 bool allow128 = false) {
+                 bool allow128 = false, int forced = 0) {
     double area = 0, t128 = 0, t64 = 0;
     for (size_t q = first; q < probs.size(); q++) {
         const double M = probs[q].M, N = probs[q].N;
@@ -221,7 +234,9 @@ void emit_launch(const std::vector<GemmProb> &probs, size_t first, std::vector<G
         t64 += std::ceil(M / 64) * std::ceil(N / 64);
     }
     r.tile = GEMM_TILE_64;
-    if (t64 < kTile32Below)
+    if (forced == GEMM_TILE_32 || forced == GEMM_TILE_64 || forced == GEMM_TILE_128)
+        r.tile = forced;  // a measured choice (selinv_tune)
+    else if (t64 < kTile32Below)
         r.tile = GEMM_TILE_32;
     else if (allow128 && t128 >= kTile128From && area / (t128 * 128 * 128) >= 0.75 * area / (t64 * 64 * 64))
         r.tile = GEMM_TILE_128;
@@ -298,7 +313,11 @@ bool persist_auto(const std::vector<selinv_handle> &hs) {
 
 // Build the work lists of one sweep over a set of factored handles.
 selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, int sweep_mode, std::unique_ptr<Sweep> &out,
-                          std::string &err) {
+                          std::string &err, const Tuning *tn = nullptr) {
+    if (tn && !tn->set) tn = nullptr;
+    auto t35_of = [&](int d) { return tn && d < (int)tn->t35.size() ? tn->t35[d] : 0; };
+    auto t4_of = [&](int d) { return tn && d < (int)tn->t4.size() ? tn->t4[d] : 0; };
+    if (tn && sweep_mode == SWEEP_AUTO && tn->sweep != SWEEP_AUTO) sweep_mode = tn->sweep;
     std::unique_ptr<Sweep> S(new Sweep());
     S->prec = prec;
     const int e = elem_bytes(prec);
@@ -425,7 +444,7 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, int sweep_mo
                     }
                 }
                 Range rr;
-                emit_launch(probs, first0, tiles, rr);
+                emit_launch(probs, first0, tiles, rr, false, tn ? tn->tri : 0);
                 PR.tri_rounds.push_back(rr);
             }
         }
@@ -450,7 +469,7 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, int sweep_mo
         // FP32 normalised panels and need a second kernel for the FP64
         // diagonal.
         if (prec != SELINV_FP64) {
-            emit_launch(probs, first, tiles, PR.norm);
+            emit_launch(probs, first, tiles, PR.norm, false, tn ? tn->norm : 0);
             first = probs.size();
         }
         for (size_t mi = 0; mi < hs.size(); mi++) {
@@ -463,7 +482,10 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, int sweep_mo
                          nullptr, 1, r.s, r.s, r.s, 1.0, 0.0, &X, 8, 8);
             }
         }
-        emit_launch(probs, first, tiles, prec == SELINV_FP64 ? PR.norm : PR.dt);
+        if (prec == SELINV_FP64)
+            emit_launch(probs, first, tiles, PR.norm, false, tn ? tn->norm : 0);
+        else
+            emit_launch(probs, first, tiles, PR.dt, false, tn ? tn->dt : 0);
     }
     if (S->split > 0) {
         HIPCHK(err, hipStreamCreateWithFlags(&S->side, hipStreamNonBlocking), "create side stream");
@@ -498,6 +520,9 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, int sweep_mo
         for (int d = 0; d < hs[mi]->P.nlevels; d++)
             for (int32_t K : hs[mi]->P.levels[d])
                 if (!small_dims(hs[mi]->sn[K])) level_small[d] = 0;
+    if (tn)
+        for (int d = 0; d < depth && d < (int)tn->no_small.size(); d++)
+            if (tn->no_small[d]) level_small[d] = 0;
     int cur_level = 0;
     auto is_small = [&](const SnRec &r) { return level_small[cur_level] && small_dims(r); };
     // The gather of a level runs in the step-4 launch of the level above when
@@ -563,7 +588,7 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, int sweep_mo
                     (pass == 0 ? S->lev_flops35[d] : S->lev_small_flops[d]) += 4.0 * r.s * (double)r.cl * r.cu;
                 }
             }
-            if (pass == 0) emit_launch(probs, first, tiles, S->g35[d], mode_of(prec) == CMP_BF16X3);
+            if (pass == 0) emit_launch(probs, first, tiles, S->g35[d], mode_of(prec) == CMP_BF16X3, t35_of(d));
         }
         // step 4
         for (int pass = 0; pass < 2; pass++) {
@@ -586,7 +611,7 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, int sweep_mo
                     (pass == 0 ? S->lev_flops4[d] : S->lev_small_flops[d]) += 2.0 * r.s * (double)r.s * r.cu;
                 }
             }
-            if (pass == 0) emit_launch(probs, first, tiles, S->g4[d], mode_of(prec) == CMP_BF16X3);
+            if (pass == 0) emit_launch(probs, first, tiles, S->g4[d], mode_of(prec) == CMP_BF16X3, t4_of(d));
         }
         S->g4gat[d].off = gts.size();
         if (d + 1 < depth && S->fused[d + 1]) {
@@ -1024,7 +1049,7 @@ static selinv_status check_run(selinv_handle h, int prec) {
 static selinv_status ensure_sweep(selinv_handle h, int prec) {
     if (h->sweep[prec]) return SELINV_OK;
     std::vector<selinv_handle> one{h};
-    return build_sweep(one, prec, h->sweep_mode, h->sweep[prec], h->err);
+    return build_sweep(one, prec, h->sweep_mode, h->sweep[prec], h->err, &h->tune[prec]);
 }
 
 selinv_status selinv_run(selinv_handle h, selinv_precision prec, void *stream) {
@@ -1132,6 +1157,228 @@ selinv_status selinv_timings(selinv_handle h, double *ms, int32_t count) {
         HIPCHK(h->err, hipEventElapsedTime(&t, h->events[i], h->events[i + 1]), "elapsed");
         ms[i] = t;
     }
+    return SELINV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// autotuner
+// ---------------------------------------------------------------------------
+static void drop_sweep(selinv_handle h, int prec) {
+    if (h->last_sweep == h->sweep[prec].get()) h->last_sweep = nullptr;
+    h->sweep[prec].reset();
+}
+
+// Runs the sweep of `prec` reps + 1 times (the first untimed) under the
+// handle's current tuning.  total: fastest run in ms (HIP events on `s`
+// around a replay of the sweep's HIP graph, or around the eager launches of a
+// profiled run); phase (profiled runs): fastest time of every event interval
+// of the profiled sweep.
+static selinv_status tune_measure(selinv_handle h, int prec, hipStream_t s, int reps, bool profiled, double &total,
+                                  std::vector<double> *phase) {
+    drop_sweep(h, prec);
+    selinv_status st = ensure_sweep(h, prec);
+    if (st) return st;
+    const bool was = h->profiling;
+    h->profiling = profiled;
+    hipEvent_t a = nullptr, b = nullptr;
+    auto done = [&](selinv_status r) {
+        h->profiling = was;
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+        return r;
+    };
+    hipError_t ec = hipEventCreate(&a);
+    if (ec == hipSuccess) ec = hipEventCreate(&b);
+    if (ec != hipSuccess) return done(dev_fail(h->err, ec, "hipEventCreate"));
+    const int nint = 3 + 4 * (int)h->sweep[prec]->gat.size();
+    total = 1e300;
+    if (phase) phase->assign(nint, 1e300);
+    std::vector<double> t(nint);
+    hipError_t e;
+    for (int r = 0; r <= reps; r++) {
+        if ((e = hipEventRecord(a, s)) != hipSuccess) return done(dev_fail(h->err, e, "event record"));
+        st = profiled ? selinv_run(h, (selinv_precision)prec, s) : selinv_run_graph(h, (selinv_precision)prec, s);
+        if (st) return done(st);
+        if ((e = hipEventRecord(b, s)) != hipSuccess) return done(dev_fail(h->err, e, "event record"));
+        if ((e = hipEventSynchronize(b)) != hipSuccess) return done(dev_fail(h->err, e, "event sync"));
+        if (r == 0) continue;
+        float ms = 0;
+        if ((e = hipEventElapsedTime(&ms, a, b)) != hipSuccess) return done(dev_fail(h->err, e, "elapsed"));
+        total = std::min(total, (double)ms);
+        if (phase) {
+            if ((st = selinv_timings(h, t.data(), nint))) return done(st);
+            for (int i = 0; i < nint; i++) (*phase)[i] = std::min((*phase)[i], t[i]);
+        }
+    }
+    return done(SELINV_OK);
+}
+
+selinv_status selinv_tune(selinv_handle h, selinv_precision prec, int32_t reps, void *stream, double *ms_policy,
+                          double *ms_tuned) {
+    selinv_status st = check_run(h, prec);
+    if (st) return st;
+    if (reps < 1 || reps > 100) {
+        h->err = "reps must be in 1..100";
+        return SELINV_E_INVALID_ARG;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (!s) {  // graphs are not captured on the legacy null stream
+        if (!h->own_stream) HIPCHK(h->err, hipStreamCreateWithFlags(&h->own_stream, hipStreamNonBlocking), "stream");
+        s = h->own_stream;
+    }
+    const int L = h->P.nlevels;
+    const bool can_persist = h->P.symbolic == SELINV_SYMBOLIC_SYMMETRIZED && h->sweep_mode == SWEEP_AUTO;
+    // the size policy, in the handle's own sweep form
+    h->tune[prec] = Tuning();
+    double t_policy = 0, t = 0;
+    if ((st = tune_measure(h, prec, s, reps, false, t_policy, nullptr))) return st;
+
+    // 1. tile edge of every launch class: the whole level sweep profiled once
+    //    per candidate edge, every class keeps its fastest edge
+    Tuning best;
+    best.set = true;
+    best.t35.assign(L, 0);
+    best.t4.assign(L, 0);
+    best.no_small.assign(L, 0);
+    best.sweep = h->sweep_mode == SWEEP_AUTO ? SWEEP_LEVELS : SWEEP_AUTO;
+    const int cand[3] = {GEMM_TILE_32, GEMM_TILE_64, GEMM_TILE_128};
+    std::vector<double> bt(3 + 2 * L, 1e300);
+    std::vector<double> ph;
+    for (int c : cand) {
+        Tuning tn = best;
+        tn.tri = tn.norm = tn.dt = c;
+        std::fill(tn.t35.begin(), tn.t35.end(), c);
+        std::fill(tn.t4.begin(), tn.t4.end(), c);
+        tn.sweep = SWEEP_LEVELS;
+        h->tune[prec] = tn;
+        if ((st = tune_measure(h, prec, s, reps, true, t, &ph))) return st;
+        auto keep = [&](int k, double v, int &slot) {
+            if (v < bt[k]) {
+                bt[k] = v;
+                slot = c;
+            }
+        };
+        // event intervals: tri, norm, dt, then per level small, gather, steps 3+5, step 4
+        keep(0, ph[0], best.tri);
+        keep(1, ph[1], best.norm);
+        keep(2, ph[2], best.dt);
+        for (int d = 0; d < L; d++) {
+            keep(3 + 2 * d, ph[3 + 4 * d + 2], best.t35[d]);
+            keep(4 + 2 * d, ph[3 + 4 * d + 3], best.t4[d]);
+        }
+    }
+    // 2. levels made only of small supernodes: the fused small-supernode
+    //    launch or the per-phase launches, compared on the level's own
+    //    intervals plus the step-4 launch above it (which takes over the
+    //    level's gather when both levels use the per-phase launches)
+    {
+        Tuning on = best, off = best;
+        on.sweep = off.sweep = SWEEP_LEVELS;
+        std::fill(off.no_small.begin(), off.no_small.end(), 1);
+        std::vector<double> pon, poff;
+        h->tune[prec] = on;
+        if ((st = tune_measure(h, prec, s, reps, true, t, &pon))) return st;
+        h->tune[prec] = off;
+        if ((st = tune_measure(h, prec, s, reps, true, t, &poff))) return st;
+        for (int d = 0; d < L; d++) {
+            auto lev = [&](const std::vector<double> &p) {
+                double v = 0;
+                for (int i = 0; i < 4; i++) v += p[3 + 4 * d + i];
+                if (d > 0) v += p[3 + 4 * (d - 1) + 3];
+                return v;
+            };
+            best.no_small[d] = lev(poff) < 0.97 * lev(pon);
+        }
+    }
+    // 3. the sweep form, where the persistent sweep is available
+    h->tune[prec] = best;
+    double t_best = 0;
+    if ((st = tune_measure(h, prec, s, reps, false, t_best, nullptr))) return st;
+    if (can_persist) {
+        Tuning pe = best;
+        pe.sweep = SWEEP_PERSISTENT;
+        h->tune[prec] = pe;
+        if ((st = tune_measure(h, prec, s, reps, false, t, nullptr))) return st;
+        if (t < t_best) {
+            best = pe;
+            t_best = t;
+        }
+    }
+    // 4. keep the size policy when the measured choices are no faster
+    if (t_best > t_policy) {
+        Tuning pol;
+        pol.set = true;
+        pol.t35.assign(L, 0);
+        pol.t4.assign(L, 0);
+        pol.no_small.assign(L, 0);
+        best = pol;
+        t_best = t_policy;
+    }
+    h->tune[prec] = best;
+    drop_sweep(h, prec);
+    if (ms_policy) *ms_policy = t_policy;
+    if (ms_tuned) *ms_tuned = t_best;
+    return SELINV_OK;
+}
+
+// flat form: [1, nlevels, sweep, tri, norm, dt, then per level: t35, t4, no_small]
+selinv_status selinv_get_tuning(selinv_handle h, selinv_precision prec, int32_t *out, int32_t cap,
+                                int32_t *count) {
+    if (!h || !valid_prec(prec) || !count) return SELINV_E_INVALID_ARG;
+    const Tuning &tn = h->tune[prec];
+    const int L = h->P.nlevels;
+    *count = tn.set ? 6 + 3 * L : 0;
+    if (!tn.set || !out) return SELINV_OK;
+    if (cap < *count) {
+        h->err = "tuning buffer too small";
+        return SELINV_E_INVALID_ARG;
+    }
+    int32_t *o = out;
+    *o++ = 1;
+    *o++ = L;
+    *o++ = tn.sweep;
+    *o++ = tn.tri;
+    *o++ = tn.norm;
+    *o++ = tn.dt;
+    for (int d = 0; d < L; d++) {
+        *o++ = tn.t35[d];
+        *o++ = tn.t4[d];
+        *o++ = tn.no_small[d];
+    }
+    return SELINV_OK;
+}
+
+selinv_status selinv_set_tuning(selinv_handle h, selinv_precision prec, const int32_t *in, int32_t count) {
+    if (!h || !valid_prec(prec)) return SELINV_E_INVALID_ARG;
+    if (count == 0) {  // back to the size policy
+        h->tune[prec] = Tuning();
+        drop_sweep(h, prec);
+        return SELINV_OK;
+    }
+    const int L = h->P.nlevels;
+    auto tile_ok = [](int v) { return v == 0 || v == GEMM_TILE_32 || v == GEMM_TILE_64 || v == GEMM_TILE_128; };
+    bool ok = in && count == 6 + 3 * L && in[0] == 1 && in[1] == L && in[2] >= SWEEP_AUTO &&
+              in[2] <= SWEEP_PERSISTENT && tile_ok(in[3]) && tile_ok(in[4]) && tile_ok(in[5]);
+    if (ok && in[2] == SWEEP_PERSISTENT && h->P.symbolic != SELINV_SYMBOLIC_SYMMETRIZED) ok = false;
+    for (int d = 0; ok && d < L; d++)
+        ok = tile_ok(in[6 + 3 * d]) && tile_ok(in[7 + 3 * d]) && (in[8 + 3 * d] == 0 || in[8 + 3 * d] == 1);
+    if (!ok) {
+        h->err = "tuning table does not fit this handle (layout, level count, tile edges or sweep form)";
+        return SELINV_E_INVALID_ARG;
+    }
+    Tuning tn;
+    tn.set = true;
+    tn.sweep = in[2];
+    tn.tri = in[3];
+    tn.norm = in[4];
+    tn.dt = in[5];
+    for (int d = 0; d < L; d++) {
+        tn.t35.push_back(in[6 + 3 * d]);
+        tn.t4.push_back(in[7 + 3 * d]);
+        tn.no_small.push_back((char)in[8 + 3 * d]);
+    }
+    h->tune[prec] = tn;
+    drop_sweep(h, prec);
     return SELINV_OK;
 }
 

@@ -30,7 +30,8 @@ EXPORTED = ["selinv_analyze", "selinv_factor", "selinv_run", "selinv_run_graph",
             "selinv_get_selected_device", "selinv_export", "selinv_structure", "selinv_query",
             "selinv_set_profiling", "selinv_timings", "selinv_level_stats", "selinv_last_error",
             "selinv_status_string", "selinv_destroy", "selinv_check_plan", "selinv_set_sweep_mode",
-            "selinv_sweep_is_persistent", "selinv_batch_set_sweep_mode"]
+            "selinv_sweep_is_persistent", "selinv_batch_set_sweep_mode", "selinv_tune", "selinv_get_tuning",
+            "selinv_set_tuning"]
 
 
 class SelinvError(RuntimeError):
@@ -89,6 +90,9 @@ def _load():
         "selinv_set_sweep_mode": ([vp, i32], C.c_int),
         "selinv_sweep_is_persistent": ([vp, C.c_int], i32),
         "selinv_batch_set_sweep_mode": ([vp, i32], C.c_int),
+        "selinv_tune": ([vp, C.c_int, i32, vp, P(dbl), P(dbl)], C.c_int),
+        "selinv_get_tuning": ([vp, C.c_int, P(i32), i32, P(i32)], C.c_int),
+        "selinv_set_tuning": ([vp, C.c_int, P(i32), i32], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -217,6 +221,30 @@ class SelInv:
 
     def sweep_is_persistent(self, precision="fp64") -> int:
         return int(_lib.selinv_sweep_is_persistent(self._h, _prec(precision)))
+
+    def tune(self, precision="fp64", reps=5, stream=None):
+        """Measure and keep the fastest launch choices of the sweep (selinv_tune);
+        returns (ms with the size policy, ms with the kept choices)."""
+        a, b = C.c_double(), C.c_double()
+        self._check(_lib.selinv_tune(self._h, _prec(precision), int(reps), _stream_ptr(stream), C.byref(a),
+                                     C.byref(b)), "tune")
+        return a.value, b.value
+
+    def get_tuning(self, precision="fp64") -> list:
+        n = C.c_int32()
+        self._check(_lib.selinv_get_tuning(self._h, _prec(precision), None, 0, C.byref(n)), "get_tuning")
+        if n.value == 0:
+            return []
+        out = np.empty(n.value, np.int32)
+        self._check(_lib.selinv_get_tuning(self._h, _prec(precision), _p(out, C.c_int32), n.value, C.byref(n)),
+                    "get_tuning")
+        return out.tolist()
+
+    def set_tuning(self, table, precision="fp64"):
+        t = np.ascontiguousarray(table, dtype=np.int32)
+        self._check(_lib.selinv_set_tuning(self._h, _prec(precision), _p(t, C.c_int32) if t.size else None,
+                                           int(t.size)), "set_tuning")
+        return self
 
     def set_profiling(self, on=True):
         self._check(_lib.selinv_set_profiling(self._h, 1 if on else 0), "set_profiling")

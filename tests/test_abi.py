@@ -283,3 +283,43 @@ def test_exact_relaxed_partition(si):
     st = rel.structure()
     assert np.array_equal(st["perm"], w.perm)  # the exact form keeps the ordering
     assert _unequal_sets(st) > 0
+
+
+# --------------------------------------------------------------------------
+# tuning tables (host side; selinv_tune itself needs the device)
+# --------------------------------------------------------------------------
+def test_tuning_table_set_get_and_validation(si):
+    w = config_c0()
+    s = si.SelInv(w.n, w.colptr, w.rowind, w.perm, w.max_super, w.relax, w.pad_pct)
+    L = s.info["nlevels"]
+    assert s.get_tuning("fp64") == []
+    table = [1, L, 1, 64, 32, 0]
+    for d in range(L):
+        table += [32 if d % 2 else 64, 128, d % 2]
+    s.set_tuning(table, "mixed_fp32")
+    assert s.get_tuning("mixed_fp32") == table
+    assert s.get_tuning("fp64") == []
+    bad = [table[:-1], [2] + table[1:], table[:1] + [L + 1] + table[2:], table[:3] + [48] + table[4:],
+           table[:8] + [2] + table[9:], table[:2] + [3] + table[3:]]
+    for b in bad:
+        with pytest.raises(si.SelinvError) as e:
+            s.set_tuning(b, "mixed_fp32")
+        assert e.value.status == "INVALID_ARG"
+    assert s.get_tuning("mixed_fp32") == table  # unchanged by the rejected tables
+    s.set_tuning([], "mixed_fp32")
+    assert s.get_tuning("mixed_fp32") == []
+    # the persistent form is refused for an exact analysis
+    x = si.SelInv(w.n, w.colptr, w.rowind, w.perm, w.max_super, w.relax, w.pad_pct, symbolic="exact")
+    Lx = x.info["nlevels"]
+    with pytest.raises(si.SelinvError) as e:
+        x.set_tuning([1, Lx, 2, 0, 0, 0] + [0, 0, 0] * Lx)
+    assert e.value.status == "INVALID_ARG"
+    x.set_tuning([1, Lx, 1, 0, 0, 0] + [0, 0, 0] * Lx)
+
+
+def test_autotune_describe():
+    from paper_1708_04539_amd.autotune import describe
+    assert describe([]) == {"tuned": False}
+    d = describe([1, 2, 1, 64, 32, 32, 32, 64, 0, 128, 128, 1])
+    assert d["steps35_tiles"] == [32, 128] and d["step4_tiles"] == [64, 128]
+    assert d["small_per_phase_levels"] == [1] and d["sweep"] == "levels"

@@ -523,3 +523,54 @@ def test_exact_batch_matches_single_runs(si):
     for m, ref in zip(mats, refs):
         assert np.array_equal(m.get_selected(), ref)
     b.close()
+
+
+# --------------------------------------------------------------------------
+# autotuner: measured launch choices keep the results
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("prec", ["fp64", "mixed_bf16x3"])
+def test_tune_c1_keeps_parity(si, c1_pair, prec):
+    w, s, o = c1_pair
+    say("c1 tune", prec)
+    ms_pol, ms_tun = s.tune(prec, reps=3)
+    table = s.get_tuning(prec)
+    say("c1 tune", prec, "policy ms", ms_pol, "tuned ms", ms_tun, "table", table)
+    assert ms_tun <= ms_pol and len(table) == 6 + 3 * s.info["nlevels"]
+    s.run(prec)
+    compare_superset(s, o, TOL[prec])
+    s.run(prec, graph=True)
+    compare_superset(s, o, TOL[prec])
+    s.set_tuning([], prec)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed_fp32", "mixed_bf16x3"])
+def test_forced_tables_keep_parity(si, prec):
+    """Every tile edge on every launch class, and the per-phase launches on
+    the levels of small supernodes, give the same results."""
+    w = config_c0()
+    say("c0 forced tables", prec)
+    s, o = lib_and_oracle(si, w.n, w.colptr, w.rowind, w.values, w.perm, w.max_super, w.relax, w.pad_pct)
+    L = s.info["nlevels"]
+    for edge in (32, 64, 128):
+        for per_phase in (0, 1):
+            s.set_tuning([1, L, 1, edge, edge, edge] + [edge, edge, per_phase] * L, prec)
+            s.run(prec)
+            compare_superset(s, o, TOL[prec])
+
+
+def test_tune_exact_upwind_and_cache(si, tmp_path):
+    from paper_1708_04539_amd.autotune import tuned
+    from workloads import config_upwind
+    w = config_upwind((64, 64), "box", 0.25, 3, 64, 32)
+    say("tune exact upwind + cache")
+    s, o = lib_and_oracle_exact(si, w.n, w.colptr, w.rowind, w.values, w.perm, w.max_super)
+    path = str(tmp_path / "tuning.json")
+    r1 = tuned(s, "fp64", path, reps=2)
+    assert not r1["cached"] and r1["table"] and r1["table"][2] != 2  # never the persistent form here
+    s.run("fp64")
+    compare_superset(s, o, TOL["fp64"])
+    s2 = si.SelInv(w.n, w.colptr, w.rowind, w.perm, w.max_super, 0, 0, symbolic="exact").factor(w.values)
+    r2 = tuned(s2, "fp64", path)
+    assert r2["cached"] and r2["table"] == r1["table"] and s2.get_tuning("fp64") == r1["table"]
+    s2.run("fp64")
+    compare_superset(s2, o, TOL["fp64"])
