@@ -12,7 +12,13 @@ struct SnRec {
     int64_t off_d, off_l, off_u;
     int64_t rl_off, ru_off;  // into rl / u_rowoff and ru / l_coloff
     int64_t g_off;           // G_K inside the gather workspace of its level
+    int64_t c_off;           // source codes of G_K in gcL / gcU (-1: none, the maps serve)
 };
+
+// Source code of one entry of G_K: array << 30 | element offset, array 1 = Zd,
+// 2 = ZL, 3 = ZU, 0 = none (the entry comes from the other code array).
+constexpr uint32_t GCODE_SHIFT = 30;
+constexpr uint32_t GCODE_MASK = (1u << GCODE_SHIFT) - 1;
 
 // One matrix (handle) on the device; every pointer is a device address.
 struct MatDev {
@@ -32,14 +38,22 @@ struct MatDev {
     const int32_t *kids_ptr, *kids;
     const int64_t *push_off;
     const int32_t *push_pos;
+    // precomputed source codes of the gather (supernodes with c_off >= 0):
+    // gcL[c_off + a + b cl] for the diagonal-block and L-side entries,
+    // gcU[c_off + b + a cu] for the U-side entries of G_K(a, b)
+    const uint32_t *gcL, *gcU;
 };
 
 // gather: tile of G_K rows [a0, a0+64) x columns [b0, b0+64); entries from
 // the diagonal block of supernode `skip` (the parent, when its step-4 product
-// pushes them, see GemmProb) are left to that product; -1: none skipped
+// pushes them, see GemmProb) are left to that product; -1: none skipped.
+// The supernode's sizes and offsets ride along, so that the tile starts its
+// loads without reading the supernode record first.
 struct GatherTile {
     int32_t mat, K, a0, b0;
-    int32_t skip, pad;
+    int32_t skip, cl, cu, pad;
+    int64_t g_off, c_off;       // as in SnRec
+    int64_t skip_lo, skip_hi;   // elements of Zd holding the skipped diagonal block
 };
 
 // C = alpha * op(A) op(B) + beta * Cin, column-major, op = N (0) or T (1)
@@ -67,6 +81,14 @@ struct TriItem {
     const double *D;  // packed L\U, s x s column-major
     double *Linv, *Uinv;
     int32_t s, j0;
+    // a supernode with s, c_L, c_U <= 64 (lpan or upan non-null, j0 = 0):
+    // the same workgroup forms Lhat = L(R_L,K) L_KK^{-1} (c_L x s),
+    // Uhat = U(K,R_U)^T U_KK^{-T} (c_U x s) and A^{-T}(K,K) := L_KK^{-T}
+    // U_KK^{-T} from the inverses in LDS; Linv / Uinv are then not stored
+    const double *lpan, *upan;
+    void *Lh, *Uh;  // FP64, or FP32 when f32out
+    double *Zd;
+    int32_t cl, cu, f32out, fused;
 };
 
 // fused step 3/4/5 of one small supernode (every product a single 64x64
@@ -74,6 +96,8 @@ struct TriItem {
 struct SmallItem {
     int32_t mat, K;
     int32_t pzu, pzl, pg4;
+    int32_t s, cl, cu;
+    int64_t g_off, c_off;
 };
 
 // extraction of the selected entries

@@ -84,7 +84,7 @@ __global__ __launch_bounds__(256) void step4_gather(const GemmProb *__restrict__
         gemm_tile<MODE, BM, BN, TA, double, true, true>(probs[tl.prob], tl.m0, tl.n0, sm.g, mats);
     } else {
         const GatherTile gt = gtiles[b - ntiles];
-        gather_tile<TA>(mats[gt.mat], gt.K, gt.a0, gt.b0, sm.t, gt.skip);
+        gather_tile<TA>(mats[gt.mat], gt, sm.t);
     }
 }
 

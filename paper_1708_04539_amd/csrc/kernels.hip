@@ -105,6 +105,82 @@ __device__ __forceinline__ void tri_round(TriSmem &sm, int lane, int wave) {
     for (int t = wave; t < 2 * (4 - D); t += 4) tri_offdiag<D>(sm, t, lane, wave);
 }
 
+// Normalisation and diagonal initialisation of a supernode with s, c_L,
+// c_U <= 64, after its inverses are complete in sm.Xs (FP64 arithmetic on
+// v_mfma_f64_16x16x4, results in the storage precision).  Every product is
+// formed transposed (the MFMA takes the inverse as its first operand), so
+// that a lane's results run down a column of the output and the stores are
+// coalesced.  The panels are staged through sm.Ds, free after the rounds.
+__device__ __forceinline__ void tri_fused_epilogue(TriSmem &sm, const TriItem &it, int lane, int wave) {
+    const int s = it.s, li = lane & 15, lk = lane >> 4;
+    const int nbs = (s + 15) / 16;
+    auto stage = [&](const double *pan, int rows) {
+        // Ds[k][m] = pan(m, k), zero outside rows x s
+        const SELINV_GLOBAL double *P = gptr(pan);
+        const int r = lane, rr = min(r, rows - 1);
+        double v[16];
+#pragma unroll
+        for (int q = 0; q < 16; q++) {
+            const int c = wave + 4 * q;
+            v[q] = P[(int64_t)rr + (int64_t)min(c, s - 1) * rows];
+        }
+#pragma unroll
+        for (int q = 0; q < 16; q++) {
+            const int c = wave + 4 * q;
+            sm.Ds[c][r] = (r < rows && c < s) ? v[q] : 0.0;
+        }
+    };
+    auto put = [&](void *out, int64_t idx, double v) {
+        if (it.f32out)
+            gptr_w((float *)out)[idx] = (float)v;
+        else
+            gptr_w((double *)out)[idx] = v;
+    };
+    // panel products: out(m, n) = sum_k pan(m, k) inv(k, n), inv(k, n) =
+    // Linv(k, n) (L side) or Uinv(n, k) (U side)
+    auto panel = [&](const double *pan, int rows, void *out, bool upper) {
+        __syncthreads();  // Ds free (rounds done / previous panel read)
+        stage(pan, rows);
+        __syncthreads();
+        const int mbs = (rows + 15) / 16;
+        for (int t = wave; t < mbs * nbs; t += 4) {
+            const int mb = t % mbs, nb = t / mbs;
+            v4d_t acc = {0, 0, 0, 0};
+            for (int kk = 0; kk < s; kk += 4) {
+                const int k = kk + lk;
+                const double a = upper ? uinv_at(sm, 16 * nb + li, k) : linv_at(sm, k, 16 * nb + li);
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, sm.Ds[k][16 * mb + li], acc, 0, 0, 0);
+            }
+            // acc[v] = out(16 mb + li, 16 nb + lk + 4 v)
+            const int m = 16 * mb + li;
+#pragma unroll
+            for (int v = 0; v < 4; v++) {
+                const int n = 16 * nb + lk + 4 * v;
+                if (m < rows && n < s) put(out, m + (int64_t)n * rows, acc[v]);
+            }
+        }
+    };
+    if (it.lpan) panel(it.lpan, it.cl, it.Lh, false);
+    if (it.upan) panel(it.upan, it.cu, it.Uh, true);
+    // A^{-T}(K,K) := Linv^T Uinv^T:  Zd(m, n) = sum_k Linv(k, m) Uinv(n, k)
+    SELINV_GLOBAL double *Zd = gptr_w(it.Zd);
+    for (int t = wave; t < nbs * nbs; t += 4) {
+        const int mb = t % nbs, nb = t / nbs;
+        v4d_t acc = {0, 0, 0, 0};
+        for (int kk = 0; kk < s; kk += 4) {
+            const int k = kk + lk;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(uinv_at(sm, 16 * nb + li, k), linv_at(sm, k, 16 * mb + li),
+                                                       acc, 0, 0, 0);
+        }
+        const int m = 16 * mb + li;
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+            const int n = 16 * nb + lk + 4 * v;
+            if (m < s && n < s) Zd[m + (int64_t)n * s] = acc[v];
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void tri_base_kernel(const TriItem *__restrict__ items) {
     __shared__ TriSmem sm;
     const TriItem it = items[blockIdx.x];
@@ -154,6 +230,10 @@ __global__ __launch_bounds__(256) void tri_base_kernel(const TriItem *__restrict
     tri_round<2>(sm, lane, wave);
     tri_round<3>(sm, lane, wave);
     __syncthreads();
+    if (it.fused) {
+        tri_fused_epilogue(sm, it, lane, wave);
+        return;
+    }
     SELINV_GLOBAL double *Linv = gptr_w(it.Linv), *Uinv = gptr_w(it.Uinv);
     {
         const int r = lane;
@@ -182,7 +262,7 @@ __global__ __launch_bounds__(256) void gather_kernel(const MatDev *__restrict__ 
                                                      const GatherTile *__restrict__ tiles) {
     __shared__ GatherSmem<T> sm;
     const GatherTile tl = tiles[blockIdx.x];
-    gather_tile<T>(mats[tl.mat], tl.K, tl.a0, tl.b0, sm, tl.skip);
+    gather_tile<T>(mats[tl.mat], tl, sm);
 }
 
 // ---------------------------------------------------------------------------

@@ -76,7 +76,7 @@ __global__ __launch_bounds__(256) void sweep_kernel(const PersistArgs a) {
         }
         __syncthreads();
         if (tk.type == PT_GATHER)
-            gather_tile<T>(a.mats[tk.mat], tk.K, tk.i0, tk.i1, sm.t);
+            gather_tile<T>(a.mats[tk.mat], gather_desc(a.mats[tk.mat], tk.mat, tk.K, tk.i0, tk.i1), sm.t);
         else if (tk.type == PT_STEP35)
             gemm_tile<MODE, 64, 64, T, T, false>(a.probs[tk.prob], tk.i0, tk.i1, sm.g);
         else
@@ -112,8 +112,9 @@ __global__ __launch_bounds__(256) void sweep_kernel(const PersistArgs a) {
 // per-phase launches; the split-BF16 form runs these small products in FP32.
 template <typename T>
 struct SmallSmem {
+    // G_K while steps 3 and 5 read it, then A^{-T}(K, R_U)^T for step 4
+    // (zu[b][j]); one tile, so that four workgroups fit on a compute unit
     GatherSmem<T> g;
-    T zu[64][65];  // zu[b][j] = A^{-T}(K, R_U)^T (b, j)
 };
 
 template <typename T>
@@ -174,15 +175,64 @@ __device__ __forceinline__ typename SmallMfma<T>::Acc small_tile(GetA getA, cons
     return acc;
 }
 
+// G_K of a small supernode (c_L, c_U <= 64) into tileS[b][a] from its source
+// codes.  The threads walk the codes in storage order (both code arrays are
+// laid out in the order their side reads the panels), CH entries per thread
+// and round (every load of a round in flight together): 4 in FP64, so that
+// the kernel stays within the registers of four workgroups per compute unit
+// (one round up to 1024 entries), 8 in FP32 (up to 2048).
+template <typename T>
+__device__ __forceinline__ void gather_small_codes(const MatDev &M, int cl, int cu, int64_t c_off,
+                                                   T (&tileS)[64][65]) {
+    constexpr int CH = sizeof(T) == sizeof(double) ? 4 : 8;
+    const int tid = threadIdx.x, n = cl * cu;
+    const SELINV_GLOBAL uint32_t *cL = gptr(M.gcL) + c_off;
+    const SELINV_GLOBAL uint32_t *cU = gptr(M.gcU) + c_off;
+    const SELINV_GLOBAL T *ZL = gptr((const T *)M.ZL);
+    const SELINV_GLOBAL T *ZU = gptr((const T *)M.ZU);
+    const SELINV_GLOBAL double *Zd = gptr(M.Zd);
+    for (int base = 0; base < n; base += 256 * CH) {
+        uint32_t kl[CH], ku[CH];
+#pragma unroll
+        for (int t = 0; t < CH; t++) {
+            const int e = base + tid + 256 * t, i = e < n ? e : 0;
+            kl[t] = cL[i];
+            ku[t] = cU[i];
+        }
+        T vl[CH], vu[CH];
+#pragma unroll
+        for (int t = 0; t < CH; t++) {
+            const uint32_t k = kl[t] >> GCODE_SHIFT, off = kl[t] & GCODE_MASK;
+            if constexpr (sizeof(T) == sizeof(double)) {
+                // one load: the diagonal blocks and the L panels hold the same type
+                vl[t] = (k == 1 ? (const SELINV_GLOBAL T *)Zd : ZL)[k >= 1 && k <= 2 ? off : 0];
+            } else {
+                const double vd = Zd[k == 1 ? off : 0];
+                const T v = ZL[k == 2 ? off : 0];
+                vl[t] = k == 1 ? (T)vd : v;
+            }
+            const uint32_t k3 = ku[t] >> GCODE_SHIFT, off3 = ku[t] & GCODE_MASK;
+            vu[t] = ZU[k3 == 3 ? off3 : 0];
+        }
+#pragma unroll
+        for (int t = 0; t < CH; t++) {
+            const int e = base + tid + 256 * t;
+            if (e >= n) continue;
+            const uint32_t k = kl[t] >> GCODE_SHIFT;
+            if (k == 1 || k == 2) tileS[e / cl][e % cl] = vl[t];
+            if ((ku[t] >> GCODE_SHIFT) == 3) tileS[e % cu][e / cu] = vu[t];
+        }
+    }
+}
+
 template <int MODE>
-__global__ __launch_bounds__(256) void small_kernel(const MatDev *__restrict__ mats, const GemmProb *__restrict__ probs,
+__global__ __launch_bounds__(256, 4) void small_kernel(const MatDev *__restrict__ mats, const GemmProb *__restrict__ probs,
                                                     const SmallItem *__restrict__ items) {
     typedef typename Mode<MODE>::T T;
     typedef SmallMfma<T> MF;
     __shared__ SmallSmem<T> sm;
     const SmallItem it = items[blockIdx.x];
-    const SELINV_GLOBAL SnRec *sn = gptr(mats[it.mat].sn);
-    const int s = sn[it.K].s, cl = sn[it.K].cl, cu = sn[it.K].cu;
+    const int s = it.s, cl = it.cl, cu = it.cu;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, li = lane & 15;
     // column block of this wavefront, and its share of the row blocks
     const int ns = (s + 15) / 16, per = 4 / ns;  // wavefronts per column block
@@ -196,24 +246,27 @@ __global__ __launch_bounds__(256) void small_kernel(const MatDev *__restrict__ m
     const GemmProb *pu = pzl ? pzl : pg4;  // Uhat: op(B) of steps 5 and 4
     small_loadB<T>(bU, pu ? (const T *)pu->B : nullptr, pu ? pu->ldb : 1, s, cu, n0);
 
-    if (cl > 0 && cu > 0) gather_tile<T, false>(mats[it.mat], it.K, 0, 0, sm.g);
+    // (a small supernode with a non-empty G_K always has source codes)
+    if (cl > 0 && cu > 0) gather_small_codes<T>(mats[it.mat], cl, cu, it.c_off, sm.g.tileS);
     __syncthreads();
-    const T(&G)[64][65] = sm.g.tileS;  // G[b][a] = G_K(a, b)
+    T(&G)[64][65] = sm.g.tileS;  // G[b][a] = G_K(a, b), later zu[b][j]
+    // step 3: A^{-T}(K,R_U)^T = -G^T Lhat (cu x s); the wavefront's tiles stay
+    // in registers until every wavefront has finished reading G
+    typename MF::Acc zacc[4];
     if (active) {
-        const int n = n0 + 0;  // first column of the block; lanes add MF::col
-        // step 3: A^{-T}(K,R_U)^T = -G^T Lhat (cu x s)
         if (pzu) {
             SELINV_GLOBAL T *C = gptr_w((T *)pzu->C);
-            for (int mb = mfirst; 16 * mb < cu; mb += per) {
-                const typename MF::Acc acc = small_tile<T>([&](int m, int k) { return G[m][k]; }, bL, cu, cl, 16 * mb);
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                const int mb = mfirst + i * per;
+                if (16 * mb >= cu) break;
+                zacc[i] = small_tile<T>([&](int m, int k) { return G[m][k]; }, bL, cu, cl, 16 * mb);
                 const int m = 16 * mb + li;
 #pragma unroll
                 for (int v = 0; v < 4; v++) {
-                    const int c = n + MF::col(lane, v);
-                    if (m >= cu || c >= s) continue;
-                    const T r = (T)(pzu->alpha * (double)acc[v]);
-                    C[m + (int64_t)c * pzu->ldc] = r;
-                    sm.zu[m][c] = r;
+                    const int c = n0 + MF::col(lane, v);
+                    zacc[i][v] = (T)(pzu->alpha * (double)zacc[i][v]);
+                    if (m < cu && c < s) C[m + (int64_t)c * pzu->ldc] = zacc[i][v];
                 }
             }
         }
@@ -225,10 +278,25 @@ __global__ __launch_bounds__(256) void small_kernel(const MatDev *__restrict__ m
                 const int m = 16 * mb + li;
 #pragma unroll
                 for (int v = 0; v < 4; v++) {
-                    const int c = n + MF::col(lane, v);
+                    const int c = n0 + MF::col(lane, v);
                     if (m >= cl || c >= s) continue;
                     C[m + (int64_t)c * pzl->ldc] = (T)(pzl->alpha * (double)acc[v]);
                 }
+            }
+        }
+    }
+    __syncthreads();
+    // A^{-T}(K,R_U)^T into LDS over G
+    if (active && pzu) {
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            const int mb = mfirst + i * per;
+            if (16 * mb >= cu) break;
+            const int m = 16 * mb + li;
+#pragma unroll
+            for (int v = 0; v < 4; v++) {
+                const int c = n0 + MF::col(lane, v);
+                if (m < cu && c < s) G[m][c] = zacc[i][v];
             }
         }
     }
@@ -238,7 +306,7 @@ __global__ __launch_bounds__(256) void small_kernel(const MatDev *__restrict__ m
         SELINV_GLOBAL double *C = gptr_w((double *)pg4->C);
         for (int mb = mfirst; 16 * mb < s; mb += per) {
             const typename MF::Acc acc =
-                small_tile<T>([&](int m, int k) { return sm.zu[k][m]; }, bU, s, cu, 16 * mb);
+                small_tile<T>([&](int m, int k) { return G[k][m]; }, bU, s, cu, 16 * mb);
             const int m = 16 * mb + li;
             double cin[4];
 #pragma unroll

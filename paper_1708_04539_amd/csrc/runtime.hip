@@ -140,6 +140,9 @@ struct selinv_handle_s {
     std::vector<int32_t> kids_ptr, kids, push_pos;
     std::vector<int64_t> push_off;
     int32_t *d_kids_ptr = nullptr, *d_kids = nullptr, *d_push_pos = nullptr;
+    // source codes of the gather (see MatDev)
+    std::vector<uint32_t> gcL, gcU;
+    uint32_t *d_gcL = nullptr, *d_gcU = nullptr;
     int64_t *d_push_off = nullptr;
     PrecBufs pb[NPREC];
     std::unique_ptr<Sweep> sweep[NPREC];
@@ -311,6 +314,13 @@ bool persist_auto(const std::vector<selinv_handle> &hs) {
     return depth > 0 && tiles / depth < 512;
 }
 
+GatherTile gather_tile_of(selinv_handle h, int32_t mi, int32_t K, int a0, int b0, int32_t skip);
+
+// A supernode whose diagonal block, R_L and R_U all fit one 64-wide tile has
+// its normalisation and diagonal initialisation done by the workgroup that
+// inverts its diagonal block (tri_base_kernel), from the inverses in LDS.
+inline bool fused_prologue(const SnRec &r) { return r.s <= 64 && r.cl <= 64 && r.cu <= 64; }
+
 // Build the work lists of one sweep over a set of factored handles.
 selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, int sweep_mode, std::unique_ptr<Sweep> &out,
                           std::string &err, const Tuning *tn = nullptr) {
@@ -362,6 +372,8 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, int sweep_mo
         m.kids = h->d_kids;
         m.push_off = h->d_push_off;
         m.push_pos = h->d_push_pos;
+        m.gcL = h->d_gcL;
+        m.gcU = h->d_gcU;
         m.Zd = b.Zd;
         m.ZL = b.ZL;
         m.ZU = b.ZU;
@@ -400,11 +412,35 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, int sweep_mo
         PR.tri.off = tri.size();
         for (size_t mi = 0; mi < hs.size(); mi++) {
             selinv_handle h = hs[mi];
+            const PrecBufs &b = h->pb[prec];
             for (int32_t K = 0; K < h->P.ns; K++) {
                 if (part[mi][K] != pp) continue;
                 const SnRec &r = h->sn[K];
-                for (int j0 = 0; j0 < r.s; j0 += 64)
-                    tri.push_back(TriItem{h->d_diag + r.off_d, h->d_Linv + r.off_d, h->d_Uinv + r.off_d, r.s, j0});
+                for (int j0 = 0; j0 < r.s; j0 += 64) {
+                    TriItem t{};
+                    t.D = h->d_diag + r.off_d;
+                    t.Linv = h->d_Linv + r.off_d;
+                    t.Uinv = h->d_Uinv + r.off_d;
+                    t.s = r.s;
+                    t.j0 = j0;
+                    if (fused_prologue(r)) {
+                        // normalisation and diagonal initialisation in the same workgroup
+                        t.fused = 1;
+                        t.lpan = r.cl > 0 ? h->d_lpan + r.off_l : nullptr;
+                        t.upan = r.cu > 0 ? h->d_upan + r.off_u : nullptr;
+                        t.Lh = (char *)b.Lh + r.off_l * e;
+                        t.Uh = (char *)b.Uh + r.off_u * e;
+                        t.Zd = b.Zd + r.off_d;
+                        t.cl = r.cl;
+                        t.cu = r.cu;
+                        t.f32out = e == 4;
+                        X.check(t.D, r.s, r.s, r.s, 8);
+                        X.check(t.Zd, r.s, r.s, r.s, 8);
+                        if (t.lpan) X.check(t.lpan, r.cl, r.s, r.cl, 8), X.check(t.Lh, r.cl, r.s, r.cl, e);
+                        if (t.upan) X.check(t.upan, r.cu, r.s, r.cu, 8), X.check(t.Uh, r.cu, r.s, r.cu, e);
+                    }
+                    tri.push_back(t);
+                }
             }
         }
         PR.tri.count = (int)(tri.size() - PR.tri.off);
@@ -454,7 +490,7 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, int sweep_mo
             selinv_handle h = hs[mi];
             const PrecBufs &b = h->pb[prec];
             for (int32_t K = 0; K < h->P.ns; K++) {
-                if (part[mi][K] != pp) continue;
+                if (part[mi][K] != pp || fused_prologue(h->sn[K])) continue;
                 const SnRec &r = h->sn[K];
                 char *Lh = (char *)b.Lh + r.off_l * e;
                 char *Uh = (char *)b.Uh + r.off_u * e;
@@ -476,7 +512,7 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, int sweep_mo
             selinv_handle h = hs[mi];
             const PrecBufs &b = h->pb[prec];
             for (int32_t K = 0; K < h->P.ns; K++) {
-                if (part[mi][K] != pp) continue;
+                if (part[mi][K] != pp || fused_prologue(h->sn[K])) continue;
                 const SnRec &r = h->sn[K];
                 add_prob(probs, h->d_Linv + r.off_d, 1, r.s, h->d_Uinv + r.off_d, 1, r.s, b.Zd + r.off_d, r.s,
                          nullptr, 1, r.s, r.s, r.s, 1.0, 0.0, &X, 8, 8);
@@ -514,7 +550,10 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, int sweep_mo
     // handled whole by one workgroup of the fused small-supernode kernel, on
     // the levels where every supernode is of that kind: the fused launch then
     // replaces the three per-phase launches of the level.
-    auto small_dims = [](const SnRec &r) { return r.s <= 64 && r.cl <= 64 && r.cu <= 64; };
+    // (the fused kernel gathers through the source codes only)
+    auto small_dims = [](const SnRec &r) {
+        return r.s <= 64 && r.cl <= 64 && r.cu <= 64 && (r.cl == 0 || r.cu == 0 || r.c_off >= 0);
+    };
     std::vector<char> level_small(depth, 1);
     for (size_t mi = 0; mi < hs.size(); mi++)
         for (int d = 0; d < hs[mi]->P.nlevels; d++)
@@ -550,7 +589,7 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, int sweep_mo
                     if (!S->fused[d])
                         for (int b0 = 0; b0 < r.cu; b0 += 64)
                             for (int a0 = 0; a0 < r.cl; a0 += 64)
-                                gts.push_back(GatherTile{(int32_t)mi, K, a0, b0, -1, 0});
+                                gts.push_back(gather_tile_of(h, (int32_t)mi, K, a0, b0, -1));
                     S->lev_gather_elems[d] += (double)r.cl * r.cu;
                 } else {
                     S->lev_small_elems[d] += (double)r.cl * r.cu;
@@ -632,7 +671,7 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, int sweep_mo
                     }
                     for (int b0 = 0; b0 < r.cu; b0 += 64)
                         for (int a0 = 0; a0 < r.cl; a0 += 64)
-                            gts.push_back(GatherTile{(int32_t)mi, K, a0, b0, skip, 0});
+                            gts.push_back(gather_tile_of(h, (int32_t)mi, K, a0, b0, skip));
                 }
             }
         }
@@ -645,7 +684,8 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, int sweep_mo
                 const SnRec &r = h->sn[K];
                 const int32_t gid = gbase[mi] + K;
                 if (!is_small(r) || (prob_zu[gid] < 0 && prob_zl[gid] < 0 && prob_g4[gid] < 0)) continue;
-                smalls.push_back(SmallItem{(int32_t)mi, K, prob_zu[gid], prob_zl[gid], prob_g4[gid]});
+                smalls.push_back(SmallItem{(int32_t)mi, K, prob_zu[gid], prob_zl[gid], prob_g4[gid], r.s, r.cl, r.cu,
+                                           r.g_off, r.c_off});
             }
         }
         S->small[d].count = (int)(smalls.size() - S->small[d].off);
@@ -860,6 +900,83 @@ hipError_t launch_sweep(const Sweep &S, hipStream_t st, std::vector<hipEvent_t> 
 
 bool valid_prec(int p) { return p >= 0 && p < NPREC; }
 
+// Source codes of the gather (MatDev::gcL / gcU): for every supernode K that
+// gets them, the location of A^{-T}(R_L(K)[a], R_U(K)[b]) as array << 30 |
+// element offset, found through the relative-index maps as the map-based
+// gather finds it.  Every supernode gets codes while their total stays within
+// kCodeBudget entries; otherwise only those with G_K of at most 64 x 64 (the
+// latency-bound ones), in order, while the budget lasts.  Offsets must fit 30
+// bits, else no codes at all.
+constexpr int64_t kCodeBudget = int64_t(1) << 26;
+
+void build_gather_codes(const Plan &P, std::vector<SnRec> &sn, std::vector<uint32_t> &gcL,
+                        std::vector<uint32_t> &gcU) {
+    gcL.clear();
+    gcU.clear();
+    for (SnRec &r : sn) r.c_off = -1;
+    const int64_t lim = int64_t(GCODE_MASK) + 1;
+    if (P.tot_d > lim || P.tot_l > lim || P.tot_u > lim) return;
+    int64_t total = 0;
+    for (int32_t K = 0; K < P.ns; K++) total += P.cl(K) * P.cu(K);
+    const bool all = total <= kCodeBudget;
+    int64_t used = 0;
+    for (int32_t K = 0; K < P.ns; K++) {
+        const int64_t cl = P.cl(K), cu = P.cu(K);
+        if (cl == 0 || cu == 0 || (!all && (cl > 64 || cu > 64)) || used + cl * cu > kCodeBudget) continue;
+        sn[K].c_off = used;
+        used += cl * cu;
+    }
+    gcL.assign(used, 0);
+    gcU.assign(used, 0);
+    for (int32_t K = 0; K < P.ns; K++) {
+        const int64_t co = sn[K].c_off, cl = P.cl(K), cu = P.cu(K);
+        if (co < 0) continue;
+        const int32_t *RL = P.rl.data() + P.rl_ptr[K], *RU = P.ru.data() + P.ru_ptr[K];
+        for (int64_t b = 0; b < cu; b++) {
+            const int32_t c = RU[b], J = P.supof[c], fJ = P.xsup[J];
+            for (int64_t a = 0; a < cl; a++) {
+                const int32_t r = RL[a], I = P.supof[r];
+                if (I == J) {
+                    const int64_t off = P.off_d[J] + int64_t(c - fJ) * P.width(J) + (r - fJ);
+                    gcL[co + a + b * cl] = (1u << GCODE_SHIFT) | (uint32_t)off;
+                } else if (I > J) {
+                    const int64_t m = P.l_coloff[P.ru_ptr[K] + b] + a;
+                    const int64_t off = P.off_l[J] + int64_t(c - fJ) * P.cl(J) + P.mapL[m];
+                    gcL[co + a + b * cl] = (2u << GCODE_SHIFT) | (uint32_t)off;
+                } else {
+                    const int64_t m = P.u_rowoff[P.rl_ptr[K] + a] + b;
+                    const int64_t off = P.off_u[I] + int64_t(r - P.xsup[I]) * P.cu(I) + P.mapU[m];
+                    gcU[co + b + a * cu] = (3u << GCODE_SHIFT) | (uint32_t)off;
+                }
+            }
+        }
+    }
+}
+
+// Gather tile of supernode K of handle h (matrix mi of the sweep); skip: the
+// supernode whose diagonal block the tile leaves to that supernode's step-4
+// product (-1: none).
+GatherTile gather_tile_of(selinv_handle h, int32_t mi, int32_t K, int a0, int b0, int32_t skip) {
+    const SnRec &r = h->sn[K];
+    GatherTile g;
+    g.mat = mi;
+    g.K = K;
+    g.a0 = a0;
+    g.b0 = b0;
+    g.skip = skip;
+    g.cl = r.cl;
+    g.cu = r.cu;
+    g.pad = 0;
+    g.g_off = r.g_off;
+    g.c_off = r.c_off;
+    g.skip_lo = g.skip_hi = 0;
+    if (skip >= 0) {
+        g.skip_lo = h->sn[skip].off_d;
+        g.skip_hi = g.skip_lo + (int64_t)h->sn[skip].s * h->sn[skip].s;
+    }
+    return g;
+}
+
 // Children of every supernode, and for each child K of P the positions of
 // P's columns first(P) + r in R_L(K) and R_U(K) (-1 where absent).  Both
 // lists are sorted, so one merge walk each.
@@ -973,6 +1090,7 @@ selinv_status selinv_analyze(int64_t n, const int64_t *colptr, const int32_t *ro
     }
     try {
         build_push_maps(P, h->kids_ptr, h->kids, h->push_off, h->push_pos);
+        build_gather_codes(P, h->sn, h->gcL, h->gcU);
     } catch (const std::bad_alloc &) {
         g_analyze_err = "host allocation failed in analyze";
         delete h;
@@ -1023,6 +1141,8 @@ selinv_status selinv_factor(selinv_handle h, const double *values) {
         HIPCHK(h->err, upload(&h->d_kids, h->kids), "upload children");
         HIPCHK(h->err, upload(&h->d_push_off, h->push_off), "upload push maps");
         HIPCHK(h->err, upload(&h->d_push_pos, h->push_pos), "upload push maps");
+        HIPCHK(h->err, upload(&h->d_gcL, h->gcL), "upload gather codes");
+        HIPCHK(h->err, upload(&h->d_gcU, h->gcU), "upload gather codes");
     }
     if (P.tot_d) HIPCHK(h->err, hipMemcpy(h->d_diag, F.d.data(), P.tot_d * 8, hipMemcpyHostToDevice), "H2D diag");
     if (P.tot_l) HIPCHK(h->err, hipMemcpy(h->d_lpan, F.l.data(), P.tot_l * 8, hipMemcpyHostToDevice), "H2D lpan");
@@ -1579,7 +1699,26 @@ selinv_status selinv_check_plan(selinv_handle h, int64_t *mismatches) {
         for (int64_t a = P.rl_ptr[K]; a < P.rl_ptr[K + 1]; a++) visit(P.rl[a]);
         for (int64_t b = P.ru_ptr[K]; b < P.ru_ptr[K + 1]; b++) visit(P.ru[b]);
     }
-    if (bad && h->err.empty()) h->err = "push maps or levels inconsistent with R_L / R_U";
+    // gather codes: each names the location that an independent binary
+    // search finds for the same entry, in the array of its kind
+    for (int32_t K = 0; K < P.ns; K++) {
+        const int64_t co = h->sn[K].c_off, cl = P.cl(K), cu = P.cu(K);
+        if (co < 0) continue;
+        if (co + cl * cu > (int64_t)h->gcL.size()) {
+            bad++;
+            continue;
+        }
+        for (int64_t b = 0; b < cu; b++)
+            for (int64_t a = 0; a < cl; a++) {
+                const int64_t loc = P.locate(P.rl[P.rl_ptr[K] + a], P.ru[P.ru_ptr[K] + b]);
+                const int64_t kind = loc >> LOC_SHIFT, off = loc & LOC_MASK;
+                const uint32_t want = (uint32_t)((kind == LOC_DIAG ? 1 : kind == LOC_L ? 2 : 3) << GCODE_SHIFT) |
+                                      (uint32_t)off;
+                const uint32_t l = h->gcL[co + a + b * cl], u = h->gcU[co + b + a * cu];
+                bad += loc < 0 || (kind == LOC_U ? (u != want || l != 0) : (l != want || u != 0));
+            }
+    }
+    if (bad && h->err.empty()) h->err = "push maps, levels or gather codes inconsistent with R_L / R_U";
     *mismatches += bad;
     return SELINV_OK;
 }
@@ -1624,7 +1763,7 @@ void selinv_destroy(selinv_handle h) {
                     (void *)h->d_tl, (void *)h->d_tu,
                     (void *)h->d_sn, (void *)h->d_supof, (void *)h->d_rl, (void *)h->d_ru, (void *)h->d_mapL,
                     (void *)h->d_mapU, (void *)h->d_lcol, (void *)h->d_urow, (void *)h->d_aloc,
-                    (void *)h->d_kids_ptr, (void *)h->d_kids, (void *)h->d_push_off, (void *)h->d_push_pos})
+                    (void *)h->d_kids_ptr, (void *)h->d_kids, (void *)h->d_push_off, (void *)h->d_push_pos, (void *)h->d_gcL, (void *)h->d_gcU})
         (void)hipFree(q);
     for (auto e : h->events) (void)hipEventDestroy(e);
     if (h->own_stream) (void)hipStreamDestroy(h->own_stream);

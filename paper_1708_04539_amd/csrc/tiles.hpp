@@ -338,22 +338,115 @@ struct GatherSmem {
     int64_t rowUp[64], rowUoff[64], colDiag[64], colLow[64], colLoff[64];
 };
 
+// Gather tile descriptor of supernode K of matrix `mat` from its record.
+__device__ __forceinline__ GatherTile gather_desc(const MatDev &M, int mat, int K, int a0, int b0) {
+    const SELINV_GLOBAL SnRec *sn = gptr(M.sn);
+    GatherTile gt;
+    gt.mat = mat;
+    gt.K = K;
+    gt.a0 = a0;
+    gt.b0 = b0;
+    gt.skip = -1;
+    gt.cl = sn[K].cl;
+    gt.cu = sn[K].cu;
+    gt.pad = 0;
+    gt.g_off = sn[K].g_off;
+    gt.c_off = sn[K].c_off;
+    gt.skip_lo = gt.skip_hi = 0;
+    return gt;
+}
+
+// Tile of G_K from the precomputed source codes: every thread loads the codes
+// of its entries (they do not depend on earlier launches), then the values
+// they name, in two rounds of 2 x 8 entries (the register budget of the GEMM
+// kernels that share this code stays unchanged).  Diagonal-block and L-side
+// entries are read with the threads along the rows of G (contiguous in ZL),
+// U-side entries with the threads along its columns (contiguous in ZU).
+template <typename T, bool STORE>
+__device__ __forceinline__ void gather_tile_codes(const MatDev &M, const GatherTile &gt, GatherSmem<T> &sm) {
+    T(&tileS)[64][65] = sm.tileS;
+    constexpr int CH = 8;
+    const int tid = threadIdx.x;
+    const int a0 = gt.a0, b0 = gt.b0, cl = gt.cl, cu = gt.cu;
+    const int na = min(64, cl - a0), nb = min(64, cu - b0);
+    const SELINV_GLOBAL uint32_t *cL = gptr(M.gcL) + gt.c_off;
+    const SELINV_GLOBAL uint32_t *cU = gptr(M.gcU) + gt.c_off;
+    const SELINV_GLOBAL T *ZL = gptr((const T *)M.ZL);
+    const SELINV_GLOBAL T *ZU = gptr((const T *)M.ZU);
+    const SELINV_GLOBAL double *Zd = gptr(M.Zd);
+    uint32_t keep = 0;  // bit t: entry tid + 256 t of the tile is written to G
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        uint32_t kl[CH], ku[CH];
+#pragma unroll
+        for (int t = 0; t < CH; t++) {
+            const int e = tid + 256 * (h * CH + t), ia = e & 63, ib = e >> 6;
+            kl[t] = cL[(ia < na && ib < nb) ? (a0 + ia) + (int64_t)(b0 + ib) * cl : 0];
+            const int jb = e & 63, ja = e >> 6;
+            ku[t] = cU[(ja < na && jb < nb) ? (b0 + jb) + (int64_t)(a0 + ja) * cu : 0];
+        }
+        T vl[CH], vu[CH];
+#pragma unroll
+        for (int t = 0; t < CH; t++) {
+            const uint32_t k = kl[t] >> GCODE_SHIFT, off = kl[t] & GCODE_MASK;
+            if constexpr (sizeof(T) == sizeof(double)) {
+                // one load: the diagonal blocks and the L panels hold the same type
+                vl[t] = (k == 1 ? (const SELINV_GLOBAL T *)Zd : ZL)[k >= 1 && k <= 2 ? off : 0];
+            } else {
+                const double vd = Zd[k == 1 ? off : 0];
+                const T v = ZL[k == 2 ? off : 0];
+                vl[t] = k == 1 ? (T)vd : v;
+            }
+            const uint32_t k3 = ku[t] >> GCODE_SHIFT, off3 = ku[t] & GCODE_MASK;
+            vu[t] = ZU[k3 == 3 ? off3 : 0];
+        }
+#pragma unroll
+        for (int t = 0; t < CH; t++) {
+            const int e = tid + 256 * (h * CH + t), ia = e & 63, ib = e >> 6;
+            const uint32_t k = kl[t] >> GCODE_SHIFT, off = kl[t] & GCODE_MASK;
+            // (a code of an entry outside the tile is that of entry 0, and its
+            // value is dropped here; entries of the skipped diagonal block are
+            // written by their owner)
+            const bool in = ia < na && ib < nb;
+            const bool skipped = k == 1 && (int64_t)off >= gt.skip_lo && (int64_t)off < gt.skip_hi;
+            if (in && !skipped) keep |= 1u << (h * CH + t);
+            if (in && (k == 2 || (k == 1 && !skipped))) tileS[ib][ia] = vl[t];
+            const int jb = e & 63, ja = e >> 6;
+            if (ja < na && jb < nb && (ku[t] >> GCODE_SHIFT) == 3) tileS[jb][ja] = vu[t];
+        }
+    }
+    __syncthreads();
+    if constexpr (!STORE) return;
+    SELINV_GLOBAL T *G = gptr_w((T *)M.G + gt.g_off);
+#pragma unroll
+    for (int t = 0; t < 2 * CH; t++) {
+        const int e = tid + 256 * t, ia = e & 63, ib = e >> 6;
+        if (keep >> t & 1) G[(a0 + ia) + (int64_t)(b0 + ib) * cl] = tileS[ib][ia];
+    }
+}
+
 // One 64x64 tile (rows a0.., columns b0..) of G_K = A^{-T}(R_L(K), R_U(K)),
 // gathered by the 256 threads of the calling workgroup (see kernels.hip).
 // Every load goes through a global-memory view and is issued unconditionally
 // (clamped to a valid index, the unused value discarded), so that a thread's
-// loads of one stage are all in flight together.
+// loads of one stage are all in flight together.  With precomputed codes
+// (gt.c_off >= 0) the codes name the sources; otherwise the relative-index
+// maps do.
 // STORE = false leaves the tile in LDS only (sm.tileS[b][a] = G(a0+a, b0+b)).
 template <typename T, bool STORE = true>
-__device__ __forceinline__ void gather_tile(const MatDev &M, const int K, const int a0, const int b0,
-                                            GatherSmem<T> &sm, const int skip = -1) {
+__device__ __forceinline__ void gather_tile(const MatDev &M, const GatherTile &gt, GatherSmem<T> &sm) {
+    if (gt.c_off >= 0) {
+        gather_tile_codes<T, STORE>(M, gt, sm);
+        return;
+    }
+    const int K = gt.K, a0 = gt.a0, b0 = gt.b0, skip = gt.skip;
     T(&tileS)[64][65] = sm.tileS;
     int32_t *rowR = sm.rowR, *rowI = sm.rowI, *colJ = sm.colJ;
     int64_t *rowUp = sm.rowUp, *rowUoff = sm.rowUoff, *colDiag = sm.colDiag, *colLow = sm.colLow,
             *colLoff = sm.colLoff;
     const SELINV_GLOBAL SnRec *sn = gptr(M.sn);
-    const int32_t sk_cl = sn[K].cl, sk_cu = sn[K].cu;
-    const int64_t sk_rl_off = sn[K].rl_off, sk_ru_off = sn[K].ru_off, sk_g_off = sn[K].g_off;
+    const int32_t sk_cl = gt.cl, sk_cu = gt.cu;
+    const int64_t sk_rl_off = sn[K].rl_off, sk_ru_off = sn[K].ru_off, sk_g_off = gt.g_off;
     const SELINV_GLOBAL int32_t *supof = gptr(M.supof);
     const int tid = threadIdx.x;
     const int na = min(64, sk_cl - a0), nb = min(64, sk_cu - b0);  // both >= 1
