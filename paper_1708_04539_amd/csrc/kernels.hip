@@ -23,8 +23,8 @@ namespace selinv {
 // ---------------------------------------------------------------------------
 // triangular inversion, diagonal 64x64 blocks
 // ---------------------------------------------------------------------------
-// One workgroup (4 wavefronts) inverts both triangles of the 64x64 diagonal
-// sub-block that starts at row/column o of one supernode's packed
+// One workgroup (4 wavefronts) inverts both triangles of the 64x64 (16 NB
+// wide) diagonal sub-block that starts at row/column o of one supernode's packed
 // L_KK \ U_KK (column-major, s x s; L unit lower, U upper).  A ragged
 // sub-block (s - o < 64) is padded with the identity, whose inverse stays the
 // identity and is not stored.  Blocked by 16:
@@ -44,30 +44,37 @@ namespace selinv {
 // it.  The off-diagonal 64x64 blocks of the inverses come from the GEMM rounds
 // of the recursive doubling (X21 = -B^{-1} C A^{-1} for L,
 // X12 = -A^{-1} C B^{-1} for U).
+// NB = 4 handles every 64-wide sub-block; NB = 1 and 2 (16- and 32-wide
+// blocks, far less LDS) serve the supernodes of at most 16 or 32 columns
+// whose normalisation runs in the same workgroup.
+template <int NB>
 struct TriSmem {
-    double Ds[64][65];     // Ds[c][r] = D(o + r, o + c), identity-padded
-    double Xs[64][65];     // Xs[c][r]: r > c: L^{-1}(r, c); r <= c: U^{-1}(r, c)
-    double Ts[4][16][17];  // per-wavefront 16x16 intermediate
-    double rd[64];         // 1 / U(c, c)
+    static constexpr int W = 16 * NB;
+    double Ds[W][65];        // Ds[c][r] = D(o + r, o + c), identity-padded; later a panel (64 rows)
+    double Xs[W][W + 1];     // Xs[c][r]: r > c: L^{-1}(r, c); r <= c: U^{-1}(r, c)
+    double Ts[4][16][17];    // per-wavefront 16x16 intermediate
+    double rd[W];            // 1 / U(c, c)
 };
 
 typedef double v4d_t __attribute__((ext_vector_type(4)));
 
 // L^{-1}(r, c) and U^{-1}(r, c) read from the packed tile (zero outside the
 // triangle; the unit diagonal of L^{-1} is implicit)
-__device__ __forceinline__ double linv_at(const TriSmem &sm, int r, int c) {
+template <class SM>
+__device__ __forceinline__ double linv_at(const SM &sm, int r, int c) {
     return r > c ? sm.Xs[c][r] : (r == c ? 1.0 : 0.0);
 }
-__device__ __forceinline__ double uinv_at(const TriSmem &sm, int r, int c) { return r <= c ? sm.Xs[c][r] : 0.0; }
+template <class SM>
+__device__ __forceinline__ double uinv_at(const SM &sm, int r, int c) { return r <= c ? sm.Xs[c][r] : 0.0; }
 
 // One off-diagonal block at distance D, computed by the calling wavefront.
 // The lanes feed the MFMA with A(i = lane % 16, k = lane / 16) and
 // B(k = lane / 16, j = lane % 16); the result row is lane / 16 + 4 v, its
 // column lane % 16 (register v of the accumulator).
-template <int D>
-__device__ __forceinline__ void tri_offdiag(TriSmem &sm, int t, int lane, int wave) {
-    const bool upper = t >= 4 - D;
-    const int i = upper ? t - (4 - D) : t + D;   // row block of the result
+template <int NB, int D>
+__device__ __forceinline__ void tri_offdiag(TriSmem<NB> &sm, int t, int lane, int wave) {
+    const bool upper = t >= NB - D;
+    const int i = upper ? t - (NB - D) : t + D;  // row block of the result
     const int j = upper ? i + D : t;             // column block
     const int kb = upper ? 16 * (i + 1) : 16 * j;  // contraction range [kb, kb + 16 D)
     const int li = lane & 15, lk = lane >> 4;
@@ -99,10 +106,10 @@ __device__ __forceinline__ void tri_offdiag(TriSmem &sm, int t, int lane, int wa
     __builtin_amdgcn_wave_barrier();
 }
 
-template <int D>
-__device__ __forceinline__ void tri_round(TriSmem &sm, int lane, int wave) {
+template <int NB, int D>
+__device__ __forceinline__ void tri_round(TriSmem<NB> &sm, int lane, int wave) {
     __syncthreads();
-    for (int t = wave; t < 2 * (4 - D); t += 4) tri_offdiag<D>(sm, t, lane, wave);
+    for (int t = wave; t < 2 * (NB - D); t += 4) tri_offdiag<NB, D>(sm, t, lane, wave);
 }
 
 // Normalisation and diagonal initialisation of a supernode with s, c_L,
@@ -111,21 +118,22 @@ __device__ __forceinline__ void tri_round(TriSmem &sm, int lane, int wave) {
 // formed transposed (the MFMA takes the inverse as its first operand), so
 // that a lane's results run down a column of the output and the stores are
 // coalesced.  The panels are staged through sm.Ds, free after the rounds.
-__device__ __forceinline__ void tri_fused_epilogue(TriSmem &sm, const TriItem &it, int lane, int wave) {
+template <int NB>
+__device__ __forceinline__ void tri_fused_epilogue(TriSmem<NB> &sm, const TriItem &it, int lane, int wave) {
     const int s = it.s, li = lane & 15, lk = lane >> 4;
     const int nbs = (s + 15) / 16;
     auto stage = [&](const double *pan, int rows) {
         // Ds[k][m] = pan(m, k), zero outside rows x s
         const SELINV_GLOBAL double *P = gptr(pan);
         const int r = lane, rr = min(r, rows - 1);
-        double v[16];
+        double v[4 * NB];
 #pragma unroll
-        for (int q = 0; q < 16; q++) {
+        for (int q = 0; q < 4 * NB; q++) {
             const int c = wave + 4 * q;
             v[q] = P[(int64_t)rr + (int64_t)min(c, s - 1) * rows];
         }
 #pragma unroll
-        for (int q = 0; q < 16; q++) {
+        for (int q = 0; q < 4 * NB; q++) {
             const int c = wave + 4 * q;
             sm.Ds[c][r] = (r < rows && c < s) ? v[q] : 0.0;
         }
@@ -181,31 +189,34 @@ __device__ __forceinline__ void tri_fused_epilogue(TriSmem &sm, const TriItem &i
     }
 }
 
+template <int NB>
 __global__ __launch_bounds__(256) void tri_base_kernel(const TriItem *__restrict__ items) {
-    __shared__ TriSmem sm;
+    constexpr int W = 16 * NB;
+    __shared__ TriSmem<NB> sm;
     const TriItem it = items[blockIdx.x];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int s = it.s, o = it.j0, b = min(64, s - o);
+    const int s = it.s, o = it.j0, b = min(W, s - o);
     {
-        // all 16 loads of a thread in flight at once; addresses clamped into
+        // all loads of a thread in flight at once; addresses clamped into
         // the block, the identity padding selected afterwards
-        const int r = lane, rr = min(r, b - 1);
-        double v[16];
+        constexpr int PER = W * W / 256 > 0 ? W * W / 256 : 1;
+        double v[PER];
 #pragma unroll
-        for (int q = 0; q < 16; q++) {
-            const int c = wave + 4 * q;
-            v[q] = gptr(it.D)[(int64_t)(o + rr) + (int64_t)(o + min(c, b - 1)) * s];
+        for (int q = 0; q < PER; q++) {
+            const int e = tid + 256 * q, r = e % W, c = e / W;
+            v[q] = gptr(it.D)[(int64_t)(o + min(r, b - 1)) + (int64_t)(o + min(c, b - 1)) * s];
         }
 #pragma unroll
-        for (int q = 0; q < 16; q++) {
-            const int c = wave + 4 * q;
+        for (int q = 0; q < PER; q++) {
+            const int e = tid + 256 * q, r = e % W, c = e / W;
+            if (e >= W * W) continue;
             const double d = (r < b && c < b) ? v[q] : (r == c ? 1.0 : 0.0);
             sm.Ds[c][r] = d;
             if (r == c) sm.rd[c] = 1.0 / d;
         }
     }
     __syncthreads();
-    {
+    if (wave < NB) {
         const int base = 16 * wave, c = lane & 15;
         const bool up = (lane & 16) != 0;  // lanes 32..63 repeat lanes 0..31 and store nothing
         double x[16];
@@ -226,32 +237,34 @@ __global__ __launch_bounds__(256) void tri_base_kernel(const TriItem *__restrict
             }
         }
     }
-    tri_round<1>(sm, lane, wave);
-    tri_round<2>(sm, lane, wave);
-    tri_round<3>(sm, lane, wave);
+    if constexpr (NB >= 2) tri_round<NB, 1>(sm, lane, wave);
+    if constexpr (NB >= 3) tri_round<NB, 2>(sm, lane, wave);
+    if constexpr (NB >= 4) tri_round<NB, 3>(sm, lane, wave);
     __syncthreads();
     if (it.fused) {
-        tri_fused_epilogue(sm, it, lane, wave);
+        tri_fused_epilogue<NB>(sm, it, lane, wave);
         return;
     }
-    SELINV_GLOBAL double *Linv = gptr_w(it.Linv), *Uinv = gptr_w(it.Uinv);
-    {
-        const int r = lane;
+    if constexpr (NB == 4) {
+        SELINV_GLOBAL double *Linv = gptr_w(it.Linv), *Uinv = gptr_w(it.Uinv);
+        {
+            const int r = lane;
 #pragma unroll
-        for (int q = 0; q < 16; q++) {
-            const int c = wave + 4 * q;
-            if (r < b && c < b) {
-                const int64_t g = (int64_t)(o + r) + (int64_t)(o + c) * s;
-                Linv[g] = linv_at(sm, r, c);
-                Uinv[g] = uinv_at(sm, r, c);
+            for (int q = 0; q < 16; q++) {
+                const int c = wave + 4 * q;
+                if (r < b && c < b) {
+                    const int64_t g = (int64_t)(o + r) + (int64_t)(o + c) * s;
+                    Linv[g] = linv_at(sm, r, c);
+                    Uinv[g] = uinv_at(sm, r, c);
+                }
             }
         }
+        // zeros of L^{-1} above the sub-block and of U^{-1} left of it
+        for (int c = wave; c < b; c += 4)
+            for (int r = lane; r < o; r += 64) Linv[r + (int64_t)(o + c) * s] = 0.0;
+        if (lane < b)
+            for (int c = wave; c < o; c += 4) Uinv[(o + lane) + (int64_t)c * s] = 0.0;
     }
-    // zeros of L^{-1} above the sub-block and of U^{-1} left of it
-    for (int c = wave; c < b; c += 4)
-        for (int r = lane; r < o; r += 64) Linv[r + (int64_t)(o + c) * s] = 0.0;
-    if (lane < b)
-        for (int c = wave; c < o; c += 4) Uinv[(o + lane) + (int64_t)c * s] = 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -287,9 +300,16 @@ __global__ __launch_bounds__(256) void extract_kernel(ExtractArgs a) {
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-hipError_t launch_tri_base(const TriItem *items, int count, hipStream_t st) {
+hipError_t launch_tri_base(const TriItem *items, int count, int nb, hipStream_t st) {
     if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(tri_base_kernel, dim3(count), dim3(256), 0, st, items);
+    if (nb == 1)
+        hipLaunchKernelGGL(tri_base_kernel<1>, dim3(count), dim3(256), 0, st, items);
+    else if (nb == 2)
+        hipLaunchKernelGGL(tri_base_kernel<2>, dim3(count), dim3(256), 0, st, items);
+    else if (nb == 4)
+        hipLaunchKernelGGL(tri_base_kernel<4>, dim3(count), dim3(256), 0, st, items);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

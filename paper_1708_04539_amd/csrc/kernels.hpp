@@ -11,8 +11,9 @@ namespace selinv {
 constexpr int TRI_MAX_S = 1024;
 
 // diagonal 64x64 sub-blocks of the triangular inverses, one item per sub-block
-// (TriItem.j0 = first row/column of the sub-block)
-hipError_t launch_tri_base(const TriItem *items, int count, hipStream_t st);
+// (TriItem.j0 = first row/column of the sub-block); nb = 1 or 2: 16- or
+// 32-wide blocks, for fused items of at most that many columns only
+hipError_t launch_tri_base(const TriItem *items, int count, int nb, hipStream_t st);
 // output tile of the grouped GEMM
 enum : int { GEMM_TILE_32 = 32, GEMM_TILE_64 = 64, GEMM_TILE_128 = 128 };
 

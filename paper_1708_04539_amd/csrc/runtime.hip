@@ -57,6 +57,7 @@ struct Sweep {
     // device idle.  split = 0: everything in pro[0], no fork.
     struct Prologue {
         Range tri, norm, dt;
+        Range tri1, tri2;  // fused items of at most 16 / 32 columns (16- / 32-wide kernel)
         std::vector<Range> tri_rounds;  // pairs (T products, X products) per doubling round
     } pro[2];
     int split = 0;
@@ -409,7 +410,7 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, int sweep_mo
         //   U: X12 = -A^{-1} (C B^{-1}),   C = U(o.., o+h..)
         // the inner products go to scratch (tl / tu) in a first launch, the
         // outer ones into L^{-1} / U^{-1} in a second.
-        PR.tri.off = tri.size();
+        std::vector<TriItem> by_nb[3];  // 64-wide, 16-wide, 32-wide
         for (size_t mi = 0; mi < hs.size(); mi++) {
             selinv_handle h = hs[mi];
             const PrecBufs &b = h->pb[prec];
@@ -439,11 +440,16 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, int sweep_mo
                         if (t.lpan) X.check(t.lpan, r.cl, r.s, r.cl, 8), X.check(t.Lh, r.cl, r.s, r.cl, e);
                         if (t.upan) X.check(t.upan, r.cu, r.s, r.cu, 8), X.check(t.Uh, r.cu, r.s, r.cu, e);
                     }
-                    tri.push_back(t);
+                    by_nb[!t.fused ? 0 : r.s <= 16 ? 1 : r.s <= 32 ? 2 : 0].push_back(t);
                 }
             }
         }
-        PR.tri.count = (int)(tri.size() - PR.tri.off);
+        Range *rg[3] = {&PR.tri, &PR.tri1, &PR.tri2};
+        for (int c = 0; c < 3; c++) {
+            rg[c]->off = tri.size();
+            tri.insert(tri.end(), by_nb[c].begin(), by_nb[c].end());
+            rg[c]->count = (int)by_nb[c].size();
+        }
         for (int hb = 64;; hb *= 2) {
             bool any = false;
             for (size_t mi = 0; mi < hs.size(); mi++)
@@ -830,7 +836,9 @@ hipError_t launch_sweep(const Sweep &S, hipStream_t st, std::vector<hipEvent_t> 
     // rounds), normalisation, diagonal initialisation
     auto tri_part = [&](const Sweep::Prologue &P, hipStream_t s) -> hipError_t {
         hipError_t e2;
-        if ((e2 = launch_tri_base(S.d_tri + P.tri.off, P.tri.count, s))) return e2;
+        if ((e2 = launch_tri_base(S.d_tri + P.tri.off, P.tri.count, 4, s))) return e2;
+        if ((e2 = launch_tri_base(S.d_tri + P.tri1.off, P.tri1.count, 1, s))) return e2;
+        if ((e2 = launch_tri_base(S.d_tri + P.tri2.off, P.tri2.count, 2, s))) return e2;
         for (const Range &r : P.tri_rounds)
             if ((e2 = launch_gemm(GEMM_PRO_F64, CMP_F64, r.tile, S.d_probs, S.d_tiles + r.off, r.count, s)))
                 return e2;
