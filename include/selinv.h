@@ -91,8 +91,7 @@ typedef enum {
  *       column as its only child and the padding estimate of the exact
  *       counts stays within pad_pct percent (as for the symmetrized form,
  *       with the rows of L and the columns of U counted separately).
- *       relax = pad_pct = 0: the fundamental supernodes alone.  Sweeps of such handles run level by level
- *       (the persistent form needs the symmetrized analysis). */
+ *       relax = pad_pct = 0: the fundamental supernodes alone. */
 typedef enum {
     SELINV_SYMBOLIC_SYMMETRIZED = 0,
     SELINV_SYMBOLIC_EXACT = 1
@@ -190,8 +189,7 @@ selinv_status selinv_set_sweep_mode(selinv_handle h, int32_t mode);
  *     HIP events; every class keeps its fastest edge;
  *   - per level made only of small supernodes, the fused small-supernode
  *     launch or the per-phase launches;
- *   - with the symmetrized analysis and sweep mode 0, the level sweep or the
- *     persistent sweep.
+ *   - with sweep mode 0, the level sweep or the persistent sweep.
  * Each configuration runs reps + 1 times (the first untimed; 1 <= reps <=
  * 100) and counts its fastest run: per-launch times from eager runs with
  * events, whole-sweep comparisons from replays of the sweep's HIP graph.  When the measured choices are not faster
@@ -215,7 +213,7 @@ selinv_status selinv_get_tuning(selinv_handle h, selinv_precision prec, int32_t 
 
 /* Installs a table of that layout (a cached one, say); count = 0 returns to
  * the size policy.  A table that does not fit the handle (layout, level
- * count, tile edges, or the persistent form with the exact analysis) gives
+ * count or tile edges) gives
  * SELINV_E_INVALID_ARG and changes nothing.  The work lists of `prec` are
  * rebuilt at the next run. */
 selinv_status selinv_set_tuning(selinv_handle h, selinv_precision prec, const int32_t *in, int32_t count);

@@ -124,7 +124,9 @@ struct PTask {
 };
 
 struct PSn {
-    int32_t parent;    // gid of the parent supernode, -1 for a root
+    // supernodes whose results the gather of this one reads (gids):
+    // deps[dep_off .. dep_off + ndep) of PersistArgs
+    int32_t dep_off, ndep;
     int32_t n_gather;  // gather tiles of this supernode
     int32_t n_zu;      // tiles of its step-3 product
     int32_t n_all;     // tiles of its step-3, step-5 and step-4 products
@@ -134,6 +136,7 @@ struct PersistArgs {
     const PTask *tasks;
     int32_t ntasks;
     const PSn *sn;
+    const int32_t *deps;
     int32_t *cnt;  // 3 per supernode: gather tiles, step-3 tiles, all product tiles done
     int32_t *head; // next task
     int32_t *err;  // set when a dependency wait ran out

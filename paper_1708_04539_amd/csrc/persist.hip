@@ -9,10 +9,12 @@
 // tiles, the tiles of the step-3/5 products and the tiles of the step-4
 // product of every supernode.  Per-supernode counters carry the
 // dependencies:
-//   gather tile of K   waits until the parent P of K is complete (every tile
-//                      of its step-3/5/4 products done).  For the
-//                      structurally symmetric pattern, C(K) minus P lies in
-//                      C(P), so by induction all of C(K) is then complete;
+//   gather tile of K   waits until every supernode its gather reads is
+//                      complete (every tile of its step-3/5/4 products
+//                      done): with the exact analysis every supernode that
+//                      R_L(K) u R_U(K) meets; with the symmetrized one the
+//                      parent P alone, since C(K) minus P lies in C(P) and by
+//                      induction all of C(K) is then complete;
 //   step-3/5 tile of K waits for all gather tiles of K;
 //   step-4 tile of K   waits for all tiles of the step-3 product of K.
 // Every task waits only on tasks earlier in the queue, and tasks are taken in
@@ -67,7 +69,10 @@ __global__ __launch_bounds__(256) void sweep_kernel(const PersistArgs a) {
         if (threadIdx.x == 0) {
             const PSn me = a.sn[tk.gid];
             if (tk.type == PT_GATHER) {
-                if (me.parent >= 0) wait_geq(&a.cnt[3 * me.parent + 2], a.sn[me.parent].n_all, a.err);
+                for (int d = 0; d < me.ndep; d++) {
+                    const int32_t P = a.deps[me.dep_off + d];
+                    wait_geq(&a.cnt[3 * P + 2], a.sn[P].n_all, a.err);
+                }
             } else if (tk.type == PT_STEP35) {
                 wait_geq(&a.cnt[3 * tk.gid + 0], me.n_gather, a.err);
             } else {

@@ -77,6 +77,7 @@ struct Sweep {
     PTask *d_ptasks = nullptr;
     int32_t ntasks = 0;
     PSn *d_psn = nullptr;
+    int32_t *d_deps = nullptr;
     int32_t *d_cnt = nullptr;  // 3 counters per supernode, then head, then error flag
     int64_t ncnt = 0;
     int grid = 0;
@@ -97,6 +98,7 @@ struct Sweep {
         (void)hipFree(d_small);
         (void)hipFree(d_ptasks);
         (void)hipFree(d_psn);
+        (void)hipFree(d_deps);
         (void)hipFree(d_cnt);
     }
 };
@@ -701,6 +703,7 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, int sweep_mo
     {
         std::vector<PTask> pt;
         std::vector<PSn> psn(nsn);
+        std::vector<int32_t> deps;
         auto tiles64 = [](int M, int N) { return ((M + 63) / 64) * ((N + 63) / 64); };
         for (size_t mi = 0; mi < hs.size(); mi++) {
             selinv_handle h = hs[mi];
@@ -708,7 +711,21 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, int sweep_mo
                 const int32_t gid = gbase[mi] + K;
                 const SnRec &r = h->sn[K];
                 PSn &q = psn[gid];
-                q.parent = h->P.sparent[K] >= 0 ? gbase[mi] + h->P.sparent[K] : -1;
+                // symmetrized sets: the parent carries every dependency on;
+                // exact sets: every supernode that R_L(K) u R_U(K) meets
+                q.dep_off = (int32_t)deps.size();
+                const Plan &P = h->P;
+                if (P.symbolic == SELINV_SYMBOLIC_SYMMETRIZED) {
+                    if (P.sparent[K] >= 0) deps.push_back(gbase[mi] + P.sparent[K]);
+                } else {
+                    std::vector<int32_t> blk;
+                    for (int64_t x = P.rl_ptr[K]; x < P.rl_ptr[K + 1]; x++) blk.push_back(P.supof[P.rl[x]]);
+                    for (int64_t x = P.ru_ptr[K]; x < P.ru_ptr[K + 1]; x++) blk.push_back(P.supof[P.ru[x]]);
+                    std::sort(blk.begin(), blk.end());
+                    blk.erase(std::unique(blk.begin(), blk.end()), blk.end());
+                    for (int32_t J : blk) deps.push_back(gbase[mi] + J);
+                }
+                q.ndep = (int32_t)deps.size() - q.dep_off;
                 q.n_gather = tiles64(r.cl, r.cu);
                 q.n_zu = prob_zu[gid] >= 0 ? tiles64(probs[prob_zu[gid]].M, probs[prob_zu[gid]].N) : 0;
                 q.n_all = q.n_zu;
@@ -754,27 +771,19 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, int sweep_mo
             if (k.type != PT_GATHER) last_all[k.gid] = t;
             if (k.is_zu) last_zu[k.gid] = t;
         }
-        for (int32_t g = 0; g < nsn; g++) {
-            const int32_t P = psn[g].parent;
-            if (P >= 0 && first_any[g] != INT64_MAX && last_all[P] >= first_any[g]) X.violations++;
-        }
+        for (int32_t g = 0; g < nsn; g++)
+            for (int32_t d = 0; d < psn[g].ndep; d++) {
+                const int32_t P = deps[psn[g].dep_off + d];
+                if (P < 0 || P >= nsn || P == g) X.violations++;
+                else if (first_any[g] != INT64_MAX && last_all[P] >= first_any[g]) X.violations++;
+            }
         for (int64_t t = 0; t < (int64_t)pt.size(); t++) {
             const PTask &k = pt[t];
             if (k.type == PT_STEP35 && last_gather[k.gid] > t) X.violations++;
             if (k.type == PT_STEP4 && last_zu[k.gid] > t) X.violations++;
         }
         const bool small = pt.size() <= 400000;
-        // the persistent kernel orders a supernode after its parent only;
-        // that covers every dependency when the sets come from the
-        // symmetrized pattern (they meet ancestors only)
-        bool tree_deps = true;
-        for (auto h : hs) tree_deps &= h->P.symbolic == SELINV_SYMBOLIC_SYMMETRIZED;
-        if (sweep_mode == SWEEP_PERSISTENT && !tree_deps) {
-            err = "the persistent sweep needs the symmetrized analysis";
-            return SELINV_E_INVALID_ARG;
-        }
-        S->persistent = tree_deps && (sweep_mode == SWEEP_PERSISTENT ||
-                                      (sweep_mode == SWEEP_AUTO && small && persist_auto(hs)));
+        S->persistent = sweep_mode == SWEEP_PERSISTENT || (sweep_mode == SWEEP_AUTO && small && persist_auto(hs));
         if (S->persistent) {
             if (pt.size() >= (size_t)INT32_MAX) {
                 err = "persistent task queue too long";
@@ -785,6 +794,7 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, int sweep_mo
             std::vector<int32_t> zero(S->ncnt + 2, 0);
             HIPCHK(err, upload(&S->d_ptasks, pt), "upload tasks");
             HIPCHK(err, upload(&S->d_psn, psn), "upload task deps");
+            HIPCHK(err, upload(&S->d_deps, deps), "upload task deps");
             HIPCHK(err, upload(&S->d_cnt, zero), "upload counters");
             S->grid = persist_grid(mode_of(prec));
             if (S->grid <= 0) {
@@ -878,6 +888,7 @@ hipError_t launch_sweep(const Sweep &S, hipStream_t st, std::vector<hipEvent_t> 
         a.tasks = S.d_ptasks;
         a.ntasks = S.ntasks;
         a.sn = S.d_psn;
+        a.deps = S.d_deps;
         a.cnt = S.d_cnt;
         a.head = S.d_cnt + S.ncnt;
         a.err = S.d_cnt + S.ncnt + 1;
@@ -1355,7 +1366,7 @@ selinv_status selinv_tune(selinv_handle h, selinv_precision prec, int32_t reps, 
         s = h->own_stream;
     }
     const int L = h->P.nlevels;
-    const bool can_persist = h->P.symbolic == SELINV_SYMBOLIC_SYMMETRIZED && h->sweep_mode == SWEEP_AUTO;
+    const bool can_persist = h->sweep_mode == SWEEP_AUTO;
     // the size policy, in the handle's own sweep form
     h->tune[prec] = Tuning();
     double t_policy = 0, t = 0;
@@ -1487,7 +1498,6 @@ selinv_status selinv_set_tuning(selinv_handle h, selinv_precision prec, const in
     auto tile_ok = [](int v) { return v == 0 || v == GEMM_TILE_32 || v == GEMM_TILE_64 || v == GEMM_TILE_128; };
     bool ok = in && count == 6 + 3 * L && in[0] == 1 && in[1] == L && in[2] >= SWEEP_AUTO &&
               in[2] <= SWEEP_PERSISTENT && tile_ok(in[3]) && tile_ok(in[4]) && tile_ok(in[5]);
-    if (ok && in[2] == SWEEP_PERSISTENT && h->P.symbolic != SELINV_SYMBOLIC_SYMMETRIZED) ok = false;
     for (int d = 0; ok && d < L; d++)
         ok = tile_ok(in[6 + 3 * d]) && tile_ok(in[7 + 3 * d]) && (in[8 + 3 * d] == 0 || in[8 + 3 * d] == 1);
     if (!ok) {

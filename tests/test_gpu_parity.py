@@ -499,13 +499,28 @@ def test_u1_exact_graph_replay_and_sweep_forms(si, u1_pair):
         torch.cuda.synchronize()
         s.run("fp64")
         assert np.array_equal(s.get_selected(), ref)
+    s.set_sweep_mode("levels")
+    s.run("fp64")
+    lev = s.get_selected()
+    # the dependency-driven sweep waits on every supernode that R_L u R_U meets
     s.set_sweep_mode("persistent")
-    with pytest.raises(si.SelinvError) as e:
-        s.run("fp64")
-    assert e.value.status == "INVALID_ARG"
+    s.run("fp64")
+    assert s.sweep_is_persistent("fp64") == 1
+    assert np.array_equal(s.get_selected(), lev)
     s.set_sweep_mode("auto")
     s.run("fp64")
     assert np.array_equal(s.get_selected(), ref)
+
+
+@pytest.mark.parametrize("case", EXACT_CASES, ids=[f"n{c[0]}_cap{c[3]}_{c[4]}" for c in EXACT_CASES])
+def test_exact_persistent_sweep(si, case):
+    n, dens, seed, cap, tri = case
+    say("exact persistent", case)
+    cp, ri, v, _ = random_sparse(n, dens, seed, lower_only=tri == "lower", upper_only=tri == "upper")
+    perm = None if tri else np.random.default_rng(seed).permutation(n).astype(np.int32)
+    s, o = lib_and_oracle_exact(si, n, cp, ri, v, perm, cap)
+    s.set_sweep_mode("persistent").run("fp64")
+    compare_superset(s, o, TOL["fp64"])
 
 
 def test_exact_batch_matches_single_runs(si):
