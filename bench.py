@@ -34,7 +34,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="c1", choices=["c0", "c1", "c2", "c4", "u1", "u4"])
+    ap.add_argument("--config", default="c1", choices=["c0", "c1", "c2", "c4", "u1", "u4", "z1"])
     ap.add_argument("--symbolic", default=None, choices=["symmetrized", "exact"],
                     help="analysis form (default: symmetrized for c*, exact for the upwind u* configs)")
     ap.add_argument("--precision", default=None, help="fp64 | mixed_fp32 | mixed_bf16x3 (default: per config)")
@@ -57,6 +57,7 @@ WORKLOADS = {
     "c4": "3D 64^3 27-point asymmetric stencil, n=262144, ND, supernodes<=512",
     "u1": "2D 256x256 9-point upwind stencil (non-symmetric pattern), n=65536, ND, supernodes<=128",
     "u4": "3D 64^3 27-point upwind stencil (non-symmetric pattern), n=262144, ND, supernodes<=512",
+    "z1": "complex 2D 256x256 9-point shifted stencil, n=65536 (real form of order 131072), ND, supernodes<=128 nodes",
 }
 
 
@@ -256,7 +257,9 @@ def main():
     stream = torch.cuda.Stream()  # graphs cannot be captured on the legacy null stream
     t0 = time.perf_counter()
     symbolic = args.symbolic or ("exact" if args.config.startswith("u") else "symmetrized")
-    s = SelInv(w.n, w.colptr, w.rowind, w.perm, w.max_super, w.relax, w.pad_pct, symbolic=symbolic)
+    cplx = bool(w.extra.get("complex"))
+    s = SelInv(w.n, w.colptr, w.rowind, w.perm, w.max_super, w.relax, w.pad_pct, symbolic=symbolic,
+               complex_values=cplx)
     s.set_sweep_mode(args.sweep)
     t_an = time.perf_counter() - t0
     t0 = time.perf_counter()
@@ -264,7 +267,7 @@ def main():
     t_fa = time.perf_counter() - t0
     info = s.info
     F = info["flops"]
-    out = torch.empty(w.nnz, dtype=torch.float64, device="cuda")
+    out = torch.empty(w.nnz, dtype=torch.complex128 if cplx else torch.float64, device="cuda")
     graph = not args.no_graph
 
     # autotuner (setup, untimed): launch choices measured on this device
@@ -314,6 +317,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.config], "n": w.n, "nnz": w.nnz, "precision": prec,
                    "symbolic": symbolic, "nnz_lu": info["nnz_lu"],
+                   "complex": "real form of order 2n: GFLOP counts the real form's flops, twice those of "
+                              "native complex arithmetic" if cplx else False,
                    "supernodes": info["nsuper"], "levels": info["nlevels"], "gflop": F / 1e9,
                    "hip_graph": graph, "sweep": "persistent" if s.sweep_is_persistent(prec) == 1 else "levels",
                    "parallelism": "single GPU"},

@@ -111,6 +111,20 @@ typedef enum {
  *               pad_pct percent of s (cnt(j) + s).  0 gives fundamental
  *               supernodes; values are clamped to [0, 100].
  *   symbolic  : a selinv_symbolic value (other values: SELINV_E_INVALID_ARG).
+ *   complex_values : nonzero for a complex A (the paper's experiments are
+ *               complex, e.g. H - zS).  The library then works on the real
+ *               form M of order 2n: the entry a = x + i y at (i, j) becomes
+ *               [[x, -y], [y, x]] at rows 2i, 2i+1 and columns 2j, 2j+1, and
+ *               M^{-1} holds A^{-1} the same way.  Every kernel, precision and
+ *               sweep form applies unchanged, at twice the flops and storage
+ *               of native complex arithmetic.  The unpivoted LU of M needs a
+ *               nonzero real part at every pivot of its 2 x 2 node blocks
+ *               (true for matrices whose diagonal dominates in its real part);
+ *               else SELINV_E_ZERO_PIVOT.  selinv_factor takes 2 nnz doubles
+ *               (re, im per entry of A); selinv_get writes 2 doubles (re, im);
+ *               selinv_get_selected(_device) writes 2 nnz doubles;
+ *               selinv_structure, selinv_export, selinv_query (n, nnz_a, ...)
+ *               and the supernode sizes (max_super, relax) refer to M.
  * Padded entries are stored explicitly; their values are still exact entries
  * of A^{-1}.  opts = NULL: all fields 0. */
 typedef struct {
@@ -118,6 +132,7 @@ typedef struct {
     int32_t relax;
     int32_t pad_pct;
     int32_t symbolic;
+    int32_t complex_values;
 } selinv_analyze_opts;
 
 typedef struct {
@@ -136,6 +151,7 @@ typedef struct {
     int32_t max_gemm_m, max_gemm_n, max_gemm_k; /* its shape                    */
     int32_t symbolic;   /* selinv_symbolic form of the analysis                  */
     int64_t nnz_l, nnz_u; /* stored entries of the off-diagonal blocks of L, U   */
+    int32_t complex_values; /* 1: a complex A in its real form (n, nnz_a of M)  */
 } selinv_info;
 
 /* Symbolic analysis (host only).  Builds the supernode partition, the block

@@ -138,6 +138,13 @@ struct selinv_handle_s {
     SnRec *d_sn = nullptr;
     int32_t *d_supof = nullptr, *d_rl = nullptr, *d_ru = nullptr, *d_mapL = nullptr, *d_mapU = nullptr;
     int64_t *d_lcol = nullptr, *d_urow = nullptr, *d_aloc = nullptr;
+    // complex matrices, held in the real-equivalent form of order 2 n_c:
+    // the pattern of A (n_c, colptr_c) and, per entry p of A, the
+    // locations of Re and Im of A^{-1}(j, i) (aloc_c[2p], aloc_c[2p + 1])
+    bool cplx = false;
+    int64_t n_c = 0, nnz_c = 0;
+    std::vector<int64_t> colptr_c, aloc_c;
+    int64_t *d_aloc_c = nullptr;
     // children lists and positions of the parent's columns in each child's
     // R_L / R_U (see MatDev), for the push of A^{-T}(P,P) into the children's G
     std::vector<int32_t> kids_ptr, kids, push_pos;
@@ -919,6 +926,61 @@ hipError_t launch_sweep(const Sweep &S, hipStream_t st, std::vector<hipEvent_t> 
 
 bool valid_prec(int p) { return p >= 0 && p < NPREC; }
 
+// Real-equivalent form of a complex matrix: the entry a = x + i y of A at
+// (i, j) becomes the block [[x, -y], [y, x]] at rows 2i, 2i+1 and columns 2j,
+// 2j+1, so that M = [[Re A, -Im A], [Im A, Re A]] up to the interleaving and
+// M^{-1} holds A^{-1} in the same way.  The pattern of column 2j and of column
+// 2j+1 lists rows 2i, 2i+1 for every row i of column j; the ordering keeps
+// the two rows and columns of a node together (perm2[2k + h] = 2 perm[k] + h).
+selinv_status complex_embedding(int64_t n, const int64_t *colptr, const int32_t *rowind, const int32_t *perm,
+                                std::vector<int64_t> &cp2, std::vector<int32_t> &ri2, std::vector<int32_t> &pm2,
+                                std::string &err) {
+    if (n < 1 || !colptr || !rowind) {
+        err = "n must be >= 1 and colptr/rowind non-null";
+        return SELINV_E_INVALID_ARG;
+    }
+    if (2 * n >= (int64_t(1) << 31) - 1) {
+        err = "2 n exceeds the int32 index range (complex matrices take the real form of order 2 n)";
+        return SELINV_E_INVALID_ARG;
+    }
+    if (colptr[0] != 0) {
+        err = "colptr[0] != 0";
+        return SELINV_E_BAD_PATTERN;
+    }
+    for (int64_t j = 0; j < n; j++)
+        if (colptr[j + 1] < colptr[j]) {
+            err = "colptr decreases";
+            return SELINV_E_BAD_PATTERN;
+        }
+    cp2.assign(2 * n + 1, 0);
+    ri2.resize(4 * colptr[n]);
+    int64_t at = 0;
+    for (int64_t j = 0; j < n; j++)
+        for (int h = 0; h < 2; h++) {
+            for (int64_t k = colptr[j]; k < colptr[j + 1]; k++) {
+                const int32_t i = rowind[k];
+                if (i < 0 || i >= n) {
+                    err = "row index out of range in column " + std::to_string(j);
+                    return SELINV_E_BAD_PATTERN;
+                }
+                ri2[at++] = 2 * i;
+                ri2[at++] = 2 * i + 1;
+            }
+            cp2[2 * j + h + 1] = at;
+        }
+    pm2.resize(2 * n);
+    for (int64_t k = 0; k < n; k++) {
+        const int32_t v = perm ? perm[k] : (int32_t)k;
+        if (v < 0 || v >= n) {
+            err = "perm is not a permutation";
+            return SELINV_E_BAD_PERM;
+        }
+        pm2[2 * k] = 2 * v;
+        pm2[2 * k + 1] = 2 * v + 1;
+    }
+    return SELINV_OK;
+}
+
 // Source codes of the gather (MatDev::gcL / gcU): for every supernode K that
 // gets them, the location of A^{-T}(R_L(K)[a], R_U(K)[b]) as array << 30 |
 // element offset, found through the relative-index maps as the map-based
@@ -1076,9 +1138,34 @@ selinv_status selinv_analyze(int64_t n, const int64_t *colptr, const int32_t *ro
     int32_t relax = opts ? std::max<int32_t>(0, opts->relax) : 0;
     int32_t pad = opts ? std::min<int32_t>(100, std::max<int32_t>(0, opts->pad_pct)) : 0;
     if (cap <= 0 || cap > TRI_MAX_S) cap = TRI_MAX_S;
+    const bool cplx = opts && opts->complex_values;
     selinv_status st;
     try {
-        st = analyze(h->P, n, colptr, rowind, perm, cap, relax, pad, symbolic, h->err);
+        if (cplx) {
+            std::vector<int64_t> cp2;
+            std::vector<int32_t> ri2, pm2;
+            st = complex_embedding(n, colptr, rowind, perm, cp2, ri2, pm2, h->err);
+            if (!st)
+                st = analyze(h->P, 2 * n, cp2.data(), ri2.data(), pm2.data(), cap, relax, pad, symbolic, h->err);
+            if (!st) {
+                h->cplx = true;
+                h->n_c = n;
+                h->nnz_c = colptr[n];
+                h->colptr_c.assign(colptr, colptr + n + 1);
+                // entry p = k of column j (row i): Re A^{-1}(j,i) = M^{-1}(2j, 2i) is
+                // the selected value of the real-form entry (2i, 2j), Im A^{-1}(j,i)
+                // = M^{-1}(2j+1, 2i) that of the entry (2i, 2j+1)
+                h->aloc_c.resize(2 * h->nnz_c);
+                for (int64_t j = 0; j < n; j++)
+                    for (int64_t k = colptr[j]; k < colptr[j + 1]; k++) {
+                        const int64_t t = k - colptr[j];
+                        h->aloc_c[2 * k] = h->P.a_loc[cp2[2 * j] + 2 * t];
+                        h->aloc_c[2 * k + 1] = h->P.a_loc[cp2[2 * j + 1] + 2 * t];
+                    }
+            }
+        } else {
+            st = analyze(h->P, n, colptr, rowind, perm, cap, relax, pad, symbolic, h->err);
+        }
     } catch (const std::bad_alloc &) {
         st = SELINV_E_NOMEM;
         h->err = "host allocation failed in analyze";
@@ -1125,7 +1212,24 @@ selinv_status selinv_factor(selinv_handle h, const double *values) {
     HostFactors F;
     selinv_status st;
     try {
-        st = factor_host(h->P, values, F, h->err);
+        std::vector<double> v2;
+        if (h->cplx) {
+            // values of the real-equivalent form: a = x + i y becomes
+            // [[x, -y], [y, x]] at rows 2i, 2i+1 of columns 2j, 2j+1
+            const Plan &P = h->P;
+            v2.resize(P.nnz_a);
+            for (int64_t j = 0; j < h->n_c; j++)
+                for (int64_t k = h->colptr_c[j]; k < h->colptr_c[j + 1]; k++) {
+                    const int64_t t = k - h->colptr_c[j];
+                    const double x = values[2 * k], y = values[2 * k + 1];
+                    const int64_t e0 = P.a_colptr[2 * j] + 2 * t, e1 = P.a_colptr[2 * j + 1] + 2 * t;
+                    v2[e0] = x;
+                    v2[e0 + 1] = y;
+                    v2[e1] = -y;
+                    v2[e1 + 1] = x;
+                }
+        }
+        st = factor_host(h->P, h->cplx ? v2.data() : values, F, h->err);
     } catch (const std::bad_alloc &) {
         h->err = "host allocation failed in factor";
         return SELINV_E_NOMEM;
@@ -1156,6 +1260,7 @@ selinv_status selinv_factor(selinv_handle h, const double *values) {
         HIPCHK(h->err, upload(&h->d_lcol, P.l_coloff), "upload l_coloff");
         HIPCHK(h->err, upload(&h->d_urow, P.u_rowoff), "upload u_rowoff");
         HIPCHK(h->err, upload(&h->d_aloc, P.a_loc), "upload a_loc");
+        if (h->cplx) HIPCHK(h->err, upload(&h->d_aloc_c, h->aloc_c), "upload complex locations");
         HIPCHK(h->err, upload(&h->d_kids_ptr, h->kids_ptr), "upload children");
         HIPCHK(h->err, upload(&h->d_kids, h->kids), "upload children");
         HIPCHK(h->err, upload(&h->d_push_off, h->push_off), "upload push maps");
@@ -1561,9 +1666,20 @@ static selinv_status sync_last(selinv_handle h) {
     return check_sweep_error(h->err, h->last_sweep);
 }
 
+static selinv_status get_real(selinv_handle h, int64_t i, int64_t j, double *out);
+
 selinv_status selinv_get(selinv_handle h, int64_t i, int64_t j, double *out) {
     if (!h || !out) return SELINV_E_INVALID_ARG;
     if (h->state < 0) return SELINV_E_STATE;
+    if (!h->cplx) return get_real(h, i, j, out);
+    // A^{-1}(i, j) = M^{-1}(2i, 2j) + i M^{-1}(2i+1, 2j)
+    if (i < 0 || j < 0 || i >= h->n_c || j >= h->n_c) return SELINV_E_INVALID_ARG;
+    selinv_status st = get_real(h, 2 * i, 2 * j, out);
+    if (!st) st = get_real(h, 2 * i + 1, 2 * j, out + 1);
+    return st;
+}
+
+static selinv_status get_real(selinv_handle h, int64_t i, int64_t j, double *out) {
     const Plan &P = h->P;
     if (i < 0 || j < 0 || i >= P.n || j >= P.n) return SELINV_E_INVALID_ARG;
     selinv_status st = sync_last(h);
@@ -1591,7 +1707,7 @@ selinv_status selinv_get_selected_device(selinv_handle h, double *out, void *str
     if (!h || !out) return SELINV_E_INVALID_ARG;
     if (h->state < 2 || h->last_prec < 0) return SELINV_E_STATE;
     const PrecBufs &b = h->pb[h->last_prec];
-    ExtractArgs a{h->d_aloc, b.Zd, b.ZL, b.ZU, out, h->P.nnz_a};
+    ExtractArgs a{h->cplx ? h->d_aloc_c : h->d_aloc, b.Zd, b.ZL, b.ZU, out, h->cplx ? 2 * h->nnz_c : h->P.nnz_a};
     hipError_t e = launch_extract(h->last_prec == SELINV_FP64, a, (hipStream_t)stream);
     if (e != hipSuccess) return dev_fail(h->err, e, "extract launch");
     return SELINV_OK;
@@ -1602,11 +1718,12 @@ selinv_status selinv_get_selected(selinv_handle h, double *out) {
     selinv_status st = sync_last(h);
     if (st) return st;
     double *d = nullptr;
-    HIPCHK(h->err, alloc_bytes((void **)&d, h->P.nnz_a * 8), "alloc extract");
+    const int64_t cnt = h->cplx ? 2 * h->nnz_c : h->P.nnz_a;
+    HIPCHK(h->err, alloc_bytes((void **)&d, cnt * 8), "alloc extract");
     st = selinv_get_selected_device(h, d, h->last_stream);
     if (!st) {
         hipError_t e = hipStreamSynchronize(h->last_stream);
-        if (e == hipSuccess) e = hipMemcpy(out, d, h->P.nnz_a * 8, hipMemcpyDeviceToHost);
+        if (e == hipSuccess) e = hipMemcpy(out, d, cnt * 8, hipMemcpyDeviceToHost);
         if (e != hipSuccess) st = dev_fail(h->err, e, "extract copy");
     }
     (void)hipFree(d);
@@ -1762,6 +1879,7 @@ selinv_status selinv_query(selinv_handle h, selinv_info *info) {
     info->symbolic = P.symbolic;
     info->nnz_l = P.tot_l;
     info->nnz_u = P.tot_u;
+    info->complex_values = h->cplx ? 1 : 0;
     return SELINV_OK;
 }
 
@@ -1780,7 +1898,7 @@ void selinv_destroy(selinv_handle h) {
     for (void *q : {(void *)h->d_diag, (void *)h->d_lpan, (void *)h->d_upan, (void *)h->d_Linv, (void *)h->d_Uinv,
                     (void *)h->d_tl, (void *)h->d_tu,
                     (void *)h->d_sn, (void *)h->d_supof, (void *)h->d_rl, (void *)h->d_ru, (void *)h->d_mapL,
-                    (void *)h->d_mapU, (void *)h->d_lcol, (void *)h->d_urow, (void *)h->d_aloc,
+                    (void *)h->d_mapU, (void *)h->d_lcol, (void *)h->d_urow, (void *)h->d_aloc, (void *)h->d_aloc_c,
                     (void *)h->d_kids_ptr, (void *)h->d_kids, (void *)h->d_push_off, (void *)h->d_push_pos, (void *)h->d_gcL, (void *)h->d_gcU})
         (void)hipFree(q);
     for (auto e : h->events) (void)hipEventDestroy(e);

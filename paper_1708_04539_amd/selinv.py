@@ -46,14 +46,16 @@ class Info(C.Structure):
                 ("nlevels", C.c_int32), ("max_s", C.c_int32), ("max_c", C.c_int32), ("flops", C.c_double),
                 ("flops_gemm", C.c_double), ("bytes_min_fp64", C.c_double), ("bytes_min_fp32", C.c_double),
                 ("max_gemm_flops", C.c_double), ("max_gemm_m", C.c_int32), ("max_gemm_n", C.c_int32),
-                ("max_gemm_k", C.c_int32), ("symbolic", C.c_int32), ("nnz_l", C.c_int64), ("nnz_u", C.c_int64)]
+                ("max_gemm_k", C.c_int32), ("symbolic", C.c_int32), ("nnz_l", C.c_int64), ("nnz_u", C.c_int64),
+                ("complex_values", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class Opts(C.Structure):
-    _fields_ = [("max_super", C.c_int32), ("relax", C.c_int32), ("pad_pct", C.c_int32), ("symbolic", C.c_int32)]
+    _fields_ = [("max_super", C.c_int32), ("relax", C.c_int32), ("pad_pct", C.c_int32), ("symbolic", C.c_int32),
+                ("complex_values", C.c_int32)]
 
 
 # analysis forms: pattern of At + At^T (R_L = R_U), or the exact pattern of L and U
@@ -127,7 +129,8 @@ def _prec(p):
 class SelInv:
     """One matrix: analyze (construction) -> factor -> run -> get*/export."""
 
-    def __init__(self, n, colptr, rowind, perm=None, max_super=0, relax=0, pad_pct=0, symbolic="symmetrized"):
+    def __init__(self, n, colptr, rowind, perm=None, max_super=0, relax=0, pad_pct=0, symbolic="symmetrized",
+                 complex_values=False):
         self._h = C.c_void_p()
         self.n = int(n)
         self._colptr = np.ascontiguousarray(colptr, dtype=np.int64)
@@ -138,7 +141,8 @@ class SelInv:
             self._perm = np.ascontiguousarray(perm, dtype=np.int32)
             pp = _p(self._perm, C.c_int32)
         sym = SYMBOLIC[symbolic] if isinstance(symbolic, str) else int(symbolic)
-        opts = Opts(int(max_super), int(relax), int(pad_pct), sym)
+        self.is_complex = bool(complex_values)
+        opts = Opts(int(max_super), int(relax), int(pad_pct), sym, 1 if self.is_complex else 0)
         rc = _lib.selinv_analyze(self.n, _p(self._colptr, C.c_int64), _p(self._rowind, C.c_int32), pp,
                                  C.byref(opts), C.byref(self._h))
         if rc:
@@ -151,7 +155,10 @@ class SelInv:
             raise SelinvError(rc, f"{what}: {_lib.selinv_last_error(self._h).decode()}")
 
     def factor(self, values):
-        v = np.ascontiguousarray(values, dtype=np.float64)
+        if self.is_complex:  # (re, im) per entry
+            v = np.ascontiguousarray(values, dtype=np.complex128).view(np.float64)
+        else:
+            v = np.ascontiguousarray(values, dtype=np.float64)
         self._check(_lib.selinv_factor(self._h, _p(v, C.c_double)), "factor")
         return self
 
@@ -160,18 +167,19 @@ class SelInv:
         self._check(f(self._h, _prec(precision), _stream_ptr(stream)), "run")
         return self
 
-    def get(self, i, j) -> float:
-        out = C.c_double()
-        self._check(_lib.selinv_get(self._h, int(i), int(j), C.byref(out)), "get")
-        return out.value
+    def get(self, i, j):
+        out = (C.c_double * 2)()
+        self._check(_lib.selinv_get(self._h, int(i), int(j), out), "get")
+        return complex(out[0], out[1]) if self.is_complex else out[0]
 
     def get_selected(self) -> np.ndarray:
-        out = np.empty(self.nnz, dtype=np.float64)
+        out = np.empty(self.nnz * (2 if self.is_complex else 1), dtype=np.float64)
         self._check(_lib.selinv_get_selected(self._h, _p(out, C.c_double)), "get_selected")
-        return out
+        return out.view(np.complex128) if self.is_complex else out
 
     def get_selected_device(self, out: "torch.Tensor", stream=None):
-        assert out.dtype == torch.float64 and out.is_cuda and out.numel() >= self.nnz and out.is_contiguous()
+        want = torch.complex128 if self.is_complex else torch.float64
+        assert out.dtype == want and out.is_cuda and out.numel() >= self.nnz and out.is_contiguous()
         self._check(_lib.selinv_get_selected_device(self._h, C.c_void_p(out.data_ptr()), _stream_ptr(stream)),
                     "get_selected_device")
         return out
@@ -187,7 +195,7 @@ class SelInv:
 
     def structure(self) -> dict:
         ns = self.info["nsuper"]
-        perm = np.empty(self.n, np.int32)
+        perm = np.empty(self.info["n"], np.int32)  # order of the plan (2 n for a complex handle)
         xsup = np.empty(ns + 1, np.int32)
         rlp = np.empty(ns + 1, np.int64)
         rup = np.empty(ns + 1, np.int64)

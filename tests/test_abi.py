@@ -321,3 +321,47 @@ def test_autotune_describe():
     d = describe([1, 2, 1, 64, 32, 32, 32, 64, 0, 128, 128, 1])
     assert d["steps35_tiles"] == [32, 128] and d["step4_tiles"] == [64, 128]
     assert d["small_per_phase_levels"] == [1] and d["sweep"] == "levels"
+
+
+# --------------------------------------------------------------------------
+# complex matrices (real form of order 2n), host side
+# --------------------------------------------------------------------------
+def test_complex_handle_is_the_real_form(si):
+    """A complex handle analyses M (entry a -> [[Re a, -Im a], [Im a, Re a]],
+    node rows and columns interleaved): its plan equals the plan of a real
+    handle built on that pattern and ordering."""
+    from workloads import config_complex
+    w = config_complex((24, 20), "box", 1, 16, 16)
+    z = si.SelInv(w.n, w.colptr, w.rowind, w.perm, w.max_super, w.relax, w.pad_pct, complex_values=True)
+    assert z.info["complex_values"] == 1 and z.info["n"] == 2 * w.n and z.info["nnz_a"] == 4 * w.nnz
+    assert z.check_plan() == 0
+    cols = np.repeat(np.arange(w.n), np.diff(w.colptr))
+    r2, c2 = [], []
+    for i, j in zip(w.rowind, cols):
+        for a in range(2):
+            for b in range(2):
+                r2.append(2 * i + a)
+                c2.append(2 * j + b)
+    m = sp.csc_matrix((np.ones(len(r2)), (r2, c2)), shape=(2 * w.n, 2 * w.n))
+    m.sort_indices()
+    perm2 = np.stack([2 * w.perm, 2 * w.perm + 1], 1).ravel().astype(np.int32)
+    r = si.SelInv(2 * w.n, m.indptr.astype(np.int64), m.indices.astype(np.int32), perm2, w.max_super, w.relax,
+                  w.pad_pct)
+    a, b = z.structure(), r.structure()
+    for k in STRUCT_KEYS:
+        assert np.array_equal(a[k], b[k]), k
+    x = si.SelInv(w.n, w.colptr, w.rowind, w.perm, w.max_super, 0, 0, symbolic="exact", complex_values=True)
+    assert x.check_plan() == 0 and x.info["symbolic"] == 1
+
+
+def test_complex_error_paths(si):
+    cp = np.array([0, 2, 4], np.int64)
+    with pytest.raises(si.SelinvError) as e:
+        si.SelInv(2, cp, np.array([0, 1, 0, 1], np.int32), np.array([1, 1], np.int32), complex_values=True)
+    assert e.value.status == "BAD_PERM"
+    with pytest.raises(si.SelinvError) as e:
+        si.SelInv(2, cp, np.array([0, 2, 0, 1], np.int32), complex_values=True)
+    assert e.value.status == "BAD_PATTERN"
+    with pytest.raises(si.SelinvError) as e:
+        si.SelInv(2, cp, np.array([1, 0, 0, 1], np.int32), complex_values=True)
+    assert e.value.status == "BAD_PATTERN"

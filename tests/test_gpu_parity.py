@@ -589,3 +589,116 @@ def test_tune_exact_upwind_and_cache(si, tmp_path):
     assert r2["cached"] and r2["table"] == r1["table"] and s2.get_tuning("fp64") == r1["table"]
     s2.run("fp64")
     compare_superset(s2, o, TOL["fp64"])
+
+
+# --------------------------------------------------------------------------
+# complex matrices (real form), against the complex oracle (the definition)
+# --------------------------------------------------------------------------
+def random_complex(n, dens, seed):
+    """Random complex matrix on random_sparse's pattern: off-diagonals
+    v (1 + 0.3 i u), diagonal 1.35 Re + 0.2 i |.|, u ~ U[-1, 1]."""
+    cp, ri, v, _ = random_sparse(n, dens, seed)
+    rng = np.random.default_rng(seed + 1000)
+    cols = np.repeat(np.arange(n), np.diff(cp))
+    z = v * (1 + 0.3j * rng.uniform(-1, 1, v.size))
+    d = ri == cols
+    z[d] = 1.35 * v[d] + 0.2j * np.abs(v[d])
+    return cp, ri, z
+
+
+def complex_errs(X, R, rows, cols):
+    err_norm = np.abs(X - R).max() / np.abs(R).max()
+    dg = rows == cols
+    err_diag = (np.abs(X[dg] - R[dg]) / np.abs(R[dg])).max() if dg.any() else 0.0
+    return err_norm, err_diag
+
+
+COMPLEX_CASES = [  # n, density, seed, cap (real-form columns), symbolic
+    (1, 0.0, 0, 2, "symmetrized"),
+    (2, 0.5, 1, 2, "symmetrized"),
+    (37, 0.08, 2, 6, "symmetrized"),
+    (150, 0.03, 3, 32, "exact"),
+    (300, 0.01, 4, 64, "symmetrized"),
+    (300, 0.02, 5, 16, "exact"),
+]
+
+
+@pytest.mark.parametrize("case", COMPLEX_CASES, ids=[f"n{c[0]}_{c[4]}" for c in COMPLEX_CASES])
+@pytest.mark.parametrize("prec", ["fp64", "mixed_fp32"])
+def test_complex_random_selected(si, case, prec):
+    from oracle.complex_ref import selected_dense
+    n, dens, seed, cap, sym = case
+    say("complex random", case, prec)
+    cp, ri, z = random_complex(n, dens, seed)
+    perm = np.random.default_rng(seed).permutation(n).astype(np.int32)
+    s = si.SelInv(n, cp, ri, perm, cap, 0, 0, symbolic=sym, complex_values=True)
+    assert s.check_plan() == 0
+    s.factor(z).run(prec)
+    got, ref = s.get_selected(), selected_dense(n, cp, ri, z)
+    cols = np.repeat(np.arange(n), np.diff(cp))
+    en, ed = complex_errs(got, ref, ri, cols)
+    assert max(en, ed) <= TOL[prec], (en, ed)
+    for p in np.random.default_rng(seed).integers(0, len(ri), 5):
+        assert s.get(int(cols[p]), int(ri[p])) == got[p]  # out[p] = A^{-1}(j, i)
+
+
+@pytest.fixture(scope="module")
+def z48(si):
+    from oracle.complex_ref import selected_dense
+    from workloads import config_complex
+    w = config_complex((48, 48), "box", 2, 32, 32)
+    say("complex 48x48 setup")
+    s = si.SelInv(w.n, w.colptr, w.rowind, w.perm, w.max_super, w.relax, w.pad_pct, complex_values=True)
+    s.factor(w.values)
+    return w, s, selected_dense(w.n, w.colptr, w.rowind, w.values)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed_fp32", "mixed_bf16x3"])
+def test_complex_stencil_selected(si, z48, prec):
+    import torch
+    w, s, ref = z48
+    say("complex 48x48", prec)
+    s.run(prec)
+    got = s.get_selected()
+    cols = np.repeat(np.arange(w.n), np.diff(w.colptr))
+    en, ed = complex_errs(got, ref, w.rowind, cols)
+    say("complex 48x48", prec, "err_norm", en, "err_diag", ed)
+    assert max(en, ed) <= TOL[prec]
+    dev = torch.empty(w.nnz, dtype=torch.complex128, device="cuda")
+    s.get_selected_device(dev)
+    torch.cuda.synchronize()
+    assert np.array_equal(dev.cpu().numpy(), got)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed_fp32"])
+def test_complex_z1_full_size(si, prec):
+    """n = 65536 complex (131072 real-form columns): sampled exact columns and
+    the identities sum_j A(i,j) A^{-1}(j,i) = 1 = sum_i A(i,j) A^{-1}(j,i)."""
+    from oracle.complex_ref import solve_columns
+    from workloads import config_z1
+    w = getattr(test_complex_z1_full_size, "_w", None) or config_z1()
+    test_complex_z1_full_size._w = w
+    say("z1", prec)
+    s = getattr(test_complex_z1_full_size, "_s", None)
+    if s is None:
+        s = si.SelInv(w.n, w.colptr, w.rowind, w.perm, w.max_super, w.relax, w.pad_pct,
+                      complex_values=True).factor(w.values)
+        test_complex_z1_full_size._s = s
+    s.run(prec)
+    sel = s.get_selected()
+    cols = np.repeat(np.arange(w.n), np.diff(w.colptr))
+    prod = w.values * sel
+    rr = np.abs(np.bincount(w.rowind, prod.real, w.n) + 1j * np.bincount(w.rowind, prod.imag, w.n) - 1).max()
+    cr = np.abs(np.bincount(cols, prod.real, w.n) + 1j * np.bincount(cols, prod.imag, w.n) - 1).max()
+    js = [int(j) for j in np.random.default_rng(7).integers(0, w.n, 2)] + [int(w.perm[-1])]
+    xs = solve_columns(w.n, w.colptr, w.rowind, w.values, js)
+    A = w.to_scipy().tocsr()
+    en = ed = 0.0
+    for j, x in zip(js, xs):
+        rows = A.indices[A.indptr[j]:A.indptr[j + 1]]  # A(j, i) != 0 -> A^{-1}(i, j) selected
+        got = np.array([s.get(int(i), j) for i in rows])
+        en = max(en, np.abs(got - x[rows]).max() / np.abs(x[rows]).max())
+        ed = max(ed, abs(s.get(j, j) - x[j]) / abs(x[j]))
+    say("z1", prec, "identity", rr, cr, "sampled", en, ed)
+    assert max(rr, cr) <= (1e-10 if prec == "fp64" else 1e-4)
+    assert max(en, ed) <= TOL[prec]

@@ -298,3 +298,42 @@ def test_error_paths():
     with pytest.raises(OracleError) as e:
         o3.get(0, 2)
     assert e.value.status == "NOT_SELECTED"
+
+
+# --------------------------------------------------------------------------
+# complex selected entries from their definition (oracle/complex_ref.py)
+# --------------------------------------------------------------------------
+def test_complex_oracle_diagonal_and_2x2_closed_forms():
+    from oracle.complex_ref import selected_dense
+    d = np.array([2 + 1j, -1 + 3j, 0.5 - 0.25j])
+    cp = np.arange(4, dtype=np.int64)
+    ri = np.arange(3, dtype=np.int32)
+    assert np.allclose(selected_dense(3, cp, ri, d), 1 / d, rtol=1e-15, atol=0)
+    # [[a, b], [c, e]]^{-1} = [[e, -b], [-c, a]] / (a e - b c)
+    a, b, c, e = 3 + 1j, -1 + 0.5j, 0.25 - 2j, 4 - 1j
+    cp = np.array([0, 2, 4], np.int64)
+    ri = np.array([0, 1, 0, 1], np.int32)
+    vals = np.array([a, c, b, e])  # CSC: column 0 = (a, c), column 1 = (b, e)
+    det = a * e - b * c
+    inv = np.array([[e, -b], [-c, a]]) / det
+    # out[p] = A^{-1}(j, i) for entry p at (i, j)
+    want = np.array([inv[0, 0], inv[0, 1], inv[1, 0], inv[1, 1]])
+    assert np.allclose(selected_dense(2, cp, ri, vals), want, rtol=1e-14, atol=0)
+
+
+def test_complex_oracle_sparse_columns_match_dense():
+    """The two routes of the complex oracle (LAPACK dense inverse, SuperLU
+    solves) agree, and the dense one satisfies A X = I."""
+    from oracle.complex_ref import selected_dense, solve_columns, to_dense
+    from workloads import stencil_csc_complex
+    cp, ri, v = stencil_csc_complex((12, 10), "box", 0.05, seed=4)
+    n = 120
+    A = to_dense(n, cp, ri, v)
+    inv = np.linalg.inv(A)
+    assert np.abs(A @ inv - np.eye(n)).max() < 1e-12
+    xs = solve_columns(n, cp, ri, v, [0, 57, 119])
+    for j, x in zip([0, 57, 119], xs):
+        assert np.abs(x - inv[:, j]).max() < 1e-13 * np.abs(inv).max()
+    sel = selected_dense(n, cp, ri, v)
+    cols = np.repeat(np.arange(n), np.diff(cp))
+    assert np.array_equal(sel, inv[cols, ri])

@@ -18,6 +18,9 @@ from .grids import (  # noqa: F401
     config_upwind,
     config_u1,
     config_u4,
+    config_complex,
+    config_z1,
+    stencil_csc_complex,
     get_config,
     random_sparse,
     tridiag_csc,

@@ -298,12 +298,71 @@ def config_u4() -> Workload:
     return config_upwind((64, 64, 64), "box", 0.25, 0, 512, 64)
 
 
+def stencil_csc_complex(dims, kind: str, margin: float, seed=None, delta: float = 0.2, eta: float = 0.5):
+    """Complex grid stencil shaped like a shifted Hamiltonian H - zS.
+
+    Per unordered neighbour pair a symmetric weight w ~ U[-1, 0]; each ordered
+    entry is w (1 + i eps), eps ~ U[-delta, delta] drawn independently.  The
+    diagonal is the row sum of |off-diagonals| plus ``margin``, plus i*eta, so
+    its real part dominates the row (an unpivoted LU exists and is stable).
+    Returns (colptr, rowind, values complex128).
+    """
+    dims3 = tuple(int(d) for d in dims) + (1,) * (3 - len(dims))
+    ndim = len(dims)
+    n = dims3[0] * dims3[1] * dims3[2]
+    rng = np.random.default_rng(seed)
+    rows, cols, vals = [], [], []
+    for off in _offsets(ndim, kind):
+        if (off[2], off[1], off[0]) <= (0, 0, 0):
+            continue
+        i, j = _pairs(dims3, off)
+        w = rng.uniform(-1.0, 0.0, size=i.size)
+        e_ij = rng.uniform(-delta, delta, size=i.size)
+        e_ji = rng.uniform(-delta, delta, size=i.size)
+        rows += [i, j]
+        cols += [j, i]
+        vals += [w * (1 + 1j * e_ij), w * (1 + 1j * e_ji)]
+    rows = np.concatenate(rows)
+    cols = np.concatenate(cols)
+    vals = np.concatenate(vals)
+    diag = np.zeros(n)
+    np.add.at(diag, rows, np.abs(vals))
+    dvals = diag + margin + 1j * eta
+    m = sp.csc_matrix((np.concatenate([vals, dvals]), (np.concatenate([rows, np.arange(n)]),
+                                                       np.concatenate([cols, np.arange(n)]))), shape=(n, n))
+    m.sum_duplicates()
+    m.sort_indices()
+    return m.indptr.astype(np.int64), m.indices.astype(np.int32), m.data.astype(np.complex128)
+
+
+def config_complex(dims=(64, 64), kind: str = "box", seed: int = 0, max_nodes: int = 64,
+                   leaf: int = 64) -> Workload:
+    """Complex stencil (stencil_csc_complex), nested-dissection order.  The
+    library holds a complex matrix in its real form of order 2n, so the
+    supernode sizes (max_super, relax) count 2 real columns per node."""
+    colptr, rowind, values = stencil_csc_complex(dims, kind, 0.05, seed)
+    n = int(np.prod(dims))
+    pts = {("star", 2): 5, ("box", 2): 9, ("star", 3): 7, ("box", 3): 27}[(kind, len(dims))]
+    return Workload(name="z" + "x".join(str(d) for d in dims), n=n, colptr=colptr, rowind=rowind,
+                    values=values, perm=nested_dissection(dims, leaf), max_super=2 * max_nodes,
+                    relax=2 * leaf, dims=tuple(dims),
+                    desc=f"complex {len(dims)}D {'x'.join(str(d) for d in dims)} {pts}-point shifted stencil, "
+                         f"n={n}, supernodes <= {max_nodes} nodes",
+                    extra={"complex": True})
+
+
+def config_z1() -> Workload:
+    """Complex counterpart of C1: 2D 256x256 9-point stencil, n = 65536,
+    supernodes of at most 128 nodes (256 columns of the real form)."""
+    return config_complex((256, 256), "box", 0, 128, 64)
+
+
 CONFIG_NAMES = ("c0", "c1", "c2", "c3", "c4")
 
 
 def get_config(name: str):
     return {"c0": config_c0, "c1": config_c1, "c2": config_c2, "c3": config_c3,
-            "c4": config_c4, "u1": config_u1, "u4": config_u4}[name]()
+            "c4": config_c4, "u1": config_u1, "u4": config_u4, "z1": config_z1}[name]()
 
 
 # ----------------------------------------------------------------------------
