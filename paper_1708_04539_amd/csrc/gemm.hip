@@ -126,7 +126,15 @@ hipError_t launch_gemm(int role, int mode, int tile, const GemmProb *probs, cons
         case GEMM_PRO_F64:  // FP64 in and out
             launch_mode<CMP_F64, double, double, 0>(tile, probs, tiles, ntiles, st);
             break;
-        case GEMM_PRO_F32OUT:  // FP64 in, FP32 out (normalised panels of the mixed forms)
+        case GEMM_PRO_MIXED:  // FP64 operands rounded when staged, FP32 or split-BF16 products, FP32 out
+            if (mode == CMP_F32)
+                launch_mode<CMP_F32, double, float, 0>(tile, probs, tiles, ntiles, st);
+            else if (mode == CMP_BF16X3)
+                launch_mode<CMP_BF16X3, double, float, 0>(tile, probs, tiles, ntiles, st);
+            else
+                return hipErrorInvalidValue;
+            break;
+        case GEMM_PRO_F32OUT:  // FP64 in, FP32 out, FP64 arithmetic
             launch_mode<CMP_F64, double, float, 0>(tile, probs, tiles, ntiles, st);
             break;
         case GEMM_STEP35:  // operands and results in the run's storage precision

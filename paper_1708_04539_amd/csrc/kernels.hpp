@@ -20,7 +20,8 @@ enum : int { GEMM_TILE_32 = 32, GEMM_TILE_64 = 64, GEMM_TILE_128 = 128 };
 // launch sites of the grouped GEMM (each is its own kernel symbol in profiles)
 enum : int {
     GEMM_PRO_F64 = 0,     // FP64 -> FP64 (triangular rounds, normalisation, diag init)
-    GEMM_PRO_F32OUT = 1,  // FP64 -> FP32 (normalisation in the mixed forms)
+    GEMM_PRO_F32OUT = 1,  // FP64 -> FP32 in FP64 arithmetic
+    GEMM_PRO_MIXED = 4,   // FP64 operands -> FP32, in the mode's arithmetic (normalisation of the mixed forms)
     GEMM_STEP35 = 2,      // steps 3 and 5, operands/results in the storage precision
     GEMM_STEP4 = 3        // step 4, accumulated into the FP64 diagonal block
 };

@@ -499,7 +499,8 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, int sweep_mo
                 PR.tri_rounds.push_back(rr);
             }
         }
-        // normalisation (FP64 arithmetic, output in the run's precision)
+        // normalisation (FP64 arithmetic in the FP64 form, the bulk arithmetic of
+        // the mixed forms; output in the run's precision)
         size_t first = probs.size();
         for (size_t mi = 0; mi < hs.size(); mi++) {
             selinv_handle h = hs[mi];
@@ -862,7 +863,10 @@ hipError_t launch_sweep(const Sweep &S, hipStream_t st, std::vector<hipEvent_t> 
         return hipSuccess;
     };
     auto norm_part = [&](const Sweep::Prologue &P, hipStream_t s) -> hipError_t {
-        return launch_gemm(f64 ? GEMM_PRO_F64 : GEMM_PRO_F32OUT, CMP_F64, P.norm.tile, S.d_probs,
+        // the mixed forms run the normalisation in their bulk arithmetic (FP32
+        // or split-BF16 from the FP64 factors); FP64 stays for the diagonal
+        // inversions and the diagonal blocks of A^{-T}
+        return launch_gemm(f64 ? GEMM_PRO_F64 : GEMM_PRO_MIXED, f64 ? CMP_F64 : mode, P.norm.tile, S.d_probs,
                            S.d_tiles + P.norm.off, P.norm.count, s);
     };
     auto dt_part = [&](const Sweep::Prologue &P, hipStream_t s) -> hipError_t {
