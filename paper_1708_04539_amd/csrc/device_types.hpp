@@ -100,6 +100,19 @@ struct SmallItem {
     int64_t g_off, c_off;
 };
 
+// split-K of a step-4 product: C(M x N, ld ldc) += sum of nparts partial
+// products P[p * pstride + m + n M], added in order p = 0, 1, ...; with
+// push_sn >= 0 the final entries also go into G of that supernode's children
+// (as the push of an unsplit step-4 product, see GemmProb), G in FP32 when
+// g_f32
+struct ReduceItem {
+    double *C;
+    const double *P;
+    int32_t M, N, ldc, nparts;
+    int64_t pstride;
+    int32_t push_sn, push_mat, g_f32, pad;
+};
+
 // extraction of the selected entries
 struct ExtractArgs {
     const int64_t *loc;  // kind << 60 | offset per entry of A

@@ -279,6 +279,43 @@ __global__ __launch_bounds__(256) void gather_kernel(const MatDev *__restrict__ 
 }
 
 // ---------------------------------------------------------------------------
+// split-K reduction of the step-4 products
+// ---------------------------------------------------------------------------
+// blockIdx.y = item; each thread one entry of C; the partial products are
+// added in a fixed order, so the result does not depend on the schedule.
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(const ReduceItem *__restrict__ items,
+                                                            const MatDev *__restrict__ mats) {
+    const ReduceItem it = items[blockIdx.y];
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x, mn = (int64_t)it.M * it.N;
+    if (e >= mn) return;
+    const int m = (int)(e % it.M), n = (int)(e / it.M);
+    SELINV_GLOBAL double *C = gptr_w(it.C) + m + (int64_t)n * it.ldc;
+    const SELINV_GLOBAL double *P = gptr(it.P) + e;
+    double acc = *C;
+    for (int p = 0; p < it.nparts; p++) acc += P[p * it.pstride];
+    *C = acc;
+    if (it.push_sn < 0) return;
+    // the final entry (m, n) of A^{-T}(P,P) into G_K of every child K of P
+    // (the children's gathers skip these entries)
+    const MatDev &Md = mats[it.push_mat];
+    const SELINV_GLOBAL SnRec *sn = gptr(Md.sn);
+    const SELINV_GLOBAL int32_t *kp = gptr(Md.kids_ptr);
+    const SELINV_GLOBAL int32_t *kids = gptr(Md.kids);
+    const int Pa = it.push_sn, sP = it.M;
+    for (int q = kp[Pa]; q < kp[Pa + 1]; q++) {
+        const int32_t K = kids[q];
+        const SELINV_GLOBAL int32_t *posL = gptr(Md.push_pos) + gptr(Md.push_off)[K];
+        const int a = posL[m], b = posL[sP + n];
+        if (a < 0 || b < 0) continue;
+        const int64_t g = sn[K].g_off + a + (int64_t)b * sn[K].cl;
+        if (it.g_f32)
+            gptr_w((float *)Md.G)[g] = (float)acc;
+        else
+            gptr_w((double *)Md.G)[g] = acc;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // extraction
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -319,6 +356,14 @@ hipError_t launch_gather(int f64, const MatDev *mats, const GatherTile *tiles, i
         hipLaunchKernelGGL(gather_kernel<double>, dim3(ntiles), dim3(256), 0, st, mats, tiles);
     else
         hipLaunchKernelGGL(gather_kernel<float>, dim3(ntiles), dim3(256), 0, st, mats, tiles);
+    return hipGetLastError();
+}
+
+hipError_t launch_splitk_reduce(const ReduceItem *items, int count, int64_t max_mn, const MatDev *mats,
+                                hipStream_t st) {
+    if (count <= 0 || max_mn <= 0) return hipSuccess;
+    hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)((max_mn + 255) / 256), count), dim3(256), 0, st, items,
+                       mats);
     return hipGetLastError();
 }
 

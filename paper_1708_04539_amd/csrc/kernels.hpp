@@ -39,6 +39,10 @@ hipError_t launch_step4_gather(int mode, int tile, const GemmProb *probs, const 
 hipError_t launch_small(int mode, const MatDev *mats, const GemmProb *probs, const SmallItem *items, int count,
                         hipStream_t st);
 hipError_t launch_extract(int f64, const ExtractArgs &a, hipStream_t st);
+// C += sum of the split-K partial products, for `count` items (count <= 65535),
+// pushing the results into the children's G where an item asks for it
+hipError_t launch_splitk_reduce(const ReduceItem *items, int count, int64_t max_mn, const MatDev *mats,
+                                hipStream_t st);
 
 // persistent sweep (64x64 product tiles): resets the ncnt counters, the queue
 // head and the error flag, then runs the task queue on `grid` workgroups

@@ -64,6 +64,12 @@ struct Sweep {
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     std::vector<Range> small, gat, g35, g4;
+    // split-K step 4: per level the reduction items (red4[d].count of them,
+    // red4_mn[d] the largest M N), the partial products in ws4
+    std::vector<Range> red4;
+    std::vector<int64_t> red4_mn;
+    ReduceItem *d_red = nullptr;
+    double *d_ws4 = nullptr;
     // gather tiles of level d + 1 launched with the step-4 products of level
     // d (fused[d + 1]); those products push A^{-T}(P,P) into the children's G
     std::vector<Range> g4gat;
@@ -96,6 +102,8 @@ struct Sweep {
         (void)hipFree(d_tiles);
         (void)hipFree(d_gt);
         (void)hipFree(d_small);
+        (void)hipFree(d_red);
+        (void)hipFree(d_ws4);
         (void)hipFree(d_ptasks);
         (void)hipFree(d_psn);
         (void)hipFree(d_deps);
@@ -221,6 +229,11 @@ constexpr double kTile32Below = 512;
 // levels at least this wide (in supernodes) start the part of the prologue
 // that runs beside the sweep of the levels above
 constexpr int kSplitWidth = 64;
+// split-K of step 4: levels whose step-4 launch has fewer 64x64 tiles than
+// this cut the k range of their products (k >= 2 kSplitKMin) into parts of at
+// least kSplitKMin, up to 8, aiming at about 1024 tiles
+constexpr double kSplitKBelow = 512;
+constexpr int kSplitKMin = 512;
 constexpr double kTile128From = 192;
 
 // row-block major: the tiles of one strip of op(A) are neighbours in the
@@ -255,6 +268,21 @@ void emit_launch(const std::vector<GemmProb> &probs, size_t first, std::vector<G
         r.tile = GEMM_TILE_128;
     r.off = tiles.size();
     for (size_t q = first; q < probs.size(); q++) add_tiles(tiles, (int)q, probs[q].M, probs[q].N, r.tile);
+    r.count = (int)(tiles.size() - r.off);
+}
+
+// As emit_launch, over the problems listed in `idx` (in that order).
+void emit_launch_list(const std::vector<GemmProb> &probs, const std::vector<int> &idx, std::vector<GemmTile> &tiles,
+                      Range &r, bool allow128 = false, int forced = 0) {
+    std::vector<GemmProb> sub;
+    sub.reserve(idx.size());
+    for (int q : idx) sub.push_back(probs[q]);
+    Range tmp;
+    std::vector<GemmTile> t2;
+    emit_launch(sub, 0, t2, tmp, allow128, forced);
+    r.tile = tmp.tile;
+    r.off = tiles.size();
+    for (const GemmTile &t : t2) tiles.push_back(GemmTile{idx[t.prob], t.m0, t.n0, 0});
     r.count = (int)(tiles.size() - r.off);
 }
 
@@ -592,6 +620,49 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, int sweep_mo
         for (int d = 1; d < hs[mi]->P.nlevels; d++)
             for (int32_t K : hs[mi]->P.levels[d])
                 if (!hs[mi]->P.one_top[K]) S->fused[d] = 0;
+    // Split-K of the step-4 products (s x s, k = c_U) on levels whose step-4
+    // launch cannot fill the device: the parts write FP64 partial products
+    // that a reduction launch adds to A^{-T}(K,K) in a fixed order.  The next
+    // level's gather still runs in the step-4 launch (skipping the parent's
+    // diagonal block); the reduction pushes that block into the children's G.
+    std::vector<int> parts4(nsn, 1);
+    std::vector<int64_t> ws_off4(nsn, -1);
+    std::vector<char> split4(depth, 0);
+    int64_t ws_elems = 0;
+    for (int d = 0; d < depth; d++) {
+        cur_level = d;
+        double t64 = 0;
+        for (size_t mi = 0; mi < hs.size(); mi++) {
+            if (d >= hs[mi]->P.nlevels) continue;
+            for (int32_t K : hs[mi]->P.levels[d]) {
+                const SnRec &r = hs[mi]->sn[K];
+                if (!is_small(r) && r.cu > 0) t64 += std::ceil(r.s / 64.0) * std::ceil(r.s / 64.0);
+            }
+        }
+        if (t64 <= 0 || t64 >= kSplitKBelow) continue;
+        const int lvl_parts = std::min(8, (int)std::ceil(1024.0 / t64));
+        for (size_t mi = 0; mi < hs.size(); mi++) {
+            if (d >= hs[mi]->P.nlevels) continue;
+            for (int32_t K : hs[mi]->P.levels[d]) {
+                const SnRec &r = hs[mi]->sn[K];
+                const int sp = std::min(lvl_parts, r.cu / kSplitKMin);
+                if (is_small(r) || sp < 2) continue;
+                const int32_t gid = gbase[mi] + K;
+                parts4[gid] = sp;
+                ws_off4[gid] = ws_elems;
+                ws_elems += (int64_t)sp * r.s * r.s;
+                split4[d] = 1;
+            }
+        }
+    }
+    std::vector<int> red_of(nsn, -1);  // reduction item of a split supernode
+    if (ws_elems) {
+        HIPCHK(err, alloc_bytes((void **)&S->d_ws4, ws_elems * 8), "alloc split-K workspace");
+        X.add(S->d_ws4, ws_elems * 8);
+    }
+    std::vector<ReduceItem> reds;
+    S->red4.assign(depth, Range());
+    S->red4_mn.assign(depth, 0);
     S->g4gat.resize(depth);
     for (int d = 0; d < depth; d++) {
         cur_level = d;
@@ -648,6 +719,8 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, int sweep_mo
         // step 4
         for (int pass = 0; pass < 2; pass++) {
             first = probs.size();
+            std::vector<int> lst;  // problems of the step-4 launch
+            if (pass == 0) S->red4[d].off = reds.size();
             for (size_t mi = 0; mi < hs.size(); mi++) {
                 selinv_handle h = hs[mi];
                 if (d >= h->P.nlevels) continue;
@@ -664,9 +737,34 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, int sweep_mo
                                        ? (int)probs.size() - 1
                                        : -1;
                     (pass == 0 ? S->lev_flops4[d] : S->lev_small_flops[d]) += 2.0 * r.s * (double)r.s * r.cu;
+                    if (pass != 0 || prob_g4[gid] < 0) continue;
+                    if (parts4[gid] < 2) {
+                        lst.push_back(prob_g4[gid]);
+                        continue;
+                    }
+                    // split-K: parts of kc (a multiple of 64) columns of k
+                    const int sp = parts4[gid];
+                    const int kc = ((r.cu + sp - 1) / sp + 63) / 64 * 64;
+                    double *P0 = S->d_ws4 + ws_off4[gid];
+                    int np = 0;
+                    for (int k0 = 0; k0 < r.cu; k0 += kc, np++) {
+                        add_prob(probs, ZU + (int64_t)k0 * e, 1, r.cu, Uh + (int64_t)k0 * e, 0, r.cu,
+                                 P0 + (int64_t)np * r.s * r.s, r.s, nullptr, 1, r.s, r.s, std::min(kc, r.cu - k0),
+                                 -1.0, 0.0, &X, e, 8);
+                        lst.push_back((int)probs.size() - 1);
+                    }
+                    X.check(b.Zd + r.off_d, r.s, r.s, r.s, 8);
+                    X.check(P0, (int64_t)r.s * r.s, np, (int64_t)r.s * r.s, 8);
+                    red_of[gid] = (int)reds.size();
+                    reds.push_back(ReduceItem{b.Zd + r.off_d, P0, r.s, r.s, r.s, np, (int64_t)r.s * r.s, -1, -1,
+                                              e == 4, 0});
+                    S->red4_mn[d] = std::max<int64_t>(S->red4_mn[d], (int64_t)r.s * r.s);
                 }
             }
-            if (pass == 0) emit_launch(probs, first, tiles, S->g4[d], mode_of(prec) == CMP_BF16X3, t4_of(d));
+            if (pass == 0) {
+                S->red4[d].count = (int)(reds.size() - S->red4[d].off);
+                emit_launch_list(probs, lst, tiles, S->g4[d], mode_of(prec) == CMP_BF16X3, t4_of(d));
+            }
         }
         S->g4gat[d].off = gts.size();
         if (d + 1 < depth && S->fused[d + 1]) {
@@ -684,6 +782,12 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, int sweep_mo
                         probs[pg].push_sn = Pa;
                         probs[pg].push_mat = (int32_t)mi;
                         skip = Pa;
+                        // a split product is pushed by its reduction
+                        const int ri = red_of[gbase[mi] + Pa];
+                        if (ri >= 0) {
+                            reds[ri].push_sn = Pa;
+                            reds[ri].push_mat = (int32_t)mi;
+                        }
                     }
                     for (int b0 = 0; b0 < r.cu; b0 += 64)
                         for (int a0 = 0; a0 < r.cl; a0 += 64)
@@ -828,6 +932,11 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, int sweep_mo
     for (auto h : hs)
         for (const SnRec &r : h->sn)
             if (r.s > TRI_MAX_S || r.off_d + (int64_t)r.s * r.s > h->P.tot_d) X.violations++;
+    // every level's reduction items lie inside the uploaded list
+    for (int d = 0; d < depth; d++)
+        if (S->red4[d].off < 0 || S->red4[d].count < 0 ||
+            S->red4[d].off + S->red4[d].count > (int64_t)reds.size())
+            X.violations++;
     if (X.violations) {
         err = "internal error: " + std::to_string(X.violations) + " work-list entries outside their buffers";
         return SELINV_E_INVALID_ARG;
@@ -838,6 +947,7 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, int sweep_mo
     HIPCHK(err, upload(&S->d_tiles, tiles), "upload tiles");
     HIPCHK(err, upload(&S->d_gt, gts), "upload gather tiles");
     HIPCHK(err, upload(&S->d_small, smalls), "upload small supernodes");
+    HIPCHK(err, upload(&S->d_red, reds), "upload split-K reductions");
     out = std::move(S);
     return SELINV_OK;
 }
@@ -922,6 +1032,8 @@ hipError_t launch_sweep(const Sweep &S, hipStream_t st, std::vector<hipEvent_t> 
         mark(6 + 4 * d);
         if ((e = launch_step4_gather(mode, S.g4[d].tile, S.d_probs, S.d_tiles + S.g4[d].off, S.g4[d].count,
                                      S.d_mats, S.d_gt + S.g4gat[d].off, S.g4gat[d].count, st)))
+            return e;
+        if ((e = launch_splitk_reduce(S.d_red + S.red4[d].off, S.red4[d].count, S.red4_mn[d], S.d_mats, st)))
             return e;
         mark(7 + 4 * d);
     }
