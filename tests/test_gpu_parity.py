@@ -702,3 +702,37 @@ def test_complex_z1_full_size(si, prec):
     say("z1", prec, "identity", rr, cr, "sampled", en, ed)
     assert max(rr, cr) <= (1e-10 if prec == "fp64" else 1e-4)
     assert max(en, ed) <= TOL[prec]
+
+
+# --------------------------------------------------------------------------
+# split-K of the step-4 products, over the whole computed set
+# --------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def split_pair(si):
+    """3D 32^3 27-point stencil, supernodes <= 256: levels 4-6 have one or two
+    supernodes with c_U >= 1024, so their step-4 products are split in k."""
+    from workloads import config_grid
+    w = config_grid("split", (32, 32, 32), "box", "sym_perturbed", 0.1, 5, 256, 64, delta=0.15)
+    say("split-K setup")
+    s, o = lib_and_oracle(si, w.n, w.colptr, w.rowind, w.values, w.perm, w.max_super, w.relax, w.pad_pct)
+    st = s.structure()
+    wd, cl, cu, lev = (np.diff(st["xsup"]), np.diff(st["rl_ptr"]), np.diff(st["ru_ptr"]), st["level"])
+    split = []
+    for d in range(lev.max() + 1):
+        m = (lev == d) & (cu > 0) & ~((wd <= 64) & (cl <= 64) & (cu <= 64))
+        t64 = (np.ceil(wd[m] / 64) ** 2).sum()
+        if 0 < t64 < 512 and (cu[m] // 512 >= 2).any():
+            split.append(d)
+    assert split  # the case exercises the split products and their reduction
+    return w, s, o
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed_fp32", "mixed_bf16x3"])
+def test_split_k_whole_superset(si, split_pair, prec):
+    w, s, o = split_pair
+    say("split-K", prec)
+    s.run(prec)
+    en, ed = compare_superset(s, o, TOL[prec])
+    say("split-K", prec, "err_norm", en, "err_diag", ed)
+    s.run(prec, graph=True)
+    compare_superset(s, o, TOL[prec])

@@ -15,6 +15,7 @@ from .grids import (  # noqa: F401
     config_c2,
     config_c3,
     config_c4,
+    config_grid,
     config_upwind,
     config_u1,
     config_u4,

@@ -269,6 +269,14 @@ def config_c4() -> Workload:
                           delta=0.15)
 
 
+def config_grid(name, dims, kind, value_mode, margin, seed, max_super, leaf, **kw) -> Workload:
+    """A stencil workload of any grid (stencil_csc arguments), nested-dissection order."""
+    pts = {("star", 2): 5, ("box", 2): 9, ("star", 3): 7, ("box", 3): 27}[(kind, len(dims))]
+    return _grid_workload(name, tuple(dims), kind, value_mode, margin, seed, max_super, leaf,
+                          f"{len(dims)}D {'x'.join(str(d) for d in dims)} {pts}-point {value_mode}, "
+                          f"n={int(np.prod(dims))}, cap {max_super}", **kw)
+
+
 def config_upwind(dims=(64, 64), kind: str = "box", keep: float = 0.25, seed: int = 0,
                   max_super: int = 128, leaf: int = 64) -> Workload:
     """Structurally non-symmetric grid stencil (one-sided upwind couplings,
