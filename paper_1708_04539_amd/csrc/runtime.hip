@@ -123,6 +123,7 @@ struct Tuning {
     std::vector<int> t35, t4;       // per level: steps 3+5, step 4 (+ the next level's gather)
     std::vector<char> no_small;     // per level: 1 = per-phase launches for its small supernodes
     int sweep = SWEEP_AUTO;         // SWEEP_LEVELS / SWEEP_PERSISTENT, or the handle's own mode
+    int no_fork = 0;                // 1: the whole prologue before the sweep, no side stream
 };
 
 constexpr int NPREC = 3;
@@ -431,6 +432,7 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, int sweep_mo
                 S->split = d;
                 break;
             }
+        if (tn && tn->no_fork) S->split = 0;
     }
     std::vector<std::vector<char>> part(hs.size());
     for (size_t mi = 0; mi < hs.size(); mi++) {
@@ -1664,7 +1666,19 @@ selinv_status selinv_tune(selinv_handle h, selinv_precision prec, int32_t reps, 
             t_best = t;
         }
     }
-    // 4. keep the size policy when the measured choices are no faster
+    // 4. the prologue of the lower levels beside the upper levels (side
+    //    stream) or entirely before the sweep
+    {
+        Tuning nf = best;
+        nf.no_fork = 1;
+        h->tune[prec] = nf;
+        if ((st = tune_measure(h, prec, s, reps, false, t, nullptr))) return st;
+        if (t < t_best) {
+            best = nf;
+            t_best = t;
+        }
+    }
+    // 5. keep the size policy when the measured choices are no faster
     if (t_best > t_policy) {
         Tuning pol;
         pol.set = true;
@@ -1681,25 +1695,27 @@ selinv_status selinv_tune(selinv_handle h, selinv_precision prec, int32_t reps, 
     return SELINV_OK;
 }
 
-// flat form: [1, nlevels, sweep, tri, norm, dt, then per level: t35, t4, no_small]
+// flat form: [2, nlevels, sweep, tri, norm, dt, no_fork, then per level: t35, t4, no_small]
+// (a table of the first layout, without no_fork, is still accepted)
 selinv_status selinv_get_tuning(selinv_handle h, selinv_precision prec, int32_t *out, int32_t cap,
                                 int32_t *count) {
     if (!h || !valid_prec(prec) || !count) return SELINV_E_INVALID_ARG;
     const Tuning &tn = h->tune[prec];
     const int L = h->P.nlevels;
-    *count = tn.set ? 6 + 3 * L : 0;
+    *count = tn.set ? 7 + 3 * L : 0;
     if (!tn.set || !out) return SELINV_OK;
     if (cap < *count) {
         h->err = "tuning buffer too small";
         return SELINV_E_INVALID_ARG;
     }
     int32_t *o = out;
-    *o++ = 1;
+    *o++ = 2;
     *o++ = L;
     *o++ = tn.sweep;
     *o++ = tn.tri;
     *o++ = tn.norm;
     *o++ = tn.dt;
+    *o++ = tn.no_fork;
     for (int d = 0; d < L; d++) {
         *o++ = tn.t35[d];
         *o++ = tn.t4[d];
@@ -1717,10 +1733,13 @@ selinv_status selinv_set_tuning(selinv_handle h, selinv_precision prec, const in
     }
     const int L = h->P.nlevels;
     auto tile_ok = [](int v) { return v == 0 || v == GEMM_TILE_32 || v == GEMM_TILE_64 || v == GEMM_TILE_128; };
-    bool ok = in && count == 6 + 3 * L && in[0] == 1 && in[1] == L && in[2] >= SWEEP_AUTO &&
-              in[2] <= SWEEP_PERSISTENT && tile_ok(in[3]) && tile_ok(in[4]) && tile_ok(in[5]);
+    const int ver = in && count > 0 ? in[0] : 0, hd = ver == 2 ? 7 : 6;
+    bool ok = in && (ver == 1 || ver == 2) && count == hd + 3 * L && in[1] == L && in[2] >= SWEEP_AUTO &&
+              in[2] <= SWEEP_PERSISTENT && tile_ok(in[3]) && tile_ok(in[4]) && tile_ok(in[5]) &&
+              (ver == 1 || in[6] == 0 || in[6] == 1);
     for (int d = 0; ok && d < L; d++)
-        ok = tile_ok(in[6 + 3 * d]) && tile_ok(in[7 + 3 * d]) && (in[8 + 3 * d] == 0 || in[8 + 3 * d] == 1);
+        ok = tile_ok(in[hd + 3 * d]) && tile_ok(in[hd + 1 + 3 * d]) &&
+             (in[hd + 2 + 3 * d] == 0 || in[hd + 2 + 3 * d] == 1);
     if (!ok) {
         h->err = "tuning table does not fit this handle (layout, level count, tile edges or sweep form)";
         return SELINV_E_INVALID_ARG;
@@ -1731,10 +1750,11 @@ selinv_status selinv_set_tuning(selinv_handle h, selinv_precision prec, const in
     tn.tri = in[3];
     tn.norm = in[4];
     tn.dt = in[5];
+    tn.no_fork = ver == 2 ? in[6] : 0;
     for (int d = 0; d < L; d++) {
-        tn.t35.push_back(in[6 + 3 * d]);
-        tn.t4.push_back(in[7 + 3 * d]);
-        tn.no_small.push_back((char)in[8 + 3 * d]);
+        tn.t35.push_back(in[hd + 3 * d]);
+        tn.t4.push_back(in[hd + 1 + 3 * d]);
+        tn.no_small.push_back((char)in[hd + 2 + 3 * d]);
     }
     h->tune[prec] = tn;
     drop_sweep(h, prec);

@@ -293,14 +293,18 @@ def test_tuning_table_set_get_and_validation(si):
     s = si.SelInv(w.n, w.colptr, w.rowind, w.perm, w.max_super, w.relax, w.pad_pct)
     L = s.info["nlevels"]
     assert s.get_tuning("fp64") == []
-    table = [1, L, 1, 64, 32, 0]
+    table = [2, L, 1, 64, 32, 0, 1]
     for d in range(L):
         table += [32 if d % 2 else 64, 128, d % 2]
     s.set_tuning(table, "mixed_fp32")
     assert s.get_tuning("mixed_fp32") == table
     assert s.get_tuning("fp64") == []
-    bad = [table[:-1], [2] + table[1:], table[:1] + [L + 1] + table[2:], table[:3] + [48] + table[4:],
-           table[:8] + [2] + table[9:], table[:2] + [3] + table[3:]]
+    # the first layout (no prologue flag) is still accepted, side stream kept
+    v1 = [1] + table[1:6] + table[7:]
+    s.set_tuning(v1, "mixed_bf16x3")
+    assert s.get_tuning("mixed_bf16x3") == [2] + table[1:6] + [0] + table[7:]
+    bad = [table[:-1], [3] + table[1:], table[:1] + [L + 1] + table[2:], table[:3] + [48] + table[4:],
+           table[:9] + [2] + table[10:], table[:2] + [3] + table[3:], table[:6] + [2] + table[7:]]
     for b in bad:
         with pytest.raises(si.SelinvError) as e:
             s.set_tuning(b, "mixed_fp32")
@@ -311,8 +315,8 @@ def test_tuning_table_set_get_and_validation(si):
     # both sweep forms for an exact analysis too
     x = si.SelInv(w.n, w.colptr, w.rowind, w.perm, w.max_super, w.relax, w.pad_pct, symbolic="exact")
     Lx = x.info["nlevels"]
-    x.set_tuning([1, Lx, 2, 0, 0, 0] + [0, 0, 0] * Lx)
-    x.set_tuning([1, Lx, 1, 0, 0, 0] + [0, 0, 0] * Lx)
+    x.set_tuning([2, Lx, 2, 0, 0, 0, 0] + [0, 0, 0] * Lx)
+    x.set_tuning([2, Lx, 1, 0, 0, 0, 1] + [0, 0, 0] * Lx)
 
 
 def test_autotune_describe():
@@ -321,6 +325,8 @@ def test_autotune_describe():
     d = describe([1, 2, 1, 64, 32, 32, 32, 64, 0, 128, 128, 1])
     assert d["steps35_tiles"] == [32, 128] and d["step4_tiles"] == [64, 128]
     assert d["small_per_phase_levels"] == [1] and d["sweep"] == "levels"
+    d = describe([2, 2, 1, 64, 32, 32, 1, 32, 64, 0, 128, 128, 1])
+    assert d["steps35_tiles"] == [32, 128] and not d["prologue_side_stream"]
 
 
 # --------------------------------------------------------------------------

@@ -550,7 +550,7 @@ def test_tune_c1_keeps_parity(si, c1_pair, prec):
     ms_pol, ms_tun = s.tune(prec, reps=3)
     table = s.get_tuning(prec)
     say("c1 tune", prec, "policy ms", ms_pol, "tuned ms", ms_tun, "table", table)
-    assert ms_tun <= ms_pol and len(table) == 6 + 3 * s.info["nlevels"]
+    assert ms_tun <= ms_pol and len(table) == 7 + 3 * s.info["nlevels"]
     s.run(prec)
     compare_superset(s, o, TOL[prec])
     s.run(prec, graph=True)
@@ -568,7 +568,7 @@ def test_forced_tables_keep_parity(si, prec):
     L = s.info["nlevels"]
     for edge in (32, 64, 128):
         for per_phase in (0, 1):
-            s.set_tuning([1, L, 1, edge, edge, edge] + [edge, edge, per_phase] * L, prec)
+            s.set_tuning([2, L, 1, edge, edge, edge, per_phase] + [edge, edge, per_phase] * L, prec)
             s.run(prec)
             compare_superset(s, o, TOL[prec])
 
