@@ -170,6 +170,26 @@ selinv_status selinv_analyze(int64_t n, const int64_t *colptr, const int32_t *ro
  * An exact zero or non-finite pivot gives SELINV_E_ZERO_PIVOT. */
 selinv_status selinv_factor(selinv_handle h, const double *values);
 
+/* The same factorization on the device, asynchronous on `stream` until its
+ * end, where the call waits for the stream to read the pivot check.
+ * values: DEVICE memory of the current device, aligned with rowind[] of
+ * selinv_analyze (nnz doubles; 2 nnz interleaved re, im for a complex
+ * handle), owned by the caller and only read; a host pointer gives
+ * SELINV_E_INVALID_ARG, a shorter buffer is undefined behaviour.  The
+ * entries are scattered into the block storage, then the levels of the
+ * dependency graph run from the deepest up: per level, 64-column steps of the
+ * diagonal blocks (tile LU in LDS, right solves of the block and panel rows,
+ * trailing GEMM updates), then W_K = -L(R_L,K) U(K,R_U) for every supernode
+ * of the level and its atomic scatter-add into the blocks of the ancestors
+ * (right-looking supernodal LU; supernodes of one level are independent).
+ * FP64 throughout; rounding differs from selinv_factor only in summation
+ * order.  The first call builds and uploads its work lists (host range checks
+ * included).  A zero or non-finite pivot gives SELINV_E_ZERO_PIVOT (the
+ * smallest such permuted column of the level where it occurs) and leaves the
+ * handle unfactored.  Earlier work of the handle on other streams must be
+ * complete before the call. */
+selinv_status selinv_factor_device(selinv_handle h, const double *values, void *stream);
+
 /* Steps 2-5 of Algorithm 1 on the device, asynchronous on `stream`:
  * diagonal-block inversion and normalisation of every supernode, then one
  * level of the supernodal tree after another (root first): gather of

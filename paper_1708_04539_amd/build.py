@@ -19,7 +19,7 @@ ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIPCC = os.path.join(ROCM, "bin", "hipcc")
 
 HOST_SOURCES = ["analyze.cpp", "factor.cpp"]
-HIP_SOURCES = ["kernels.hip", "gemm.hip", "persist.hip", "runtime.hip"]
+HIP_SOURCES = ["kernels.hip", "gemm.hip", "persist.hip", "lu_device.hip", "runtime.hip"]
 
 HOST_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-fopenmp", "-march=x86-64-v3", "-Wall", "-Wextra",
               "-Wno-unused-parameter"]

@@ -113,6 +113,21 @@ struct ReduceItem {
     int32_t push_sn, push_mat, g_f32, pad;
 };
 
+// device LU: one 64x64 diagonal tile (rows / columns j0 ..) of the s x s
+// block D of the supernode whose first column is f; and the right solve
+// X T = B of up to 64 rows of X (X(i, t) = X[i rs + t cs], T(u, t) =
+// T[u tu + t tt], b x b upper triangular, unit diagonal when `unit`)
+struct LuTile {
+    double *D;
+    int32_t s, j0, f, pad;
+};
+struct TrsmItem {
+    double *X;
+    const double *T;
+    int64_t rs, cs, tu, tt;
+    int32_t rows, b, unit, pad;
+};
+
 // extraction of the selected entries
 struct ExtractArgs {
     const int64_t *loc;  // kind << 60 | offset per entry of A

@@ -44,6 +44,18 @@ hipError_t launch_extract(int f64, const ExtractArgs &a, hipStream_t st);
 hipError_t launch_splitk_reduce(const ReduceItem *items, int count, int64_t max_mn, const MatDev *mats,
                                 hipStream_t st);
 
+// device LU (lu_device.hip): entries of A into the block storage (emb:
+// complex source map or null); LU of 64x64 diagonal tiles (a zero or
+// non-finite pivot lowers *bad to its permuted column); right solves of row
+// blocks; the Schur complement updates W_K (tiles: K, a0, b0, cl, cu, g_off
+// into W) added to the ancestors' blocks of `mat`
+hipError_t launch_scatter_values(const int64_t *loc, const double *vals, const int64_t *emb, int64_t nnz,
+                                 double *diag, double *lpan, double *upan, hipStream_t st);
+hipError_t launch_lu_tiles(const LuTile *items, int count, int32_t *bad, hipStream_t st);
+hipError_t launch_trsm_tiles(const TrsmItem *items, int count, hipStream_t st);
+hipError_t launch_scatter_update(const MatDev *mat, const GatherTile *tiles, int count, const double *W,
+                                 double *diag, double *lpan, double *upan, hipStream_t st);
+
 // persistent sweep (64x64 product tiles): resets the ncnt counters, the queue
 // head and the error flag, then runs the task queue on `grid` workgroups
 hipError_t launch_persist(int mode, const PersistArgs &a, int64_t ncnt, int grid, hipStream_t st);

@@ -128,6 +128,34 @@ struct Tuning {
 
 constexpr int NPREC = 3;
 
+// Work lists of the device LU (selinv_factor_device), built once per handle:
+// per level (deepest first) and per 64-column step of the diagonal blocks one
+// launch of tile LUs, one of right solves and one of trailing updates, then
+// the Schur complement products W_K and their scatter into the ancestors.
+struct LuPlan {
+    enum : int { L_TILES = 0, L_TRSM = 1, L_UPDATE = 2, L_SCHUR = 3, L_SCATTER = 4 };
+    struct Launch {
+        int kind;
+        int64_t first;
+        int count;
+    };
+    std::vector<Launch> launches;
+    LuTile *d_lu = nullptr;
+    TrsmItem *d_trsm = nullptr;
+    GemmProb *d_probs = nullptr;
+    GemmTile *d_tiles = nullptr;
+    GatherTile *d_sc = nullptr;
+    MatDev *d_mat = nullptr;
+    double *d_W = nullptr;  // W_K of one level
+    int32_t *d_bad = nullptr;
+    int64_t *d_emb = nullptr;  // complex handles: source of every entry of the real form
+    ~LuPlan() {
+        for (void *q : {(void *)d_lu, (void *)d_trsm, (void *)d_probs, (void *)d_tiles, (void *)d_sc, (void *)d_mat,
+                        (void *)d_W, (void *)d_bad, (void *)d_emb})
+            (void)hipFree(q);
+    }
+};
+
 inline int elem_bytes(int prec) { return prec == SELINV_FP64 ? 8 : 4; }
 inline int mode_of(int prec) {
     return prec == SELINV_FP64 ? CMP_F64 : prec == SELINV_MIXED_FP32 ? CMP_F32 : CMP_BF16X3;
@@ -172,6 +200,7 @@ struct selinv_handle_s {
     bool profiling = false;
     int sweep_mode = SWEEP_AUTO;
     Tuning tune[NPREC];
+    std::unique_ptr<LuPlan> lu;
     std::vector<hipEvent_t> events;
     std::vector<double> times;
 };
@@ -1324,6 +1353,8 @@ selinv_status selinv_analyze(int64_t n, const int64_t *colptr, const int32_t *ro
     return SELINV_OK;
 }
 
+static selinv_status ensure_device(selinv_handle h);
+
 selinv_status selinv_factor(selinv_handle h, const double *values) {
     if (!h || !values) return SELINV_E_INVALID_ARG;
     if (h->state < 0) return SELINV_E_STATE;
@@ -1353,6 +1384,17 @@ selinv_status selinv_factor(selinv_handle h, const double *values) {
         return SELINV_E_NOMEM;
     }
     if (st) return st;
+    if ((st = ensure_device(h))) return st;
+    const Plan &P = h->P;
+    if (P.tot_d) HIPCHK(h->err, hipMemcpy(h->d_diag, F.d.data(), P.tot_d * 8, hipMemcpyHostToDevice), "H2D diag");
+    if (P.tot_l) HIPCHK(h->err, hipMemcpy(h->d_lpan, F.l.data(), P.tot_l * 8, hipMemcpyHostToDevice), "H2D lpan");
+    if (P.tot_u) HIPCHK(h->err, hipMemcpy(h->d_upan, F.u.data(), P.tot_u * 8, hipMemcpyHostToDevice), "H2D upan");
+    h->state = 1;
+    return SELINV_OK;
+}
+
+// Factor storage and plan metadata on the current device (first factor call).
+static selinv_status ensure_device(selinv_handle h) {
     int dev = 0;
     HIPCHK(h->err, hipGetDevice(&dev), "hipGetDevice");
     if (h->device >= 0 && h->device != dev) {
@@ -1386,9 +1428,256 @@ selinv_status selinv_factor(selinv_handle h, const double *values) {
         HIPCHK(h->err, upload(&h->d_gcL, h->gcL), "upload gather codes");
         HIPCHK(h->err, upload(&h->d_gcU, h->gcU), "upload gather codes");
     }
-    if (P.tot_d) HIPCHK(h->err, hipMemcpy(h->d_diag, F.d.data(), P.tot_d * 8, hipMemcpyHostToDevice), "H2D diag");
-    if (P.tot_l) HIPCHK(h->err, hipMemcpy(h->d_lpan, F.l.data(), P.tot_l * 8, hipMemcpyHostToDevice), "H2D lpan");
-    if (P.tot_u) HIPCHK(h->err, hipMemcpy(h->d_upan, F.u.data(), P.tot_u * 8, hipMemcpyHostToDevice), "H2D upan");
+    return SELINV_OK;
+}
+
+// Work lists of the device LU.  Every operand range of a tile LU, right
+// solve or product is checked on the host against its supernode's segment of
+// the factor storage, and every destination of a Schur complement entry
+// against the segment and the level of the supernode that holds it, before
+// anything is uploaded.
+static selinv_status build_lu(selinv_handle h) {
+    const Plan &P = h->P;
+    auto L = std::make_unique<LuPlan>();
+    std::vector<LuTile> lus;
+    std::vector<TrsmItem> trs;
+    std::vector<GemmProb> probs;
+    std::vector<GemmTile> tiles;
+    std::vector<GatherTile> scs;
+    bool ok = true;
+    // elements [off, off + last] inside [seg, seg + len)
+    auto inside = [&](int64_t off, int64_t last, int64_t seg, int64_t len) {
+        if (off < seg || last < 0 || off + last >= seg + len) ok = false;
+    };
+    // W_K of one level, packed: the largest level decides the buffer
+    int64_t w_max = 0;
+    for (int32_t lev = 0; lev < P.nlevels; lev++) {
+        int64_t w = 0;
+        for (int32_t K : P.levels[lev]) w += (int64_t)h->sn[K].cl * h->sn[K].cu;
+        w_max = std::max(w_max, w);
+    }
+    HIPCHK(h->err, alloc_bytes((void **)&L->d_W, w_max * 8), "alloc Schur complement buffer");
+    double *D0 = h->d_diag, *L0 = h->d_lpan, *U0 = h->d_upan, *W0 = L->d_W;
+    // C = -op(A) op(B) + beta C
+    auto gemm = [&](const double *A, int64_t lda, int opA, const double *B, int64_t ldb, int opB, double *C,
+                    int64_t ldc, int M, int N, int K, double beta) {
+        GemmProb g{};
+        g.A = A;
+        g.B = B;
+        g.C = C;
+        g.Cin = beta != 0.0 ? C : nullptr;
+        g.M = M;
+        g.N = N;
+        g.K = K;
+        g.lda = (int32_t)lda;
+        g.ldb = (int32_t)ldb;
+        g.ldc = g.ldcin = (int32_t)ldc;
+        g.opA = opA;
+        g.opB = opB;
+        g.push_sn = g.push_mat = -1;
+        g.alpha = -1.0;
+        g.beta = beta;
+        add_tiles(tiles, (int)probs.size(), M, N, GEMM_TILE_64);
+        probs.push_back(g);
+    };
+    auto mark = [&](int kind, size_t first, size_t end) {
+        if (end > first) L->launches.push_back({kind, (int64_t)first, (int)(end - first)});
+    };
+    for (int32_t lev = P.nlevels - 1; lev >= 0; lev--) {
+        const std::vector<int32_t> &Ks = P.levels[lev];
+        int smax = 0;
+        for (int32_t K : Ks) smax = std::max(smax, h->sn[K].s);
+        for (int j0 = 0; j0 < smax; j0 += 64) {
+            const size_t l0 = lus.size(), t0 = trs.size(), g0 = tiles.size();
+            for (int32_t K : Ks) {
+                const SnRec &r = h->sn[K];
+                const int s = r.s, cl = r.cl, cu = r.cu;
+                if (s <= j0) continue;
+                const int b = std::min(64, s - j0), rest = s - j0 - b;
+                const int64_t ss = (int64_t)s * s, ld = s;
+                double *D = D0 + r.off_d;
+                const int64_t tile = j0 + j0 * ld;
+                inside(r.off_d + tile, (b - 1) + (b - 1) * ld, r.off_d, ss);
+                lus.push_back(LuTile{D, s, j0, r.f, 0});
+                const double *T = D + tile;
+                // U of the tile: T(u, t) = D(j0+u, j0+t); its unit L transposed: D(j0+t, j0+u)
+                auto trsm = [&](double *X, int64_t rs, int64_t cs, int rows, bool lower) {
+                    trs.push_back(TrsmItem{X, T, rs, cs, lower ? ld : 1, lower ? 1 : ld, rows, b, lower ? 1 : 0, 0});
+                };
+                for (int i0 = 0; i0 < rest; i0 += 64) {
+                    const int rows = std::min(64, rest - i0);
+                    int64_t o = (j0 + b + i0) + j0 * ld;  // rows of L below the tile
+                    inside(r.off_d + o, (rows - 1) + (b - 1) * ld, r.off_d, ss);
+                    trsm(D + o, 1, ld, rows, false);
+                    o = j0 + (j0 + b + i0) * ld;  // columns of U right of the tile
+                    inside(r.off_d + o, (rows - 1) * ld + (b - 1), r.off_d, ss);
+                    trsm(D + o, ld, 1, rows, true);
+                }
+                for (int i0 = 0; i0 < cl; i0 += 64) {
+                    const int rows = std::min(64, cl - i0);
+                    const int64_t o = r.off_l + i0 + (int64_t)j0 * cl;
+                    inside(o, (rows - 1) + (int64_t)(b - 1) * cl, r.off_l, (int64_t)cl * s);
+                    trsm(L0 + o, 1, cl, rows, false);
+                }
+                for (int i0 = 0; i0 < cu; i0 += 64) {
+                    const int rows = std::min(64, cu - i0);
+                    const int64_t o = r.off_u + i0 + (int64_t)j0 * cu;
+                    inside(o, (rows - 1) + (int64_t)(b - 1) * cu, r.off_u, (int64_t)cu * s);
+                    trsm(U0 + o, 1, cu, rows, true);
+                }
+                if (rest > 0) {
+                    const int64_t l21 = (j0 + b) + j0 * ld, u12 = j0 + (j0 + b) * ld, c22 = (j0 + b) * (1 + ld);
+                    inside(r.off_d + l21, (rest - 1) + (b - 1) * ld, r.off_d, ss);
+                    inside(r.off_d + u12, (b - 1) + (rest - 1) * ld, r.off_d, ss);
+                    inside(r.off_d + c22, (rest - 1) + (rest - 1) * ld, r.off_d, ss);
+                    gemm(D + l21, ld, 0, D + u12, ld, 0, D + c22, ld, rest, rest, b, 1.0);
+                    if (cl > 0) {
+                        const int64_t a = r.off_l + (int64_t)j0 * cl, c = r.off_l + (int64_t)(j0 + b) * cl;
+                        inside(a, (cl - 1) + (int64_t)(b - 1) * cl, r.off_l, (int64_t)cl * s);
+                        inside(c, (cl - 1) + (int64_t)(rest - 1) * cl, r.off_l, (int64_t)cl * s);
+                        gemm(L0 + a, cl, 0, D + u12, ld, 0, L0 + c, cl, cl, rest, b, 1.0);
+                    }
+                    if (cu > 0) {  // U(K, R_U)^T(:, later) -= U(K, R_U)^T(:, tile) L21^T
+                        const int64_t a = r.off_u + (int64_t)j0 * cu, c = r.off_u + (int64_t)(j0 + b) * cu;
+                        inside(a, (cu - 1) + (int64_t)(b - 1) * cu, r.off_u, (int64_t)cu * s);
+                        inside(c, (cu - 1) + (int64_t)(rest - 1) * cu, r.off_u, (int64_t)cu * s);
+                        gemm(U0 + a, cu, 0, D + l21, ld, 1, U0 + c, cu, cu, rest, b, 1.0);
+                    }
+                }
+            }
+            mark(LuPlan::L_TILES, l0, lus.size());
+            mark(LuPlan::L_TRSM, t0, trs.size());
+            mark(LuPlan::L_UPDATE, g0, tiles.size());
+        }
+        // W_K = -L(R_L, K) U(K, R_U) and its scatter into the ancestors
+        const size_t g0 = tiles.size(), c0 = scs.size();
+        int64_t w = 0;
+        for (int32_t K : Ks) {
+            const SnRec &r = h->sn[K];
+            const int s = r.s, cl = r.cl, cu = r.cu;
+            if (cl == 0 || cu == 0) continue;
+            inside(w, (int64_t)cl * cu - 1, 0, w_max);
+            gemm(L0 + r.off_l, cl, 0, U0 + r.off_u, cu, 1, W0 + w, cl, cl, cu, s, 0.0);
+            for (int a0 = 0; a0 < cl; a0 += 64)
+                for (int b0 = 0; b0 < cu; b0 += 64) scs.push_back(GatherTile{0, K, a0, b0, -1, cl, cu, 0, w, -1, 0, 0});
+            // destinations of every entry of W_K
+            const int32_t *RL = P.rl.data() + P.rl_ptr[K], *RU = P.ru.data() + P.ru_ptr[K];
+            for (int b2 = 0; b2 < cu && ok; b2++) {
+                const int32_t c = RU[b2], J = P.supof[c];
+                for (int a = 0; a < cl; a++) {
+                    const int32_t rr = RL[a], I = P.supof[rr];
+                    const int32_t Q = std::min(I, J);
+                    if (P.level[Q] >= lev) ok = false;
+                    if (I == J) {
+                        if (c < P.xsup[J] || c >= P.xsup[J + 1] || rr < P.xsup[J] || rr >= P.xsup[J + 1]) ok = false;
+                    } else if (I > J) {
+                        const int64_t m = P.l_coloff[P.ru_ptr[K] + b2] + a;
+                        if (m < 0 || m >= (int64_t)P.mapL.size() || P.mapL[m] < 0 || P.mapL[m] >= P.cl(J)) ok = false;
+                    } else {
+                        const int64_t m = P.u_rowoff[P.rl_ptr[K] + a] + b2;
+                        if (m < 0 || m >= (int64_t)P.mapU.size() || P.mapU[m] < 0 || P.mapU[m] >= P.cu(I)) ok = false;
+                    }
+                }
+            }
+            w += (int64_t)cl * cu;
+        }
+        mark(LuPlan::L_SCHUR, g0, tiles.size());
+        mark(LuPlan::L_SCATTER, c0, scs.size());
+    }
+    if (!ok) {
+        h->err = "device LU: work list outside the factor storage (inconsistent analysis)";
+        return SELINV_E_STATE;
+    }
+    HIPCHK(h->err, upload(&L->d_lu, lus), "upload LU tiles");
+    HIPCHK(h->err, upload(&L->d_trsm, trs), "upload solves");
+    HIPCHK(h->err, upload(&L->d_probs, probs), "upload LU products");
+    HIPCHK(h->err, upload(&L->d_tiles, tiles), "upload LU product tiles");
+    HIPCHK(h->err, upload(&L->d_sc, scs), "upload scatter tiles");
+    MatDev m{};
+    m.sn = h->d_sn;
+    m.supof = h->d_supof;
+    m.rl = h->d_rl;
+    m.ru = h->d_ru;
+    m.l_coloff = h->d_lcol;
+    m.u_rowoff = h->d_urow;
+    m.mapL = h->d_mapL;
+    m.mapU = h->d_mapU;
+    HIPCHK(h->err, upload(&L->d_mat, std::vector<MatDev>{m}), "upload LU matrix record");
+    HIPCHK(h->err, alloc_bytes((void **)&L->d_bad, sizeof(int32_t)), "alloc pivot flag");
+    if (h->cplx) {
+        // entry e of the real form: +-(Re or Im) of complex entry k, as in selinv_factor
+        std::vector<int64_t> emb(P.nnz_a, 0);
+        for (int64_t j = 0; j < h->n_c; j++)
+            for (int64_t k = h->colptr_c[j]; k < h->colptr_c[j + 1]; k++) {
+                const int64_t t = k - h->colptr_c[j];
+                const int64_t e0 = P.a_colptr[2 * j] + 2 * t, e1 = P.a_colptr[2 * j + 1] + 2 * t;
+                emb[e0] = (2 * k) << 1;
+                emb[e0 + 1] = (2 * k + 1) << 1;
+                emb[e1] = ((2 * k + 1) << 1) | 1;
+                emb[e1 + 1] = (2 * k) << 1;
+            }
+        HIPCHK(h->err, upload(&L->d_emb, emb), "upload complex entry map");
+    }
+    h->lu = std::move(L);
+    return SELINV_OK;
+}
+
+selinv_status selinv_factor_device(selinv_handle h, const double *values, void *stream) {
+    if (!h || !values) return SELINV_E_INVALID_ARG;
+    if (h->state < 0) return SELINV_E_STATE;
+    selinv_status st;
+    if ((st = ensure_device(h))) return st;
+    {
+        hipPointerAttribute_t attr;
+        const hipError_t e = hipPointerGetAttributes(&attr, values);
+        if (e != hipSuccess || (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged) ||
+            attr.device != h->device) {
+            (void)hipGetLastError();
+            h->err = "factor_device: values is not device memory of the handle's device";
+            return SELINV_E_INVALID_ARG;
+        }
+    }
+    try {
+        if (!h->lu && (st = build_lu(h))) return st;
+    } catch (const std::bad_alloc &) {
+        h->err = "host allocation failed in factor_device";
+        return SELINV_E_NOMEM;
+    }
+    const Plan &P = h->P;
+    LuPlan &L = *h->lu;
+    hipStream_t s = (hipStream_t)stream;
+    h->state = 0;  // the factor storage is rewritten from here on
+    HIPCHK(h->err, hipMemsetAsync(h->d_diag, 0, P.tot_d * 8, s), "clear diag");
+    HIPCHK(h->err, hipMemsetAsync(h->d_lpan, 0, P.tot_l * 8, s), "clear lpan");
+    HIPCHK(h->err, hipMemsetAsync(h->d_upan, 0, P.tot_u * 8, s), "clear upan");
+    HIPCHK(h->err, hipMemsetAsync(L.d_bad, 0x7f, sizeof(int32_t), s), "clear pivot flag");
+    HIPCHK(h->err, launch_scatter_values(h->d_aloc, values, L.d_emb, P.nnz_a, h->d_diag, h->d_lpan, h->d_upan, s),
+           "scatter values");
+    for (const LuPlan::Launch &l : L.launches) {
+        hipError_t e = hipSuccess;
+        switch (l.kind) {
+            case LuPlan::L_TILES: e = launch_lu_tiles(L.d_lu + l.first, l.count, L.d_bad, s); break;
+            case LuPlan::L_TRSM: e = launch_trsm_tiles(L.d_trsm + l.first, l.count, s); break;
+            case LuPlan::L_UPDATE:
+                e = launch_gemm(GEMM_STEP4, CMP_F64, GEMM_TILE_64, L.d_probs, L.d_tiles + l.first, l.count, s);
+                break;
+            case LuPlan::L_SCHUR:
+                e = launch_gemm(GEMM_PRO_F64, CMP_F64, GEMM_TILE_64, L.d_probs, L.d_tiles + l.first, l.count, s);
+                break;
+            default:
+                e = launch_scatter_update(L.d_mat, L.d_sc + l.first, l.count, L.d_W, h->d_diag, h->d_lpan,
+                                          h->d_upan, s);
+        }
+        HIPCHK(h->err, e, "device LU launch");
+    }
+    int32_t bad = 0;
+    HIPCHK(h->err, hipMemcpyAsync(&bad, L.d_bad, sizeof(bad), hipMemcpyDeviceToHost, s), "pivot flag");
+    HIPCHK(h->err, hipStreamSynchronize(s), "device LU");
+    if (bad != 0x7f7f7f7f) {
+        h->err = "zero or non-finite pivot at permuted column " + std::to_string(bad) + " (original column " +
+                 std::to_string(bad >= 0 && bad < (int32_t)P.p.size() ? P.p[bad] : -1) + ")";
+        return SELINV_E_ZERO_PIVOT;
+    }
     h->state = 1;
     return SELINV_OK;
 }
@@ -2031,6 +2320,7 @@ void selinv_destroy(selinv_handle h) {
         (void)hipFree(b.Uh);
         (void)hipFree(b.G);
     }
+    h->lu.reset();
     for (void *q : {(void *)h->d_diag, (void *)h->d_lpan, (void *)h->d_upan, (void *)h->d_Linv, (void *)h->d_Uinv,
                     (void *)h->d_tl, (void *)h->d_tu,
                     (void *)h->d_sn, (void *)h->d_supof, (void *)h->d_rl, (void *)h->d_ru, (void *)h->d_mapL,

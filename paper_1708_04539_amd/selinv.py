@@ -25,7 +25,7 @@ PRECISIONS = {"fp64": FP64, "mixed_fp32": MIXED_FP32, "mixed_bf16x3": MIXED_BF16
 STATUS = {0: "OK", 1: "INVALID_ARG", 2: "BAD_PATTERN", 3: "BAD_PERM", 4: "ZERO_PIVOT",
           5: "NOT_SELECTED", 6: "STATE", 7: "NOMEM", 8: "DEVICE"}
 
-EXPORTED = ["selinv_analyze", "selinv_factor", "selinv_run", "selinv_run_graph", "selinv_batch_create",
+EXPORTED = ["selinv_analyze", "selinv_factor", "selinv_factor_device", "selinv_run", "selinv_run_graph", "selinv_batch_create",
             "selinv_batch_run", "selinv_batch_destroy", "selinv_get", "selinv_get_selected",
             "selinv_get_selected_device", "selinv_export", "selinv_structure", "selinv_query",
             "selinv_set_profiling", "selinv_timings", "selinv_level_stats", "selinv_last_error",
@@ -71,6 +71,7 @@ def _load():
     sig = {
         "selinv_analyze": ([i64, P(i64), P(i32), P(i32), P(Opts), P(vp)], C.c_int),
         "selinv_factor": ([vp, P(dbl)], C.c_int),
+        "selinv_factor_device": ([vp, vp, vp], C.c_int),
         "selinv_run": ([vp, C.c_int, vp], C.c_int),
         "selinv_run_graph": ([vp, C.c_int, vp], C.c_int),
         "selinv_batch_create": ([P(vp), i32, P(vp)], C.c_int),
@@ -160,6 +161,17 @@ class SelInv:
         else:
             v = np.ascontiguousarray(values, dtype=np.float64)
         self._check(_lib.selinv_factor(self._h, _p(v, C.c_double)), "factor")
+        return self
+
+    def factor_device(self, values: "torch.Tensor", stream=None):
+        """LU on the GPU from values already in device memory (float64, or
+        complex128 for a complex handle), aligned with rowind."""
+        want = torch.complex128 if self.is_complex else torch.float64
+        if not (values.dtype == want and values.is_cuda and values.is_contiguous()
+                and values.numel() == self.nnz):
+            raise ValueError(f"factor_device wants a contiguous {want} CUDA tensor of {self.nnz} entries")
+        self._check(_lib.selinv_factor_device(self._h, C.c_void_p(values.data_ptr()), _stream_ptr(stream)),
+                    "factor_device")
         return self
 
     def run(self, precision="fp64", stream=None, graph=False):
