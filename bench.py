@@ -44,6 +44,7 @@ def parse():
     ap.add_argument("--no-tune", action="store_true", help="size policy instead of the autotuner's choices")
     ap.add_argument("--tune-reps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-device-lu", action="store_true", help="skip timing the LU on the device (setup)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="bound on the oracle's CPU time")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (for scaling HBM counters) and exit")
@@ -343,6 +344,32 @@ def main():
     if mixed:
         res["mixed"] = mixed
         res["mixed_speedup_vs_main"] = ms / mixed["ms_per_matrix"]
+
+    # LU factorisation on the device (setup, not part of a step): first call
+    # (work lists built and uploaded) and the mean of repeats, then one run on
+    # its factors against the run on the host factors
+    if not args.no_device_lu:
+        dvals = torch.from_numpy(np.ascontiguousarray(w.values)).to("cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.factor_device(dvals, stream)
+        t_first = time.perf_counter() - t0
+        reps = 5
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            s.factor_device(dvals, stream)
+        t_dev = (time.perf_counter() - t0) / reps
+        with torch.cuda.stream(stream):
+            s.run(prec, stream)
+            s.get_selected_device(out, stream)
+        stream.synchronize()
+        sel_dev = out.cpu().numpy()
+        res["device_lu"] = {"ms": 1e3 * t_dev, "first_call_s": t_first,
+                            "host_lu_and_h2d_ms": 1e3 * t_fa,
+                            "max_rel_diff_vs_host_lu": float(np.abs(sel_dev - sel_main).max()
+                                                             / np.abs(sel_main).max()),
+                            "note": "wall clock of selinv_factor_device (values resident in HBM; ends with "
+                                    "a stream synchronisation), mean of %d calls" % reps}
 
     if not args.no_cpu_baseline and args.config in ("c0", "c1", "u1"):
         o, sel_ref, t_cpu, reps, threads = cpu_baseline(w, args.cpu_seconds)

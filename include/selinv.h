@@ -178,16 +178,17 @@ selinv_status selinv_factor(selinv_handle h, const double *values);
  * SELINV_E_INVALID_ARG, a shorter buffer is undefined behaviour.  The
  * entries are scattered into the block storage, then the levels of the
  * dependency graph run from the deepest up: per level, 64-column steps of the
- * diagonal blocks (tile LU in LDS, right solves of the block and panel rows,
- * trailing GEMM updates), then W_K = -L(R_L,K) U(K,R_U) for every supernode
- * of the level and its atomic scatter-add into the blocks of the ancestors
- * (right-looking supernodal LU; supernodes of one level are independent).
- * FP64 throughout; rounding differs from selinv_factor only in summation
- * order.  The first call builds and uploads its work lists (host range checks
- * included).  A zero or non-finite pivot gives SELINV_E_ZERO_PIVOT (the
- * smallest such permuted column of the level where it occurs) and leaves the
- * handle unfactored.  Earlier work of the handle on other streams must be
- * complete before the call. */
+ * diagonal blocks (LU of the 64x64 tile in one wave, the inverses of its
+ * triangular factors, the solves of the block and panel rows as products
+ * with them, trailing GEMM updates), then W_K = -L(R_L,K) U(K,R_U) for every
+ * supernode of the level and its atomic scatter-add into the blocks of the
+ * ancestors (right-looking supernodal LU; supernodes of one level are
+ * independent).  FP64 throughout; rounding differs from selinv_factor (the
+ * solves multiply by tile inverses, sums run in another order).  The first
+ * call builds and uploads its work lists (host range checks included).  A
+ * zero or non-finite pivot gives SELINV_E_ZERO_PIVOT (the smallest permuted
+ * column with such a pivot) and leaves the handle unfactored.  Earlier work
+ * of the handle on other streams must be complete before the call. */
 selinv_status selinv_factor_device(selinv_handle h, const double *values, void *stream);
 
 /* Steps 2-5 of Algorithm 1 on the device, asynchronous on `stream`:

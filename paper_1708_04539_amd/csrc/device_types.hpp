@@ -114,18 +114,10 @@ struct ReduceItem {
 };
 
 // device LU: one 64x64 diagonal tile (rows / columns j0 ..) of the s x s
-// block D of the supernode whose first column is f; and the right solve
-// X T = B of up to 64 rows of X (X(i, t) = X[i rs + t cs], T(u, t) =
-// T[u tu + t tt], b x b upper triangular, unit diagonal when `unit`)
+// block D of the supernode whose first column is f
 struct LuTile {
     double *D;
     int32_t s, j0, f, pad;
-};
-struct TrsmItem {
-    double *X;
-    const double *T;
-    int64_t rs, cs, tu, tt;
-    int32_t rows, b, unit, pad;
 };
 
 // extraction of the selected entries

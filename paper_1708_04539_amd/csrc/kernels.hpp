@@ -46,13 +46,12 @@ hipError_t launch_splitk_reduce(const ReduceItem *items, int count, int64_t max_
 
 // device LU (lu_device.hip): entries of A into the block storage (emb:
 // complex source map or null); LU of 64x64 diagonal tiles (a zero or
-// non-finite pivot lowers *bad to its permuted column); right solves of row
-// blocks; the Schur complement updates W_K (tiles: K, a0, b0, cl, cu, g_off
-// into W) added to the ancestors' blocks of `mat`
+// non-finite pivot lowers *bad to its permuted column); the Schur complement
+// updates W_K (tiles: K, a0, b0, cl, cu, g_off into W) added to the
+// ancestors' blocks of `mat`
 hipError_t launch_scatter_values(const int64_t *loc, const double *vals, const int64_t *emb, int64_t nnz,
                                  double *diag, double *lpan, double *upan, hipStream_t st);
 hipError_t launch_lu_tiles(const LuTile *items, int count, int32_t *bad, hipStream_t st);
-hipError_t launch_trsm_tiles(const TrsmItem *items, int count, hipStream_t st);
 hipError_t launch_scatter_update(const MatDev *mat, const GatherTile *tiles, int count, const double *W,
                                  double *diag, double *lpan, double *upan, hipStream_t st);
 

@@ -130,10 +130,11 @@ constexpr int NPREC = 3;
 
 // Work lists of the device LU (selinv_factor_device), built once per handle:
 // per level (deepest first) and per 64-column step of the diagonal blocks one
-// launch of tile LUs, one of right solves and one of trailing updates, then
-// the Schur complement products W_K and their scatter into the ancestors.
+// launch each of tile LUs, tile inverses, solves (products with the
+// inverses) and trailing updates, then the Schur complement products W_K and
+// their scatter into the ancestors.
 struct LuPlan {
-    enum : int { L_TILES = 0, L_TRSM = 1, L_UPDATE = 2, L_SCHUR = 3, L_SCATTER = 4 };
+    enum : int { L_TILES = 0, L_TRI = 1, L_SOLVE = 2, L_UPDATE = 3, L_SCHUR = 4, L_SCATTER = 5 };
     struct Launch {
         int kind;
         int64_t first;
@@ -141,7 +142,7 @@ struct LuPlan {
     };
     std::vector<Launch> launches;
     LuTile *d_lu = nullptr;
-    TrsmItem *d_trsm = nullptr;
+    TriItem *d_tri = nullptr;
     GemmProb *d_probs = nullptr;
     GemmTile *d_tiles = nullptr;
     GatherTile *d_sc = nullptr;
@@ -150,7 +151,7 @@ struct LuPlan {
     int32_t *d_bad = nullptr;
     int64_t *d_emb = nullptr;  // complex handles: source of every entry of the real form
     ~LuPlan() {
-        for (void *q : {(void *)d_lu, (void *)d_trsm, (void *)d_probs, (void *)d_tiles, (void *)d_sc, (void *)d_mat,
+        for (void *q : {(void *)d_lu, (void *)d_tri, (void *)d_probs, (void *)d_tiles, (void *)d_sc, (void *)d_mat,
                         (void *)d_W, (void *)d_bad, (void *)d_emb})
             (void)hipFree(q);
     }
@@ -1431,8 +1432,8 @@ static selinv_status ensure_device(selinv_handle h) {
     return SELINV_OK;
 }
 
-// Work lists of the device LU.  Every operand range of a tile LU, right
-// solve or product is checked on the host against its supernode's segment of
+// Work lists of the device LU.  Every operand range of a tile LU, tile
+// inverse or product is checked on the host against its supernode's segment of
 // the factor storage, and every destination of a Schur complement entry
 // against the segment and the level of the supernode that holds it, before
 // anything is uploaded.
@@ -1440,7 +1441,7 @@ static selinv_status build_lu(selinv_handle h) {
     const Plan &P = h->P;
     auto L = std::make_unique<LuPlan>();
     std::vector<LuTile> lus;
-    std::vector<TrsmItem> trs;
+    std::vector<TriItem> tris;
     std::vector<GemmProb> probs;
     std::vector<GemmTile> tiles;
     std::vector<GatherTile> scs;
@@ -1458,9 +1459,10 @@ static selinv_status build_lu(selinv_handle h) {
     }
     HIPCHK(h->err, alloc_bytes((void **)&L->d_W, w_max * 8), "alloc Schur complement buffer");
     double *D0 = h->d_diag, *L0 = h->d_lpan, *U0 = h->d_upan, *W0 = L->d_W;
-    // C = -op(A) op(B) + beta C
+    double *Li0 = h->d_Linv, *Ui0 = h->d_Uinv;  // the tile inverses (the run recomputes them)
+    // C = alpha op(A) op(B) + beta C
     auto gemm = [&](const double *A, int64_t lda, int opA, const double *B, int64_t ldb, int opB, double *C,
-                    int64_t ldc, int M, int N, int K, double beta) {
+                    int64_t ldc, int M, int N, int K, double alpha, double beta) {
         GemmProb g{};
         g.A = A;
         g.B = B;
@@ -1475,7 +1477,7 @@ static selinv_status build_lu(selinv_handle h) {
         g.opA = opA;
         g.opB = opB;
         g.push_sn = g.push_mat = -1;
-        g.alpha = -1.0;
+        g.alpha = alpha;
         g.beta = beta;
         add_tiles(tiles, (int)probs.size(), M, N, GEMM_TILE_64);
         probs.push_back(g);
@@ -1488,7 +1490,20 @@ static selinv_status build_lu(selinv_handle h) {
         int smax = 0;
         for (int32_t K : Ks) smax = std::max(smax, h->sn[K].s);
         for (int j0 = 0; j0 < smax; j0 += 64) {
-            const size_t l0 = lus.size(), t0 = trs.size(), g0 = tiles.size();
+            // solves first (launch L_SOLVE), trailing updates after them
+            const size_t l0 = lus.size(), t0 = tris.size(), g0 = tiles.size();
+            struct Upd {
+                const double *A;
+                int64_t lda;
+                int opA;
+                const double *B;
+                int64_t ldb;
+                int opB;
+                double *C;
+                int64_t ldc;
+                int M, N, K;
+            };
+            std::vector<Upd> upd;
             for (int32_t K : Ks) {
                 const SnRec &r = h->sn[K];
                 const int s = r.s, cl = r.cl, cu = r.cu;
@@ -1499,55 +1514,53 @@ static selinv_status build_lu(selinv_handle h) {
                 const int64_t tile = j0 + j0 * ld;
                 inside(r.off_d + tile, (b - 1) + (b - 1) * ld, r.off_d, ss);
                 lus.push_back(LuTile{D, s, j0, r.f, 0});
-                const double *T = D + tile;
-                // U of the tile: T(u, t) = D(j0+u, j0+t); its unit L transposed: D(j0+t, j0+u)
-                auto trsm = [&](double *X, int64_t rs, int64_t cs, int rows, bool lower) {
-                    trs.push_back(TrsmItem{X, T, rs, cs, lower ? ld : 1, lower ? 1 : ld, rows, b, lower ? 1 : 0, 0});
-                };
-                for (int i0 = 0; i0 < rest; i0 += 64) {
-                    const int rows = std::min(64, rest - i0);
-                    int64_t o = (j0 + b + i0) + j0 * ld;  // rows of L below the tile
-                    inside(r.off_d + o, (rows - 1) + (b - 1) * ld, r.off_d, ss);
-                    trsm(D + o, 1, ld, rows, false);
-                    o = j0 + (j0 + b + i0) * ld;  // columns of U right of the tile
-                    inside(r.off_d + o, (rows - 1) * ld + (b - 1), r.off_d, ss);
-                    trsm(D + o, ld, 1, rows, true);
-                }
-                for (int i0 = 0; i0 < cl; i0 += 64) {
-                    const int rows = std::min(64, cl - i0);
-                    const int64_t o = r.off_l + i0 + (int64_t)j0 * cl;
-                    inside(o, (rows - 1) + (int64_t)(b - 1) * cl, r.off_l, (int64_t)cl * s);
-                    trsm(L0 + o, 1, cl, rows, false);
-                }
-                for (int i0 = 0; i0 < cu; i0 += 64) {
-                    const int rows = std::min(64, cu - i0);
-                    const int64_t o = r.off_u + i0 + (int64_t)j0 * cu;
-                    inside(o, (rows - 1) + (int64_t)(b - 1) * cu, r.off_u, (int64_t)cu * s);
-                    trsm(U0 + o, 1, cu, rows, true);
-                }
+                TriItem ti{};
+                ti.D = D;
+                ti.Linv = Li0 + r.off_d;
+                ti.Uinv = Ui0 + r.off_d;
+                ti.s = s;
+                ti.j0 = j0;
+                tris.push_back(ti);
+                const double *Lt = Li0 + r.off_d + tile, *Ut = Ui0 + r.off_d + tile;
+                // solves, in place: every product has one 64-wide tile along
+                // the solved dimension, so each workgroup reads only the rows
+                // (columns) it writes
                 if (rest > 0) {
                     const int64_t l21 = (j0 + b) + j0 * ld, u12 = j0 + (j0 + b) * ld, c22 = (j0 + b) * (1 + ld);
                     inside(r.off_d + l21, (rest - 1) + (b - 1) * ld, r.off_d, ss);
                     inside(r.off_d + u12, (b - 1) + (rest - 1) * ld, r.off_d, ss);
                     inside(r.off_d + c22, (rest - 1) + (rest - 1) * ld, r.off_d, ss);
-                    gemm(D + l21, ld, 0, D + u12, ld, 0, D + c22, ld, rest, rest, b, 1.0);
-                    if (cl > 0) {
-                        const int64_t a = r.off_l + (int64_t)j0 * cl, c = r.off_l + (int64_t)(j0 + b) * cl;
-                        inside(a, (cl - 1) + (int64_t)(b - 1) * cl, r.off_l, (int64_t)cl * s);
+                    gemm(D + l21, ld, 0, Ut, ld, 0, D + l21, ld, rest, b, b, 1.0, 0.0);  // L21 = A21 U11^{-1}
+                    gemm(Lt, ld, 0, D + u12, ld, 0, D + u12, ld, b, rest, b, 1.0, 0.0);  // U12 = L11^{-1} A12
+                    upd.push_back({D + l21, ld, 0, D + u12, ld, 0, D + c22, ld, rest, rest, b});
+                }
+                if (cl > 0) {  // L(R_L, K) columns of the tile: A U11^{-1}; later columns -= them U12
+                    const int64_t a = r.off_l + (int64_t)j0 * cl;
+                    inside(a, (cl - 1) + (int64_t)(b - 1) * cl, r.off_l, (int64_t)cl * s);
+                    gemm(L0 + a, cl, 0, Ut, ld, 0, L0 + a, cl, cl, b, b, 1.0, 0.0);
+                    if (rest > 0) {
+                        const int64_t c = r.off_l + (int64_t)(j0 + b) * cl;
                         inside(c, (cl - 1) + (int64_t)(rest - 1) * cl, r.off_l, (int64_t)cl * s);
-                        gemm(L0 + a, cl, 0, D + u12, ld, 0, L0 + c, cl, cl, rest, b, 1.0);
+                        upd.push_back({L0 + a, cl, 0, D + j0 + (j0 + b) * ld, ld, 0, L0 + c, cl, cl, rest, b});
                     }
-                    if (cu > 0) {  // U(K, R_U)^T(:, later) -= U(K, R_U)^T(:, tile) L21^T
-                        const int64_t a = r.off_u + (int64_t)j0 * cu, c = r.off_u + (int64_t)(j0 + b) * cu;
-                        inside(a, (cu - 1) + (int64_t)(b - 1) * cu, r.off_u, (int64_t)cu * s);
+                }
+                if (cu > 0) {  // U(K, R_U)^T columns of the tile: A L11^{-T}; later columns -= them L21^T
+                    const int64_t a = r.off_u + (int64_t)j0 * cu;
+                    inside(a, (cu - 1) + (int64_t)(b - 1) * cu, r.off_u, (int64_t)cu * s);
+                    gemm(U0 + a, cu, 0, Lt, ld, 1, U0 + a, cu, cu, b, b, 1.0, 0.0);
+                    if (rest > 0) {
+                        const int64_t c = r.off_u + (int64_t)(j0 + b) * cu;
                         inside(c, (cu - 1) + (int64_t)(rest - 1) * cu, r.off_u, (int64_t)cu * s);
-                        gemm(U0 + a, cu, 0, D + l21, ld, 1, U0 + c, cu, cu, rest, b, 1.0);
+                        upd.push_back({U0 + a, cu, 0, D + (j0 + b) + j0 * ld, ld, 1, U0 + c, cu, cu, rest, b});
                     }
                 }
             }
             mark(LuPlan::L_TILES, l0, lus.size());
-            mark(LuPlan::L_TRSM, t0, trs.size());
-            mark(LuPlan::L_UPDATE, g0, tiles.size());
+            mark(LuPlan::L_TRI, t0, tris.size());
+            mark(LuPlan::L_SOLVE, g0, tiles.size());
+            const size_t g1 = tiles.size();
+            for (const Upd &u : upd) gemm(u.A, u.lda, u.opA, u.B, u.ldb, u.opB, u.C, u.ldc, u.M, u.N, u.K, -1.0, 1.0);
+            mark(LuPlan::L_UPDATE, g1, tiles.size());
         }
         // W_K = -L(R_L, K) U(K, R_U) and its scatter into the ancestors
         const size_t g0 = tiles.size(), c0 = scs.size();
@@ -1557,7 +1570,7 @@ static selinv_status build_lu(selinv_handle h) {
             const int s = r.s, cl = r.cl, cu = r.cu;
             if (cl == 0 || cu == 0) continue;
             inside(w, (int64_t)cl * cu - 1, 0, w_max);
-            gemm(L0 + r.off_l, cl, 0, U0 + r.off_u, cu, 1, W0 + w, cl, cl, cu, s, 0.0);
+            gemm(L0 + r.off_l, cl, 0, U0 + r.off_u, cu, 1, W0 + w, cl, cl, cu, s, -1.0, 0.0);
             for (int a0 = 0; a0 < cl; a0 += 64)
                 for (int b0 = 0; b0 < cu; b0 += 64) scs.push_back(GatherTile{0, K, a0, b0, -1, cl, cu, 0, w, -1, 0, 0});
             // destinations of every entry of W_K
@@ -1589,7 +1602,7 @@ static selinv_status build_lu(selinv_handle h) {
         return SELINV_E_STATE;
     }
     HIPCHK(h->err, upload(&L->d_lu, lus), "upload LU tiles");
-    HIPCHK(h->err, upload(&L->d_trsm, trs), "upload solves");
+    HIPCHK(h->err, upload(&L->d_tri, tris), "upload tile inverses");
     HIPCHK(h->err, upload(&L->d_probs, probs), "upload LU products");
     HIPCHK(h->err, upload(&L->d_tiles, tiles), "upload LU product tiles");
     HIPCHK(h->err, upload(&L->d_sc, scs), "upload scatter tiles");
@@ -1657,7 +1670,10 @@ selinv_status selinv_factor_device(selinv_handle h, const double *values, void *
         hipError_t e = hipSuccess;
         switch (l.kind) {
             case LuPlan::L_TILES: e = launch_lu_tiles(L.d_lu + l.first, l.count, L.d_bad, s); break;
-            case LuPlan::L_TRSM: e = launch_trsm_tiles(L.d_trsm + l.first, l.count, s); break;
+            case LuPlan::L_TRI: e = launch_tri_base(L.d_tri + l.first, l.count, 4, s); break;
+            case LuPlan::L_SOLVE:
+                e = launch_gemm(GEMM_PRO_F64, CMP_F64, GEMM_TILE_64, L.d_probs, L.d_tiles + l.first, l.count, s);
+                break;
             case LuPlan::L_UPDATE:
                 e = launch_gemm(GEMM_STEP4, CMP_F64, GEMM_TILE_64, L.d_probs, L.d_tiles + l.first, l.count, s);
                 break;
