@@ -228,7 +228,11 @@ selinv_status selinv_set_sweep_mode(selinv_handle h, int32_t mode);
  *     launch or the per-phase launches;
  *   - with sweep mode 0, the level sweep or the persistent sweep;
  *   - the prologue of the wide lower levels on a side stream beside the
- *     upper levels, or all of the prologue before the sweep.
+ *     upper levels, or all of the prologue before the sweep;
+ *   - with the side stream, its tile inversions in one launch or in chunks
+ *     of 5/4, 3/2, 7/4, 2, 5/2 or 3 times the compute-unit count (a launch
+ *     that fills the device holds the upper levels' launches back until it
+ *     drains).
  * Each configuration runs reps + 1 times (the first untimed; 1 <= reps <=
  * 100) and counts its fastest run: per-launch times from eager runs with
  * events, whole-sweep comparisons from replays of the sweep's HIP graph.  When the measured choices are not faster
@@ -239,17 +243,19 @@ selinv_status selinv_tune(selinv_handle h, selinv_precision prec, int32_t reps, 
                           double *ms_policy, double *ms_tuned);
 
 /* The tuning table of `prec` as int32 values:
- *   [2, nlevels, sweep form (0: the handle's mode, 1: levels, 2: persistent),
+ *   [3, nlevels, sweep form (0: the handle's mode, 1: levels, 2: persistent),
  *    tile of the inversion rounds, of the normalisation, of the diagonal
  *    initialisation, 1 if the whole prologue runs before the sweep (no side
- *    stream), then for every level d = 0 .. nlevels-1: tile of steps 3+5,
- *    tile of step 4, 1 if the level's small supernodes use the per-phase
- *    launches],
- * tile 0 meaning the size policy.  *count receives 7 + 3 nlevels (0 when the
+ *    stream), tile-inversion items per launch on the side stream (0: one
+ *    launch; at most 2^20), then for every level d = 0 .. nlevels-1: tile of
+ *    steps 3+5, tile of step 4, 1 if the level's small supernodes use the
+ *    per-phase launches],
+ * tile 0 meaning the size policy.  *count receives 8 + 3 nlevels (0 when the
  * handle is untuned; nothing written); out = NULL queries the count;
  * cap < count gives SELINV_E_INVALID_ARG.  selinv_set_tuning also takes the
- * earlier layout [1, nlevels, sweep, tri, norm, dt, per level ...] (6 + 3
- * nlevels values, side stream kept). */
+ * earlier layouts [2, nlevels, sweep, tri, norm, dt, no_fork, per level ...]
+ * (7 + 3 nlevels values, one side launch) and [1, nlevels, sweep, tri, norm,
+ * dt, per level ...] (6 + 3 nlevels values, side stream kept). */
 selinv_status selinv_get_tuning(selinv_handle h, selinv_precision prec, int32_t *out, int32_t cap,
                                 int32_t *count);
 

@@ -77,10 +77,11 @@ def describe(table: list) -> dict:
     if not table:
         return {"tuned": False}
     L = table[1]
-    hd = 7 if table[0] == 2 else 6
+    hd = {3: 8, 2: 7}.get(table[0], 6)
     per = [table[hd + 3 * d: hd + 3 + 3 * d] for d in range(L)]
     return {"tuned": True, "sweep": {0: "handle", 1: "levels", 2: "persistent"}[table[2]],
             "prologue_tiles": {"tri": table[3], "norm": table[4], "diag_init": table[5]},
-            "prologue_side_stream": not (hd == 7 and table[6] == 1),
+            "prologue_side_stream": not (hd >= 7 and table[6] == 1),
+            "side_inversion_chunk": table[7] if hd == 8 else 0,
             "steps35_tiles": [p[0] for p in per], "step4_tiles": [p[1] for p in per],
             "small_per_phase_levels": [d for d, p in enumerate(per) if p[2]]}

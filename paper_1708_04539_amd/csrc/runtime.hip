@@ -62,6 +62,11 @@ struct Sweep {
     } pro[2];
     int split = 0;
     hipStream_t side = nullptr;
+    // tile-inversion items per launch on the side stream (0: one launch).  A
+    // launch that fills every compute unit leaves the upper levels' launches
+    // waiting for slots until it drains; cut into chunks, the side stream
+    // frees slots between its launches.
+    int side_chunk = 0;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     std::vector<Range> small, gat, g35, g4;
     // split-K step 4: per level the reduction items (red4[d].count of them,
@@ -124,6 +129,7 @@ struct Tuning {
     std::vector<char> no_small;     // per level: 1 = per-phase launches for its small supernodes
     int sweep = SWEEP_AUTO;         // SWEEP_LEVELS / SWEEP_PERSISTENT, or the handle's own mode
     int no_fork = 0;                // 1: the whole prologue before the sweep, no side stream
+    int side_chunk = 0;             // tile-inversion items per launch on the side stream (0: one launch)
 };
 
 constexpr int NPREC = 3;
@@ -463,6 +469,7 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, int sweep_mo
                 break;
             }
         if (tn && tn->no_fork) S->split = 0;
+        if (tn) S->side_chunk = tn->side_chunk;
     }
     std::vector<std::vector<char>> part(hs.size());
     for (size_t mi = 0; mi < hs.size(); mi++) {
@@ -994,11 +1001,19 @@ hipError_t launch_sweep(const Sweep &S, hipStream_t st, std::vector<hipEvent_t> 
     };
     // prologue parts: diagonal-block inversion (base blocks and doubling
     // rounds), normalisation, diagonal initialisation
+    auto tri_launch = [&](const Range &r, int nb, hipStream_t s) -> hipError_t {
+        const int chunk = (s == S.side && S.side_chunk > 0) ? S.side_chunk : r.count;
+        for (int o = 0; o < r.count; o += chunk) {
+            hipError_t e2 = launch_tri_base(S.d_tri + r.off + o, std::min(chunk, r.count - o), nb, s);
+            if (e2) return e2;
+        }
+        return hipSuccess;
+    };
     auto tri_part = [&](const Sweep::Prologue &P, hipStream_t s) -> hipError_t {
         hipError_t e2;
-        if ((e2 = launch_tri_base(S.d_tri + P.tri.off, P.tri.count, 4, s))) return e2;
-        if ((e2 = launch_tri_base(S.d_tri + P.tri1.off, P.tri1.count, 1, s))) return e2;
-        if ((e2 = launch_tri_base(S.d_tri + P.tri2.off, P.tri2.count, 2, s))) return e2;
+        if ((e2 = tri_launch(P.tri, 4, s))) return e2;
+        if ((e2 = tri_launch(P.tri1, 1, s))) return e2;
+        if ((e2 = tri_launch(P.tri2, 2, s))) return e2;
         for (const Range &r : P.tri_rounds)
             if ((e2 = launch_gemm(GEMM_PRO_F64, CMP_F64, r.tile, S.d_probs, S.d_tiles + r.off, r.count, s)))
                 return e2;
@@ -1983,7 +1998,29 @@ selinv_status selinv_tune(selinv_handle h, selinv_precision prec, int32_t reps, 
             t_best = t;
         }
     }
-    // 5. keep the size policy when the measured choices are no faster
+    // 5. with a side stream: its tile inversions in chunks of a multiple of
+    //    the compute-unit count, or in one launch
+    if (!best.no_fork) {
+        h->tune[prec] = best;
+        drop_sweep(h, prec);
+        if ((st = ensure_sweep(h, prec))) return st;
+        int cus = 0;
+        HIPCHK(h->err, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device),
+               "device attribute");
+        if (h->sweep[prec]->split > 0 && cus > 0) {
+            for (int q : {5, 6, 7, 8, 10, 12}) {
+                Tuning ch = best;
+                ch.side_chunk = q * cus / 4;
+                h->tune[prec] = ch;
+                if ((st = tune_measure(h, prec, s, reps, false, t, nullptr))) return st;
+                if (t < t_best) {
+                    best = ch;
+                    t_best = t;
+                }
+            }
+        }
+    }
+    // 6. keep the size policy when the measured choices are no faster
     if (t_best > t_policy) {
         Tuning pol;
         pol.set = true;
@@ -2000,27 +2037,29 @@ selinv_status selinv_tune(selinv_handle h, selinv_precision prec, int32_t reps, 
     return SELINV_OK;
 }
 
-// flat form: [2, nlevels, sweep, tri, norm, dt, no_fork, then per level: t35, t4, no_small]
-// (a table of the first layout, without no_fork, is still accepted)
+// flat form: [3, nlevels, sweep, tri, norm, dt, no_fork, side_chunk, then per
+// level: t35, t4, no_small] (tables of the earlier layouts, without
+// side_chunk (2) or without no_fork as well (1), are still accepted)
 selinv_status selinv_get_tuning(selinv_handle h, selinv_precision prec, int32_t *out, int32_t cap,
                                 int32_t *count) {
     if (!h || !valid_prec(prec) || !count) return SELINV_E_INVALID_ARG;
     const Tuning &tn = h->tune[prec];
     const int L = h->P.nlevels;
-    *count = tn.set ? 7 + 3 * L : 0;
+    *count = tn.set ? 8 + 3 * L : 0;
     if (!tn.set || !out) return SELINV_OK;
     if (cap < *count) {
         h->err = "tuning buffer too small";
         return SELINV_E_INVALID_ARG;
     }
     int32_t *o = out;
-    *o++ = 2;
+    *o++ = 3;
     *o++ = L;
     *o++ = tn.sweep;
     *o++ = tn.tri;
     *o++ = tn.norm;
     *o++ = tn.dt;
     *o++ = tn.no_fork;
+    *o++ = tn.side_chunk;
     for (int d = 0; d < L; d++) {
         *o++ = tn.t35[d];
         *o++ = tn.t4[d];
@@ -2038,10 +2077,10 @@ selinv_status selinv_set_tuning(selinv_handle h, selinv_precision prec, const in
     }
     const int L = h->P.nlevels;
     auto tile_ok = [](int v) { return v == 0 || v == GEMM_TILE_32 || v == GEMM_TILE_64 || v == GEMM_TILE_128; };
-    const int ver = in && count > 0 ? in[0] : 0, hd = ver == 2 ? 7 : 6;
-    bool ok = in && (ver == 1 || ver == 2) && count == hd + 3 * L && in[1] == L && in[2] >= SWEEP_AUTO &&
+    const int ver = in && count > 0 ? in[0] : 0, hd = ver == 3 ? 8 : ver == 2 ? 7 : 6;
+    bool ok = in && ver >= 1 && ver <= 3 && count == hd + 3 * L && in[1] == L && in[2] >= SWEEP_AUTO &&
               in[2] <= SWEEP_PERSISTENT && tile_ok(in[3]) && tile_ok(in[4]) && tile_ok(in[5]) &&
-              (ver == 1 || in[6] == 0 || in[6] == 1);
+              (ver == 1 || in[6] == 0 || in[6] == 1) && (ver < 3 || (in[7] >= 0 && in[7] <= (1 << 20)));
     for (int d = 0; ok && d < L; d++)
         ok = tile_ok(in[hd + 3 * d]) && tile_ok(in[hd + 1 + 3 * d]) &&
              (in[hd + 2 + 3 * d] == 0 || in[hd + 2 + 3 * d] == 1);
@@ -2055,7 +2094,8 @@ selinv_status selinv_set_tuning(selinv_handle h, selinv_precision prec, const in
     tn.tri = in[3];
     tn.norm = in[4];
     tn.dt = in[5];
-    tn.no_fork = ver == 2 ? in[6] : 0;
+    tn.no_fork = ver >= 2 ? in[6] : 0;
+    tn.side_chunk = ver == 3 ? in[7] : 0;
     for (int d = 0; d < L; d++) {
         tn.t35.push_back(in[hd + 3 * d]);
         tn.t4.push_back(in[hd + 1 + 3 * d]);

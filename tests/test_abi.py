@@ -293,18 +293,23 @@ def test_tuning_table_set_get_and_validation(si):
     s = si.SelInv(w.n, w.colptr, w.rowind, w.perm, w.max_super, w.relax, w.pad_pct)
     L = s.info["nlevels"]
     assert s.get_tuning("fp64") == []
-    table = [2, L, 1, 64, 32, 0, 1]
+    table = [3, L, 1, 64, 32, 0, 0, 448]
     for d in range(L):
         table += [32 if d % 2 else 64, 128, d % 2]
     s.set_tuning(table, "mixed_fp32")
     assert s.get_tuning("mixed_fp32") == table
     assert s.get_tuning("fp64") == []
-    # the first layout (no prologue flag) is still accepted, side stream kept
-    v1 = [1] + table[1:6] + table[7:]
+    # the earlier layouts are still accepted: without the side chunk (one side
+    # launch), and without the prologue flag as well (side stream kept)
+    v2 = [2] + table[1:7] + table[8:]
+    s.set_tuning(v2, "fp64")
+    assert s.get_tuning("fp64") == table[:7] + [0] + table[8:]
+    v1 = [1] + table[1:6] + table[8:]
     s.set_tuning(v1, "mixed_bf16x3")
-    assert s.get_tuning("mixed_bf16x3") == [2] + table[1:6] + [0] + table[7:]
-    bad = [table[:-1], [3] + table[1:], table[:1] + [L + 1] + table[2:], table[:3] + [48] + table[4:],
-           table[:9] + [2] + table[10:], table[:2] + [3] + table[3:], table[:6] + [2] + table[7:]]
+    assert s.get_tuning("mixed_bf16x3") == table[:6] + [0, 0] + table[8:]
+    bad = [table[:-1], [4] + table[1:], table[:1] + [L + 1] + table[2:], table[:3] + [48] + table[4:],
+           table[:10] + [2] + table[11:], table[:2] + [3] + table[3:], table[:6] + [2] + table[7:],
+           table[:7] + [-1] + table[8:], table[:7] + [(1 << 20) + 1] + table[8:], v2[:-1]]
     for b in bad:
         with pytest.raises(si.SelinvError) as e:
             s.set_tuning(b, "mixed_fp32")
@@ -315,8 +320,8 @@ def test_tuning_table_set_get_and_validation(si):
     # both sweep forms for an exact analysis too
     x = si.SelInv(w.n, w.colptr, w.rowind, w.perm, w.max_super, w.relax, w.pad_pct, symbolic="exact")
     Lx = x.info["nlevels"]
-    x.set_tuning([2, Lx, 2, 0, 0, 0, 0] + [0, 0, 0] * Lx)
-    x.set_tuning([2, Lx, 1, 0, 0, 0, 1] + [0, 0, 0] * Lx)
+    x.set_tuning([3, Lx, 2, 0, 0, 0, 0, 0] + [0, 0, 0] * Lx)
+    x.set_tuning([3, Lx, 1, 0, 0, 0, 1, 0] + [0, 0, 0] * Lx)
 
 
 def test_autotune_describe():
@@ -327,6 +332,8 @@ def test_autotune_describe():
     assert d["small_per_phase_levels"] == [1] and d["sweep"] == "levels"
     d = describe([2, 2, 1, 64, 32, 32, 1, 32, 64, 0, 128, 128, 1])
     assert d["steps35_tiles"] == [32, 128] and not d["prologue_side_stream"]
+    d = describe([3, 2, 1, 64, 32, 32, 0, 512, 32, 64, 0, 128, 128, 1])
+    assert d["steps35_tiles"] == [32, 128] and d["prologue_side_stream"] and d["side_inversion_chunk"] == 512
 
 
 # --------------------------------------------------------------------------

@@ -550,7 +550,7 @@ def test_tune_c1_keeps_parity(si, c1_pair, prec):
     ms_pol, ms_tun = s.tune(prec, reps=3)
     table = s.get_tuning(prec)
     say("c1 tune", prec, "policy ms", ms_pol, "tuned ms", ms_tun, "table", table)
-    assert ms_tun <= ms_pol and len(table) == 7 + 3 * s.info["nlevels"]
+    assert ms_tun <= ms_pol and len(table) == 8 + 3 * s.info["nlevels"]
     s.run(prec)
     compare_superset(s, o, TOL[prec])
     s.run(prec, graph=True)
@@ -571,6 +571,25 @@ def test_forced_tables_keep_parity(si, prec):
             s.set_tuning([2, L, 1, edge, edge, edge, per_phase] + [edge, edge, per_phase] * L, prec)
             s.run(prec)
             compare_superset(s, o, TOL[prec])
+
+
+def test_side_inversion_chunks_bitwise_c1(si, c1_pair):
+    """The side stream's tile inversions cut into chunks (ragged last chunk
+    included) give bitwise the same results as one launch, eager and from the
+    HIP graph: every item writes only its own outputs."""
+    w, s, o = c1_pair
+    L = s.info["nlevels"]
+    say("c1 side chunks")
+    s.set_tuning([3, L, 1, 0, 0, 0, 0, 0] + [0, 0, 0] * L, "fp64")
+    s.run("fp64")
+    ref = s.export()[2]
+    for chunk in (37, 300, 1 << 20):
+        s.set_tuning([3, L, 1, 0, 0, 0, 0, chunk] + [0, 0, 0] * L, "fp64")
+        s.run("fp64")
+        assert np.array_equal(s.export()[2], ref)
+        s.run("fp64", graph=True)
+        assert np.array_equal(s.export()[2], ref)
+    s.set_tuning([], "fp64")
 
 
 def test_tune_exact_upwind_and_cache(si, tmp_path):
