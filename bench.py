@@ -12,7 +12,7 @@ Default workload: 2D 9-point asymmetric stencil on a 256x256 grid (n = 65536),
 nested dissection, supernodes <= 128, FP64 (the plain-FP64 GPU configuration);
 the mixed form is measured on the same matrix and reported beside it.
 
-Prints ONE JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
+Prints ONE JSON line.  --gpus N with N > 1 exits: the library runs on one GPU.
 """
 from __future__ import annotations
 
@@ -255,7 +255,7 @@ def main():
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design note, "
+        print(json.dumps({"error": "the library runs on one GPU only; multi-GPU sharding is a design note, "
                                    "not an implemented path", "n_gpus": args.gpus}))
         sys.exit(2)
     import numpy as np
