@@ -194,7 +194,8 @@ class Oracle:
         v = np.empty(m, np.float64)
         self._check(self._lib.oracle_export(self._h, _ptr(r, C.c_int32), _ptr(c, C.c_int32),
                                             _ptr(v, C.c_double)), "export")
-        order = np.lexsort((r, c))
+        # sorted by (column, row); the keys are unique
+        order = np.argsort(c.astype(np.int64) * self.n + r)
         return r[order], c[order], v[order]
 
     def structure(self) -> dict:

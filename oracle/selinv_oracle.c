@@ -829,20 +829,31 @@ int oracle_selinv(oracle_t *o) {
                 Ui[r * s + c] = acc / D[r * s + r];
             }
         }
-        /* Lhat(R_L, K) = L(R_L, K) (L_KK)^{-1} */
-        for (int64_t a = 0; a < cl; a++)
+        /* Lhat(R_L, K) = L(R_L, K) (L_KK)^{-1}  (row a of L(R_L, K) looked up once) */
+        double *lrow = (double *)malloc(sizeof(double) * (s + 1));
+        if (!lrow) {
+            nomem = 1;
+            continue;
+        }
+        for (int64_t a = 0; a < cl; a++) {
+            for (int64_t k = 0; k < s; k++) lrow[k] = o->lu[slot(o, RL[a], f + k)];
             for (int64_t t = 0; t < s; t++) {
                 double acc = 0.0;
-                for (int64_t k = 0; k < s; k++) acc += o->lu[slot(o, RL[a], f + k)] * Li[k * s + t];
+                for (int64_t k = 0; k < s; k++) acc += lrow[k] * Li[k * s + t];
                 Lh[K][a * s + t] = acc;
             }
-        /* Uhat(K, R_U) = (U_KK)^{-1} U(K, R_U) */
-        for (int64_t t = 0; t < s; t++)
-            for (int64_t b = 0; b < cu; b++) {
+        }
+        /* Uhat(K, R_U) = (U_KK)^{-1} U(K, R_U)  (column b of U(K, R_U) looked up once) */
+        double *ucol = lrow;
+        for (int64_t b = 0; b < cu; b++) {
+            for (int64_t k = 0; k < s; k++) ucol[k] = o->lu[slot(o, f + k, RU[b])];
+            for (int64_t t = 0; t < s; t++) {
                 double acc = 0.0;
-                for (int64_t k = 0; k < s; k++) acc += Ui[t * s + k] * o->lu[slot(o, f + k, RU[b])];
+                for (int64_t k = 0; k < s; k++) acc += Ui[t * s + k] * ucol[k];
                 Uh[K][t * cu + b] = acc;
             }
+        }
+        free(lrow);
         /* (L_KK)^{-T} (U_KK)^{-T}, entry (t, t2) = sum_k Li(k, t) Ui(t2, k) */
         for (int64_t t = 0; t < s; t++)
             for (int64_t t2 = 0; t2 < s; t2++) {
@@ -888,14 +899,20 @@ int oracle_selinv(oracle_t *o) {
             set_err(o, "an entry of A^{-T}(R_L, R_U) is outside the block pattern");
             return OR_E_CLOSURE;
         }
-        /* step 3: X = A^{-T}(K, R_U) = -Lhat(R_L, K)^T G */
+        /* step 3: X = A^{-T}(K, R_U) = -Lhat(R_L, K)^T G.  Every entry X(t, b)
+         * sums its terms in increasing a; the sums of one row t advance
+         * together so that the inner loop runs along a row of G. */
 #pragma omp parallel for schedule(static)
-        for (int64_t t = 0; t < s; t++)
-            for (int64_t b = 0; b < cu; b++) {
-                double acc = 0.0;
-                for (int64_t a = 0; a < cl; a++) acc += Lh[K][a * s + t] * G[a * cu + b];
-                X[t * cu + b] = -acc;
+        for (int64_t t = 0; t < s; t++) {
+            double *acc = X + t * cu;
+            for (int64_t b = 0; b < cu; b++) acc[b] = 0.0;
+            for (int64_t a = 0; a < cl; a++) {
+                const double l = Lh[K][a * s + t];
+                const double *g = G + a * cu;
+                for (int64_t b = 0; b < cu; b++) acc[b] += l * g[b];
             }
+            for (int64_t b = 0; b < cu; b++) acc[b] = -acc[b];
+        }
         /* step 4: Z = (L_KK)^{-T}(U_KK)^{-T} - X Uhat(K, R_U)^T */
 #pragma omp parallel for schedule(static)
         for (int64_t t = 0; t < s; t++)
@@ -912,16 +929,28 @@ int oracle_selinv(oracle_t *o) {
                 for (int64_t b = 0; b < cu; b++) acc += G[a * cu + b] * Uh[K][t * cu + b];
                 Y[a * s + t] = -acc;
             }
-        /* the other diagonal formula, (L_KK)^{-T}(U_KK)^{-T} - Lhat^T Y, as a check */
-        for (int64_t t = 0; t < s; t++)
+        /* the other diagonal formula, (L_KK)^{-T}(U_KK)^{-T} - Lhat^T Y, as a check
+         * (each sum in increasing a, the sums of one row t together) */
+#pragma omp parallel for schedule(static) reduction(max : altdiff, altabs)
+        for (int64_t t = 0; t < s; t++) {
+            double *acc = (double *)calloc((size_t)s + 1, sizeof(double));
+            if (!acc) {
+                altdiff = INFINITY;
+                continue;
+            }
+            for (int64_t a = 0; a < cl; a++) {
+                const double l = Lh[K][a * s + t];
+                const double *y = Y + a * s;
+                for (int64_t t2 = 0; t2 < s; t2++) acc[t2] += l * y[t2];
+            }
             for (int64_t t2 = 0; t2 < s; t2++) {
-                double acc = 0.0;
-                for (int64_t a = 0; a < cl; a++) acc += Lh[K][a * s + t] * Y[a * s + t2];
-                double alt = Dt[K][t * s + t2] - acc;
+                double alt = Dt[K][t * s + t2] - acc[t2];
                 double d = fabs(alt - Z[t * s + t2]);
                 if (d > altdiff) altdiff = d;
                 if (fabs(Z[t * s + t2]) > altabs) altabs = fabs(Z[t * s + t2]);
             }
+            free(acc);
+        }
         for (int64_t t = 0; t < s; t++)
             for (int64_t b = 0; b < cu; b++) o->z[slot(o, f + t, RU[b])] = X[t * cu + b];
         for (int64_t t = 0; t < s; t++)
