@@ -17,6 +17,8 @@ it never forms L or U.
 """
 from __future__ import annotations
 
+import os
+
 import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
@@ -53,3 +55,41 @@ def solve_column(A: sp.spmatrix, j: int, max_refine: int = 6):
     r = b - A_ld @ x.astype(np.longdouble)
     res = float(np.abs(r).max())
     return x, varah_bound(A) * res
+
+
+_A = None
+
+
+def _init_worker(A):
+    global _A
+    _A = A
+
+
+def _solve_one(j):
+    return solve_column(_A, j)
+
+
+def solve_columns(A: sp.spmatrix, js, workers: int = 0):
+    """solve_column for every column in js, in a pool of worker processes
+    (spawned, one BLAS thread each; workers = 0: one per available core, at
+    most 16).  Returns a list of (x, err_bound) in the order of js."""
+    import multiprocessing as mp
+    js = [int(j) for j in js]
+    if workers <= 0:
+        workers = min(16, len(os.sched_getaffinity(0)))
+    workers = max(1, min(workers, len(js)))
+    A = sp.csr_matrix(A)
+    if workers == 1:
+        return [solve_column(A, j) for j in js]
+    keep = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    for k in keep:
+        os.environ[k] = "1"
+    try:
+        with mp.get_context("spawn").Pool(workers, initializer=_init_worker, initargs=(A,)) as pool:
+            return pool.map(_solve_one, js, chunksize=1)
+    finally:
+        for k, v in keep.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v

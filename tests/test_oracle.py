@@ -337,3 +337,43 @@ def test_complex_oracle_sparse_columns_match_dense():
     sel = selected_dense(n, cp, ri, v)
     cols = np.repeat(np.arange(n), np.diff(cp))
     assert np.array_equal(sel, inv[cols, ri])
+
+
+# --------------------------------------------------------------------------
+# sampled exact columns (oracle.sampled): the reference at full size
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("which", ["c0", "grid3d_27pt"])
+def test_sampled_columns_match_dense_inverse(which):
+    """solve_column against LAPACK's dense inverse, on C0 and on a 13x13x12
+    27-point stencil of the C4 recipe (n = 2028): every entry of each solved
+    column to 1e-13, and the returned bound (Varah's bound on ||A^{-1}||_inf
+    times the extended-precision residual) holds and is small."""
+    from oracle.sampled import solve_column, solve_columns, varah_bound
+    from workloads import config_grid
+    if which == "c0":
+        w = config_c0()
+    else:
+        w = config_grid("g", (13, 13, 12), "box", "sym_perturbed", 0.1, 0, 512, 64, delta=0.15)
+    A = w.to_scipy()
+    inv = np.linalg.inv(A.toarray())
+    js = [0, w.n - 1, int(w.perm[-1])] + [int(j) for j in np.random.default_rng(5).integers(0, w.n, 3)]
+    for j in js[:3]:
+        x, bound = solve_column(A, j)
+        err = np.abs(x - inv[:, j]).max()
+        assert err <= 1e-13, (j, err)
+        assert bound <= 1e-13, (j, bound)
+        assert err <= bound + 1e-14, (j, err, bound)
+    # the pool gives the same columns
+    for j, (x, bound) in zip(js, solve_columns(A, js, workers=2)):
+        assert np.abs(x - inv[:, j]).max() <= 1e-13 and bound <= 1e-13
+
+
+def test_varah_bound_is_the_margin():
+    """The stencil recipe makes every row dominant by exactly its margin, so
+    the bound is 1 / margin, and it bounds ||A^{-1}||_inf."""
+    from oracle.sampled import varah_bound
+    w = config_c0()  # margin 0.1
+    A = w.to_scipy()
+    b = varah_bound(A)
+    assert abs(b - 10.0) < 1e-9
+    assert np.abs(np.linalg.inv(A.toarray())).sum(axis=1).max() <= b
