@@ -116,32 +116,31 @@ void etree(int64_t n, const std::vector<int64_t> &ptr, const std::vector<int32_t
     }
 }
 
+// Postorder of an elimination forest (parent[j] > j, or -1 at a root),
+// children taken in increasing order.  In that order every subtree occupies
+// a contiguous block of positions: the blocks of the node's children, in
+// increasing order, then the node itself.  A pass from the leaves up sizes
+// every block and places each child's block inside its parent's (children
+// are met in increasing order, so they are placed in that order); a pass from
+// the roots down turns the relative places into absolute positions.
 void tree_postorder(int64_t n, const std::vector<int32_t> &parent, std::vector<int32_t> &post) {
-    std::vector<int32_t> head(n, -1), next(n, -1), stack, cur(n);
-    for (int64_t j = n - 1; j >= 0; j--)
-        if (parent[j] >= 0) {
-            next[j] = head[parent[j]];
-            head[parent[j]] = (int32_t)j;
+    std::vector<int64_t> size(n, 1), used(n, 0), place(n, 0);
+    int64_t roots_used = 0;
+    for (int64_t j = 0; j < n; j++) {
+        const int32_t p = parent[j];
+        if (p < 0) {
+            place[j] = roots_used;
+            roots_used += size[j];
+        } else {
+            place[j] = used[p];
+            used[p] += size[j];
+            size[p] += size[j];
         }
-    post.clear();
-    post.reserve(n);
-    stack.reserve(n);
-    for (int64_t r = 0; r < n; r++) {
-        if (parent[r] >= 0) continue;
-        stack.push_back((int32_t)r);
-        cur[r] = head[r];
-        while (!stack.empty()) {
-            int32_t v = stack.back();
-            int32_t c = cur[v];
-            if (c >= 0) {
-                cur[v] = next[c];
-                cur[c] = head[c];
-                stack.push_back(c);
-            } else {
-                post.push_back(v);
-                stack.pop_back();
-            }
-        }
+    }
+    post.assign(n, 0);
+    for (int64_t v = n - 1; v >= 0; v--) {
+        if (parent[v] >= 0) place[v] += place[parent[v]];
+        post[place[v] + size[v] - 1] = (int32_t)v;
     }
 }
 
@@ -542,40 +541,48 @@ void symmetrized_sets(Plan &P, int64_t n, const int64_t *colptr, const int32_t *
     }
 
     // ---- partition -------------------------------------------------------
+    // Columns are in postorder, so the subtree of v is the column range
+    // [v - size(v) + 1, v].  (i) Every maximal subtree of at most `relax`
+    // columns is one supernode.  (ii) Elsewhere a supernode starts at a column
+    // and takes in the next column j while j is the parent of the last column
+    // taken and has no other child (a chain), and the padding estimate of the
+    // extended run [f, j],
+    //     Z = s cnt(j) - (cnt(f) + ... + cnt(j)) + s(s-1)/2,   s = j - f + 1,
+    // stays within pad_pct percent of the s (cnt(j) + s) entries it stores
+    // (Z counts the explicit zeros a run of nested column structures would
+    // hold; 0 for identical structures).  (iii) Cut at max_super.
     std::vector<int64_t> cnt;
     column_counts(n, aptr, adj, parent, cnt);
-    std::vector<int32_t> nkids(n, 0), relroot(n, -1);
-    std::vector<int64_t> size(n, 1);
-    for (int64_t j = 0; j < n; j++)
-        if (parent[j] >= 0) {
-            nkids[parent[j]]++;
-            size[parent[j]] += size[j];
-        }
-    for (int64_t v = 0; v < n; v++)
-        if (size[v] <= relax && (parent[v] < 0 || size[parent[v]] > relax))
-            for (int64_t u = v - size[v] + 1; u <= v; u++) relroot[u] = (int32_t)v;
-    // chains of nearly identical columns: j joins [f, j-1] while the padding
-    // estimate Z = s cnt(j) - sum_t cnt(t) + s(s-1)/2 of [f, j] (s = j-f+1) is
-    // at most pad_pct percent of the s (cnt(j) + s) stored entries
-    std::vector<int32_t> starts;
-    int64_t run_first = 0, run_sum = 0;
+    std::vector<int64_t> size(n, 1), pre(n + 1, 0);
+    std::vector<int32_t> nchild(n, 0);
     for (int64_t j = 0; j < n; j++) {
-        bool join = false;
-        if (j > 0) {
-            if (relroot[j] >= 0 || relroot[j - 1] >= 0) {
-                join = relroot[j] >= 0 && relroot[j] == relroot[j - 1];
-            } else if (parent[j - 1] == j && nkids[j] == 1) {
-                const int64_t sz = j - run_first + 1;
-                const int64_t Z = sz * cnt[j] - (run_sum + cnt[j]) + sz * (sz - 1) / 2;
-                join = 100 * Z <= int64_t(pad_pct) * sz * (cnt[j] + sz);
-            }
+        pre[j + 1] = pre[j] + cnt[j];
+        if (parent[j] >= 0) {
+            size[parent[j]] += size[j];
+            nchild[parent[j]]++;
         }
-        if (!join) {
-            starts.push_back((int32_t)j);
-            run_first = j;
-            run_sum = 0;
+    }
+    std::vector<int32_t> relaxed_last(n, -1);  // at the first column of a relaxed subtree: its last
+    for (int64_t v = 0; v < n; v++) {
+        const bool top = parent[v] < 0 || size[parent[v]] > relax;
+        if (size[v] <= relax && top) relaxed_last[v - size[v] + 1] = (int32_t)v;
+    }
+    auto extends = [&](int64_t f, int64_t j) {  // may column j join the run [f, j-1]?
+        if (relaxed_last[j] >= 0 || parent[j - 1] != j || nchild[j] != 1) return false;
+        const int64_t s = j - f + 1;
+        const int64_t Z = s * cnt[j] - (pre[j + 1] - pre[f]) + s * (s - 1) / 2;
+        return 100 * Z <= int64_t(pad_pct) * s * (cnt[j] + s);
+    };
+    std::vector<int32_t> starts;
+    for (int64_t j = 0; j < n;) {
+        starts.push_back((int32_t)j);
+        if (relaxed_last[j] >= 0) {
+            j = relaxed_last[j] + 1;
+            continue;
         }
-        run_sum += cnt[j];
+        const int64_t f = j;
+        while (j + 1 < n && extends(f, j + 1)) j++;
+        j++;
     }
     starts.push_back((int32_t)n);
     cut_partition(P, starts, max_super);
