@@ -26,8 +26,9 @@
  *     the fill nor any result.  The exact analysis keeps perm as given.
  *   * Every input array is copied; the caller may free it on return.  The
  *     handle owns all host and device memory until selinv_destroy().
- *   * Device memory is allocated with hipMalloc on the device that is current
- *     when selinv_factor() is called; later calls must use the same device.
+ *   * Device memory comes from hipMalloc, or from the hook installed with
+ *     selinv_set_allocator(), on the device that is current when
+ *     selinv_factor() is called; later calls must use the same device.
  *   * Streams: `stream` is a hipStream_t passed as void* (NULL = the null
  *     stream).  selinv_run() is asynchronous on that stream; the get/export
  *     calls synchronise it.
@@ -153,6 +154,26 @@ typedef struct {
     int64_t nnz_l, nnz_u; /* stored entries of the off-diagonal blocks of L, U   */
     int32_t complex_values; /* 1: a complex A in its real form (n, nnz_a of M)  */
 } selinv_info;
+
+/* Source of device memory (Algorithm 1 takes the factors and returns the
+ * selected blocks; the paper's implementation keeps them in its own
+ * distributed objects, section "Distributed data layout and structure").
+ * alloc(bytes, ctx) returns device memory of the current device, aligned to
+ * 256 bytes, or NULL when it has none (the calling library function then
+ * returns SELINV_E_NOMEM; a pointer that is not 256-byte aligned is handed
+ * back and gives SELINV_E_DEVICE); dealloc(ptr, ctx) takes back a pointer
+ * that alloc returned.  Both are called on the thread that called the
+ * library, never from a kernel or a stream callback.  Before a pointer is
+ * handed back, the library waits for the device to finish its work
+ * (hipDeviceSynchronize), so the hook may reuse the memory at once.
+ * alloc = dealloc = NULL restores hipMalloc / hipFree (the default); one of
+ * them NULL gives SELINV_E_INVALID_ARG.  The setting is process-wide; each
+ * handle and batch keeps the one in effect when it was created
+ * (selinv_analyze, selinv_batch_create) for all of its memory, so changing it
+ * later affects only new handles and batches.  Thread-safe. */
+typedef void *(*selinv_alloc_fn)(size_t bytes, void *ctx);
+typedef void (*selinv_free_fn)(void *ptr, void *ctx);
+selinv_status selinv_set_allocator(selinv_alloc_fn alloc, selinv_free_fn dealloc, void *ctx);
 
 /* Symbolic analysis (host only).  Builds the supernode partition, the block
  * row/column sets R_L(K), R_U(K) of Algorithm 1 (from At + At^T or from the
@@ -281,6 +302,16 @@ void selinv_batch_destroy(selinv_batch b);
  * outside the computed set. */
 selinv_status selinv_get(selinv_handle h, int64_t i, int64_t j, double *out);
 
+/* Many entries at once (step 6 for a list of positions; eq. unpermute):
+ * out[k] = A^{-1}(i[k], j[k]) for k < count (host arrays; a complex handle
+ * writes re, im pairs, 2 count doubles).  Every position is checked on the
+ * host first: an index outside [0, n) gives SELINV_E_INVALID_ARG, a position
+ * outside the computed set SELINV_E_NOT_SELECTED, and then nothing is
+ * written.  The values are gathered on the device (one launch) from the last
+ * run's results, after the run's stream is synchronised; count = 0 does
+ * nothing. */
+selinv_status selinv_get_many(selinv_handle h, int64_t count, const int64_t *i, const int64_t *j, double *out);
+
 /* out[p] = A^{-1}(j, i) for the p-th stored entry (i, j) of A (host buffer of
  * nnz(A) doubles).  Tr[B A^{-1}] = sum_p B_p out[p] for any B on A's pattern. */
 selinv_status selinv_get_selected(selinv_handle h, double *out);
@@ -301,6 +332,18 @@ selinv_status selinv_structure(selinv_handle h, int32_t *perm_out, int32_t *xsup
                                int32_t *rl, int64_t *ru_ptr, int32_t *ru, int32_t *level);
 
 selinv_status selinv_query(selinv_handle h, selinv_info *info);
+
+/* Budget of the gather's precomputed source codes, in entries of G (one
+ * 32-bit code per entry and side): while the total of |R_L(K)| |R_U(K)| over
+ * all supernodes stays within it, every supernode gets codes; otherwise only
+ * supernodes whose G_K fits one 64 x 64 tile, in order, while the budget
+ * lasts.  Supernodes without codes gather through the relative-index maps
+ * (Theorem 1: the positions of R_L(K) inside R_L(J) and of R_U(K) inside
+ * R_U(I)), and supernodes of at most 64 columns without codes take the
+ * per-phase launches instead of the fused small-supernode kernel.  entries < 0
+ * restores the default (2^26); 0 turns the codes off.  Only before the first
+ * factor call of the handle (SELINV_E_STATE afterwards). */
+selinv_status selinv_set_gather_code_budget(selinv_handle h, int64_t entries);
 
 /* Host-only consistency check of the analysis: recomputes the source location
  * of every entry of every G_K from the relative-index maps (as the gather
@@ -323,7 +366,7 @@ selinv_status selinv_check_plan(selinv_handle h, int64_t *mismatches);
 selinv_status selinv_set_profiling(selinv_handle h, int32_t on);
 selinv_status selinv_timings(selinv_handle h, double *ms, int32_t count);
 
-/* Work of one level of the last run's sweep (stats: 14 doubles): [0]
+/* Work of one level of the last run's sweep (stats: 19 doubles): [0]
  * supernodes, [1] widest supernode; for the launches of the large supernodes
  * [2] flops of steps 3+5, [3] flops of step 4, [4] entries of G gathered, [5]
  * gather tiles, [6] product tiles of steps 3+5, [7] of step 4, [8] and [9] the
@@ -331,7 +374,21 @@ selinv_status selinv_timings(selinv_handle h, double *ms, int32_t count);
  * small-supernode launch [10] supernodes, [11] flops of steps 3-5, [12]
  * entries of G gathered; [13] 1 when the level's gather tiles run in the
  * step-4 launch of the level above (the parent's step-4 product then writes
- * its diagonal block into the children's G), so that [5] is 0. */
+ * its diagonal block into the children's G), so that [5] is 0.  Algorithmic
+ * HBM bytes (every operand read once, every result written once, e bytes per
+ * element of the run's storage precision, 8 for diagonal blocks; a
+ * materialised G is not counted, the sources it is gathered from are):
+ * [14] of the steps-3+5 launch, e (c_L c_U + 2 s (c_L + c_U)) per supernode;
+ * [15] of the step-4 launch, 2 e s c_U + 16 s^2 per supernode, plus
+ * e c_L c_U for each supernode of the next level whose gather runs in it;
+ * [16] of the standalone gather, e c_L c_U per supernode; [17] of the
+ * small-supernode launch; [18] flops of the largest single step-3/5 product
+ * (2 s c_L c_U) of the level.  level = -1: the prologue, [0]/[1] flops/bytes
+ * of the diagonal-block inversion (with the normalisation and diagonal
+ * initialisation of the supernodes it does whole), [2]/[3] of the
+ * normalisation (in the FP64 form with the diagonal initialisation, which
+ * shares its launch), [4]/[5] of the diagonal initialisation of the mixed
+ * forms; the rest 0. */
 selinv_status selinv_level_stats(selinv_handle h, int32_t level, double *stats);
 
 /* Message of the last failure on handle h; with h == NULL, of the last failed

@@ -19,6 +19,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -29,6 +30,47 @@
 using namespace selinv;
 
 namespace {
+
+// Source of device memory (selinv_set_allocator): hipMalloc / hipFree, or the
+// caller's hook.  Each handle and batch keeps the source in effect when it was
+// created and returns every allocation to it.  Memory handed back to a hook
+// may be given out again at once, so the device is drained before the hook
+// sees a pointer again.
+struct DevAlloc {
+    selinv_alloc_fn alloc = nullptr;
+    selinv_free_fn dealloc = nullptr;
+    void *ctx = nullptr;
+    hipError_t get(void **p, size_t bytes) const {
+        bytes = std::max<size_t>(bytes, 16);
+        if (!alloc) return hipMalloc(p, bytes);
+        *p = alloc(bytes, ctx);
+        if (!*p) return hipErrorOutOfMemory;
+        if ((uintptr_t)*p % 256) {  // the kernels' vector loads assume this alignment
+            (void)hipDeviceSynchronize();
+            dealloc(*p, ctx);
+            *p = nullptr;
+            return hipErrorInvalidValue;
+        }
+        return hipSuccess;
+    }
+    void put(void *p) const {
+        if (!p) return;
+        if (!alloc) {
+            (void)hipFree(p);
+            return;
+        }
+        (void)hipDeviceSynchronize();
+        dealloc(p, ctx);
+    }
+};
+
+std::mutex g_alloc_mu;
+DevAlloc g_alloc;  // the source new handles and batches take
+
+DevAlloc current_alloc() {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    return g_alloc;
+}
 
 struct PrecBufs {
     bool ready = false;
@@ -83,6 +125,15 @@ struct Sweep {
     std::vector<double> lev_flops35, lev_flops4, lev_gather_elems;  // launches of the large supernodes
     std::vector<double> lev_small_flops, lev_small_elems;          // the fused small-supernode launch
     std::vector<int> lev_nsup, lev_maxs;
+    // algorithmic HBM bytes per launch (every operand read once, every result
+    // written once; a materialised G is not counted, its sources are):
+    // steps 3+5, step 4 (with the sources of the next level's gather when that
+    // runs in the same launch), the standalone gather, the small-supernode
+    // launch; and the largest single step-3/5 product of the level (flops)
+    std::vector<double> lev_bytes35, lev_bytes4, lev_bytes_gather, lev_bytes_small, lev_max_prod;
+    // prologue phases (0 inversion, 1 normalisation, 2 diagonal initialisation
+    // of the mixed forms): algorithmic flops and bytes
+    double pro_flops[3] = {0, 0, 0}, pro_bytes[3] = {0, 0, 0};
     // persistent sweep (used instead of the per-level launches when `persistent`)
     bool persistent = false;
     PTask *d_ptasks = nullptr;
@@ -95,24 +146,17 @@ struct Sweep {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     hipStream_t graph_stream = nullptr;
+    DevAlloc al;  // source of the work lists' device memory
     ~Sweep() {
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (graph) (void)hipGraphDestroy(graph);
         if (ev_fork) (void)hipEventDestroy(ev_fork);
         if (ev_join) (void)hipEventDestroy(ev_join);
         if (side) (void)hipStreamDestroy(side);
-        (void)hipFree(d_mats);
-        (void)hipFree(d_tri);
-        (void)hipFree(d_probs);
-        (void)hipFree(d_tiles);
-        (void)hipFree(d_gt);
-        (void)hipFree(d_small);
-        (void)hipFree(d_red);
-        (void)hipFree(d_ws4);
-        (void)hipFree(d_ptasks);
-        (void)hipFree(d_psn);
-        (void)hipFree(d_deps);
-        (void)hipFree(d_cnt);
+        for (void *q : {(void *)d_mats, (void *)d_tri, (void *)d_probs, (void *)d_tiles, (void *)d_gt,
+                        (void *)d_small, (void *)d_red, (void *)d_ws4, (void *)d_ptasks, (void *)d_psn,
+                        (void *)d_deps, (void *)d_cnt})
+            al.put(q);
     }
 };
 
@@ -156,10 +200,11 @@ struct LuPlan {
     double *d_W = nullptr;  // W_K of one level
     int32_t *d_bad = nullptr;
     int64_t *d_emb = nullptr;  // complex handles: source of every entry of the real form
+    DevAlloc al;
     ~LuPlan() {
         for (void *q : {(void *)d_lu, (void *)d_tri, (void *)d_probs, (void *)d_tiles, (void *)d_sc, (void *)d_mat,
                         (void *)d_W, (void *)d_bad, (void *)d_emb})
-            (void)hipFree(q);
+            al.put(q);
     }
 };
 
@@ -171,6 +216,7 @@ inline int mode_of(int prec) {
 }  // namespace
 
 struct selinv_handle_s {
+    DevAlloc al;  // source of all of the handle's device memory
     Plan P;
     std::string err;
     int state = 0;  // 0 analyzed, 1 factored, 2 ran
@@ -205,6 +251,7 @@ struct selinv_handle_s {
     const Sweep *last_sweep = nullptr;  // sweep of the last run (own or a batch's)
     hipStream_t own_stream = nullptr;
     bool profiling = false;
+    bool last_profiled = false;  // the last run recorded its phase events
     int sweep_mode = SWEEP_AUTO;
     Tuning tune[NPREC];
     std::unique_ptr<LuPlan> lu;
@@ -213,6 +260,7 @@ struct selinv_handle_s {
 };
 
 struct selinv_batch_s {
+    DevAlloc al;
     std::vector<selinv_handle> hs;
     std::unique_ptr<Sweep> sweep[NPREC];
     std::string err;
@@ -233,27 +281,27 @@ selinv_status dev_fail(std::string &err, hipError_t e, const char *what) {
     } while (0)
 
 template <class T>
-hipError_t upload(T **dptr, const std::vector<T> &v) {
+hipError_t upload(const DevAlloc &al, T **dptr, const std::vector<T> &v) {
     size_t bytes = std::max<size_t>(1, v.size()) * sizeof(T);
-    hipError_t e = hipMalloc((void **)dptr, bytes);
+    hipError_t e = al.get((void **)dptr, bytes);
     if (e != hipSuccess) return e;
     if (!v.empty()) e = hipMemcpy(*dptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
     return e;
 }
 
-hipError_t alloc_bytes(void **p, size_t bytes) { return hipMalloc(p, std::max<size_t>(bytes, 16)); }
+hipError_t alloc_bytes(const DevAlloc &al, void **p, size_t bytes) { return al.get(p, bytes); }
 
 selinv_status ensure_prec(selinv_handle h, int prec) {
     PrecBufs &b = h->pb[prec];
     if (b.ready) return SELINV_OK;
     const Plan &P = h->P;
     const size_t e = elem_bytes(prec);
-    HIPCHK(h->err, alloc_bytes((void **)&b.Zd, P.tot_d * 8), "alloc Zd");
-    HIPCHK(h->err, alloc_bytes(&b.ZL, P.tot_l * e), "alloc ZL");
-    HIPCHK(h->err, alloc_bytes(&b.ZU, P.tot_u * e), "alloc ZU");
-    HIPCHK(h->err, alloc_bytes(&b.Lh, P.tot_l * e), "alloc Lh");
-    HIPCHK(h->err, alloc_bytes(&b.Uh, P.tot_u * e), "alloc Uh");
-    HIPCHK(h->err, alloc_bytes(&b.G, h->g_elems * e), "alloc G");
+    HIPCHK(h->err, alloc_bytes(h->al, (void **)&b.Zd, P.tot_d * 8), "alloc Zd");
+    HIPCHK(h->err, alloc_bytes(h->al, &b.ZL, P.tot_l * e), "alloc ZL");
+    HIPCHK(h->err, alloc_bytes(h->al, &b.ZU, P.tot_u * e), "alloc ZU");
+    HIPCHK(h->err, alloc_bytes(h->al, &b.Lh, P.tot_l * e), "alloc Lh");
+    HIPCHK(h->err, alloc_bytes(h->al, &b.Uh, P.tot_u * e), "alloc Uh");
+    HIPCHK(h->err, alloc_bytes(h->al, &b.G, h->g_elems * e), "alloc G");
     b.ready = true;
     return SELINV_OK;
 }
@@ -397,13 +445,14 @@ GatherTile gather_tile_of(selinv_handle h, int32_t mi, int32_t K, int a0, int b0
 inline bool fused_prologue(const SnRec &r) { return r.s <= 64 && r.cl <= 64 && r.cu <= 64; }
 
 // Build the work lists of one sweep over a set of factored handles.
-selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, int sweep_mode, std::unique_ptr<Sweep> &out,
-                          std::string &err, const Tuning *tn = nullptr) {
+selinv_status build_sweep(std::vector<selinv_handle> &hs, const DevAlloc &al, int prec, int sweep_mode,
+                          std::unique_ptr<Sweep> &out, std::string &err, const Tuning *tn = nullptr) {
     if (tn && !tn->set) tn = nullptr;
     auto t35_of = [&](int d) { return tn && d < (int)tn->t35.size() ? tn->t35[d] : 0; };
     auto t4_of = [&](int d) { return tn && d < (int)tn->t4.size() ? tn->t4[d] : 0; };
     if (tn && sweep_mode == SWEEP_AUTO && tn->sweep != SWEEP_AUTO) sweep_mode = tn->sweep;
     std::unique_ptr<Sweep> S(new Sweep());
+    S->al = al;
     S->prec = prec;
     const int e = elem_bytes(prec);
     std::vector<MatDev> mats;
@@ -493,6 +542,21 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, int sweep_mo
             for (int32_t K = 0; K < h->P.ns; K++) {
                 if (part[mi][K] != pp) continue;
                 const SnRec &r = h->sn[K];
+                {
+                    const double s3 = (double)r.s * r.s * r.s, s2 = (double)r.s * r.s, pc = (double)r.s * (r.cl + r.cu);
+                    S->pro_flops[0] += 2.0 * s3 / 3;  // both triangular inverses
+                    S->pro_bytes[0] += 16.0 * s2;
+                    if (fused_prologue(r)) {  // normalisation and diagonal initialisation in the same workgroup
+                        S->pro_flops[0] += (double)r.s * pc + 2.0 * s3 / 3;
+                        S->pro_bytes[0] += 8.0 * pc + e * pc + 8.0 * s2;
+                    } else {
+                        S->pro_flops[1] += (double)r.s * pc;
+                        S->pro_bytes[1] += 8.0 * pc + 8.0 * s2 + e * pc;
+                        const int ph = prec == SELINV_FP64 ? 1 : 2;  // FP64: one launch for both
+                        S->pro_flops[ph] += 2.0 * s3 / 3;
+                        S->pro_bytes[ph] += 16.0 * s2;
+                    }
+                }
                 for (int j0 = 0; j0 < r.s; j0 += 64) {
                     TriItem t{};
                     t.D = h->d_diag + r.off_d;
@@ -629,6 +693,11 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, int sweep_mo
     S->lev_small_elems.assign(depth, 0);
     S->lev_nsup.assign(depth, 0);
     S->lev_maxs.assign(depth, 0);
+    S->lev_bytes35.assign(depth, 0);
+    S->lev_bytes4.assign(depth, 0);
+    S->lev_bytes_gather.assign(depth, 0);
+    S->lev_bytes_small.assign(depth, 0);
+    S->lev_max_prod.assign(depth, 0);
     // A supernode whose gather and three products are single 64x64 tiles is
     // handled whole by one workgroup of the fused small-supernode kernel, on
     // the levels where every supernode is of that kind: the fused launch then
@@ -696,7 +765,7 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, int sweep_mo
     }
     std::vector<int> red_of(nsn, -1);  // reduction item of a split supernode
     if (ws_elems) {
-        HIPCHK(err, alloc_bytes((void **)&S->d_ws4, ws_elems * 8), "alloc split-K workspace");
+        HIPCHK(err, alloc_bytes(S->al, (void **)&S->d_ws4, ws_elems * 8), "alloc split-K workspace");
         X.add(S->d_ws4, ws_elems * 8);
     }
     std::vector<ReduceItem> reds;
@@ -751,6 +820,9 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, int sweep_mo
                                        ? (int)probs.size() - 1
                                        : -1;
                     (pass == 0 ? S->lev_flops35[d] : S->lev_small_flops[d]) += 4.0 * r.s * (double)r.cl * r.cu;
+                    (pass == 0 ? S->lev_bytes35[d] : S->lev_bytes_small[d]) +=
+                        e * ((double)r.cl * r.cu + 2.0 * r.s * ((double)r.cl + r.cu));
+                    if (pass == 0) S->lev_max_prod[d] = std::max(S->lev_max_prod[d], 2.0 * r.s * (double)r.cl * r.cu);
                 }
             }
             if (pass == 0) emit_launch(probs, first, tiles, S->g35[d], mode_of(prec) == CMP_BF16X3, t35_of(d));
@@ -776,6 +848,10 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, int sweep_mo
                                        ? (int)probs.size() - 1
                                        : -1;
                     (pass == 0 ? S->lev_flops4[d] : S->lev_small_flops[d]) += 2.0 * r.s * (double)r.s * r.cu;
+                    if (pass == 0)
+                        S->lev_bytes4[d] += 2.0 * e * r.s * (double)r.cu + 16.0 * r.s * (double)r.s;
+                    else
+                        S->lev_bytes_small[d] += 16.0 * r.s * (double)r.s;
                     if (pass != 0 || prob_g4[gid] < 0) continue;
                     if (parts4[gid] < 2) {
                         lst.push_back(prob_g4[gid]);
@@ -848,6 +924,13 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, int sweep_mo
             }
         }
         S->small[d].count = (int)(smalls.size() - S->small[d].off);
+    }
+    for (int d = 0; d < depth; d++) {
+        const double src = e * S->lev_gather_elems[d];
+        if (d > 0 && S->fused[d])
+            S->lev_bytes4[d - 1] += src;
+        else
+            S->lev_bytes_gather[d] += src;
     }
     // persistent task queue: level by level from the root; per level all
     // gather tiles, then the step-3 tiles, the step-5 tiles, the step-4 tiles
@@ -943,10 +1026,10 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, int sweep_mo
             S->ntasks = (int32_t)pt.size();
             S->ncnt = 3 * (int64_t)nsn;
             std::vector<int32_t> zero(S->ncnt + 2, 0);
-            HIPCHK(err, upload(&S->d_ptasks, pt), "upload tasks");
-            HIPCHK(err, upload(&S->d_psn, psn), "upload task deps");
-            HIPCHK(err, upload(&S->d_deps, deps), "upload task deps");
-            HIPCHK(err, upload(&S->d_cnt, zero), "upload counters");
+            HIPCHK(err, upload(S->al, &S->d_ptasks, pt), "upload tasks");
+            HIPCHK(err, upload(S->al, &S->d_psn, psn), "upload task deps");
+            HIPCHK(err, upload(S->al, &S->d_deps, deps), "upload task deps");
+            HIPCHK(err, upload(S->al, &S->d_cnt, zero), "upload counters");
             S->grid = persist_grid(mode_of(prec));
             if (S->grid <= 0) {
                 err = "could not size the persistent grid";
@@ -980,13 +1063,13 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, int prec, int sweep_mo
         err = "internal error: " + std::to_string(X.violations) + " work-list entries outside their buffers";
         return SELINV_E_INVALID_ARG;
     }
-    HIPCHK(err, upload(&S->d_mats, mats), "upload mats");
-    HIPCHK(err, upload(&S->d_tri, tri), "upload tri");
-    HIPCHK(err, upload(&S->d_probs, probs), "upload probs");
-    HIPCHK(err, upload(&S->d_tiles, tiles), "upload tiles");
-    HIPCHK(err, upload(&S->d_gt, gts), "upload gather tiles");
-    HIPCHK(err, upload(&S->d_small, smalls), "upload small supernodes");
-    HIPCHK(err, upload(&S->d_red, reds), "upload split-K reductions");
+    HIPCHK(err, upload(S->al, &S->d_mats, mats), "upload mats");
+    HIPCHK(err, upload(S->al, &S->d_tri, tri), "upload tri");
+    HIPCHK(err, upload(S->al, &S->d_probs, probs), "upload probs");
+    HIPCHK(err, upload(S->al, &S->d_tiles, tiles), "upload tiles");
+    HIPCHK(err, upload(S->al, &S->d_gt, gts), "upload gather tiles");
+    HIPCHK(err, upload(S->al, &S->d_small, smalls), "upload small supernodes");
+    HIPCHK(err, upload(S->al, &S->d_red, reds), "upload split-K reductions");
     out = std::move(S);
     return SELINV_OK;
 }
@@ -1154,7 +1237,7 @@ selinv_status complex_embedding(int64_t n, const int64_t *colptr, const int32_t 
 constexpr int64_t kCodeBudget = int64_t(1) << 26;
 
 void build_gather_codes(const Plan &P, std::vector<SnRec> &sn, std::vector<uint32_t> &gcL,
-                        std::vector<uint32_t> &gcU) {
+                        std::vector<uint32_t> &gcU, int64_t budget) {
     gcL.clear();
     gcU.clear();
     for (SnRec &r : sn) r.c_off = -1;
@@ -1162,11 +1245,11 @@ void build_gather_codes(const Plan &P, std::vector<SnRec> &sn, std::vector<uint3
     if (P.tot_d > lim || P.tot_l > lim || P.tot_u > lim) return;
     int64_t total = 0;
     for (int32_t K = 0; K < P.ns; K++) total += P.cl(K) * P.cu(K);
-    const bool all = total <= kCodeBudget;
+    const bool all = total <= budget;
     int64_t used = 0;
     for (int32_t K = 0; K < P.ns; K++) {
         const int64_t cl = P.cl(K), cu = P.cu(K);
-        if (cl == 0 || cu == 0 || (!all && (cl > 64 || cu > 64)) || used + cl * cu > kCodeBudget) continue;
+        if (cl == 0 || cu == 0 || (!all && (cl > 64 || cu > 64)) || used + cl * cu > budget) continue;
         sn[K].c_off = used;
         used += cl * cu;
     }
@@ -1291,6 +1374,7 @@ selinv_status selinv_analyze(int64_t n, const int64_t *colptr, const int32_t *ro
     *out = nullptr;
     selinv_handle h = new (std::nothrow) selinv_handle_s();
     if (!h) return SELINV_E_NOMEM;
+    h->al = current_alloc();
     const int32_t symbolic = opts ? opts->symbolic : SELINV_SYMBOLIC_SYMMETRIZED;
     if (symbolic != SELINV_SYMBOLIC_SYMMETRIZED && symbolic != SELINV_SYMBOLIC_EXACT) {
         g_analyze_err = "opts->symbolic must be SELINV_SYMBOLIC_SYMMETRIZED or SELINV_SYMBOLIC_EXACT";
@@ -1359,7 +1443,7 @@ selinv_status selinv_analyze(int64_t n, const int64_t *colptr, const int32_t *ro
     }
     try {
         build_push_maps(P, h->kids_ptr, h->kids, h->push_off, h->push_pos);
-        build_gather_codes(P, h->sn, h->gcL, h->gcU);
+        build_gather_codes(P, h->sn, h->gcL, h->gcU, kCodeBudget);
     } catch (const std::bad_alloc &) {
         g_analyze_err = "host allocation failed in analyze";
         delete h;
@@ -1420,29 +1504,29 @@ static selinv_status ensure_device(selinv_handle h) {
     h->device = dev;
     const Plan &P = h->P;
     if (!h->d_diag) {
-        HIPCHK(h->err, alloc_bytes((void **)&h->d_diag, P.tot_d * 8), "alloc diag");
-        HIPCHK(h->err, alloc_bytes((void **)&h->d_lpan, P.tot_l * 8), "alloc lpan");
-        HIPCHK(h->err, alloc_bytes((void **)&h->d_upan, P.tot_u * 8), "alloc upan");
-        HIPCHK(h->err, alloc_bytes((void **)&h->d_Linv, P.tot_d * 8), "alloc Linv");
-        HIPCHK(h->err, alloc_bytes((void **)&h->d_Uinv, P.tot_d * 8), "alloc Uinv");
-        HIPCHK(h->err, alloc_bytes((void **)&h->d_tl, P.tot_d * 8), "alloc tri scratch");
-        HIPCHK(h->err, alloc_bytes((void **)&h->d_tu, P.tot_d * 8), "alloc tri scratch");
-        HIPCHK(h->err, upload(&h->d_sn, h->sn), "upload sn");
-        HIPCHK(h->err, upload(&h->d_supof, P.supof), "upload supof");
-        HIPCHK(h->err, upload(&h->d_rl, P.rl), "upload rl");
-        HIPCHK(h->err, upload(&h->d_ru, P.ru), "upload ru");
-        HIPCHK(h->err, upload(&h->d_mapL, P.mapL), "upload mapL");
-        HIPCHK(h->err, upload(&h->d_mapU, P.mapU), "upload mapU");
-        HIPCHK(h->err, upload(&h->d_lcol, P.l_coloff), "upload l_coloff");
-        HIPCHK(h->err, upload(&h->d_urow, P.u_rowoff), "upload u_rowoff");
-        HIPCHK(h->err, upload(&h->d_aloc, P.a_loc), "upload a_loc");
-        if (h->cplx) HIPCHK(h->err, upload(&h->d_aloc_c, h->aloc_c), "upload complex locations");
-        HIPCHK(h->err, upload(&h->d_kids_ptr, h->kids_ptr), "upload children");
-        HIPCHK(h->err, upload(&h->d_kids, h->kids), "upload children");
-        HIPCHK(h->err, upload(&h->d_push_off, h->push_off), "upload push maps");
-        HIPCHK(h->err, upload(&h->d_push_pos, h->push_pos), "upload push maps");
-        HIPCHK(h->err, upload(&h->d_gcL, h->gcL), "upload gather codes");
-        HIPCHK(h->err, upload(&h->d_gcU, h->gcU), "upload gather codes");
+        HIPCHK(h->err, alloc_bytes(h->al, (void **)&h->d_diag, P.tot_d * 8), "alloc diag");
+        HIPCHK(h->err, alloc_bytes(h->al, (void **)&h->d_lpan, P.tot_l * 8), "alloc lpan");
+        HIPCHK(h->err, alloc_bytes(h->al, (void **)&h->d_upan, P.tot_u * 8), "alloc upan");
+        HIPCHK(h->err, alloc_bytes(h->al, (void **)&h->d_Linv, P.tot_d * 8), "alloc Linv");
+        HIPCHK(h->err, alloc_bytes(h->al, (void **)&h->d_Uinv, P.tot_d * 8), "alloc Uinv");
+        HIPCHK(h->err, alloc_bytes(h->al, (void **)&h->d_tl, P.tot_d * 8), "alloc tri scratch");
+        HIPCHK(h->err, alloc_bytes(h->al, (void **)&h->d_tu, P.tot_d * 8), "alloc tri scratch");
+        HIPCHK(h->err, upload(h->al, &h->d_sn, h->sn), "upload sn");
+        HIPCHK(h->err, upload(h->al, &h->d_supof, P.supof), "upload supof");
+        HIPCHK(h->err, upload(h->al, &h->d_rl, P.rl), "upload rl");
+        HIPCHK(h->err, upload(h->al, &h->d_ru, P.ru), "upload ru");
+        HIPCHK(h->err, upload(h->al, &h->d_mapL, P.mapL), "upload mapL");
+        HIPCHK(h->err, upload(h->al, &h->d_mapU, P.mapU), "upload mapU");
+        HIPCHK(h->err, upload(h->al, &h->d_lcol, P.l_coloff), "upload l_coloff");
+        HIPCHK(h->err, upload(h->al, &h->d_urow, P.u_rowoff), "upload u_rowoff");
+        HIPCHK(h->err, upload(h->al, &h->d_aloc, P.a_loc), "upload a_loc");
+        if (h->cplx) HIPCHK(h->err, upload(h->al, &h->d_aloc_c, h->aloc_c), "upload complex locations");
+        HIPCHK(h->err, upload(h->al, &h->d_kids_ptr, h->kids_ptr), "upload children");
+        HIPCHK(h->err, upload(h->al, &h->d_kids, h->kids), "upload children");
+        HIPCHK(h->err, upload(h->al, &h->d_push_off, h->push_off), "upload push maps");
+        HIPCHK(h->err, upload(h->al, &h->d_push_pos, h->push_pos), "upload push maps");
+        HIPCHK(h->err, upload(h->al, &h->d_gcL, h->gcL), "upload gather codes");
+        HIPCHK(h->err, upload(h->al, &h->d_gcU, h->gcU), "upload gather codes");
     }
     return SELINV_OK;
 }
@@ -1455,6 +1539,7 @@ static selinv_status ensure_device(selinv_handle h) {
 static selinv_status build_lu(selinv_handle h) {
     const Plan &P = h->P;
     auto L = std::make_unique<LuPlan>();
+    L->al = h->al;
     std::vector<LuTile> lus;
     std::vector<TriItem> tris;
     std::vector<GemmProb> probs;
@@ -1472,7 +1557,7 @@ static selinv_status build_lu(selinv_handle h) {
         for (int32_t K : P.levels[lev]) w += (int64_t)h->sn[K].cl * h->sn[K].cu;
         w_max = std::max(w_max, w);
     }
-    HIPCHK(h->err, alloc_bytes((void **)&L->d_W, w_max * 8), "alloc Schur complement buffer");
+    HIPCHK(h->err, alloc_bytes(L->al, (void **)&L->d_W, w_max * 8), "alloc Schur complement buffer");
     double *D0 = h->d_diag, *L0 = h->d_lpan, *U0 = h->d_upan, *W0 = L->d_W;
     double *Li0 = h->d_Linv, *Ui0 = h->d_Uinv;  // the tile inverses (the run recomputes them)
     // C = alpha op(A) op(B) + beta C
@@ -1616,11 +1701,11 @@ static selinv_status build_lu(selinv_handle h) {
         h->err = "device LU: work list outside the factor storage (inconsistent analysis)";
         return SELINV_E_STATE;
     }
-    HIPCHK(h->err, upload(&L->d_lu, lus), "upload LU tiles");
-    HIPCHK(h->err, upload(&L->d_tri, tris), "upload tile inverses");
-    HIPCHK(h->err, upload(&L->d_probs, probs), "upload LU products");
-    HIPCHK(h->err, upload(&L->d_tiles, tiles), "upload LU product tiles");
-    HIPCHK(h->err, upload(&L->d_sc, scs), "upload scatter tiles");
+    HIPCHK(h->err, upload(L->al, &L->d_lu, lus), "upload LU tiles");
+    HIPCHK(h->err, upload(L->al, &L->d_tri, tris), "upload tile inverses");
+    HIPCHK(h->err, upload(L->al, &L->d_probs, probs), "upload LU products");
+    HIPCHK(h->err, upload(L->al, &L->d_tiles, tiles), "upload LU product tiles");
+    HIPCHK(h->err, upload(L->al, &L->d_sc, scs), "upload scatter tiles");
     MatDev m{};
     m.sn = h->d_sn;
     m.supof = h->d_supof;
@@ -1630,8 +1715,8 @@ static selinv_status build_lu(selinv_handle h) {
     m.u_rowoff = h->d_urow;
     m.mapL = h->d_mapL;
     m.mapU = h->d_mapU;
-    HIPCHK(h->err, upload(&L->d_mat, std::vector<MatDev>{m}), "upload LU matrix record");
-    HIPCHK(h->err, alloc_bytes((void **)&L->d_bad, sizeof(int32_t)), "alloc pivot flag");
+    HIPCHK(h->err, upload(L->al, &L->d_mat, std::vector<MatDev>{m}), "upload LU matrix record");
+    HIPCHK(h->err, alloc_bytes(L->al, (void **)&L->d_bad, sizeof(int32_t)), "alloc pivot flag");
     if (h->cplx) {
         // entry e of the real form: +-(Re or Im) of complex entry k, as in selinv_factor
         std::vector<int64_t> emb(P.nnz_a, 0);
@@ -1644,7 +1729,7 @@ static selinv_status build_lu(selinv_handle h) {
                 emb[e1] = ((2 * k + 1) << 1) | 1;
                 emb[e1 + 1] = (2 * k) << 1;
             }
-        HIPCHK(h->err, upload(&L->d_emb, emb), "upload complex entry map");
+        HIPCHK(h->err, upload(L->al, &L->d_emb, emb), "upload complex entry map");
     }
     h->lu = std::move(L);
     return SELINV_OK;
@@ -1731,7 +1816,7 @@ static selinv_status check_run(selinv_handle h, int prec) {
 static selinv_status ensure_sweep(selinv_handle h, int prec) {
     if (h->sweep[prec]) return SELINV_OK;
     std::vector<selinv_handle> one{h};
-    return build_sweep(one, prec, h->sweep_mode, h->sweep[prec], h->err, &h->tune[prec]);
+    return build_sweep(one, h->al, prec, h->sweep_mode, h->sweep[prec], h->err, &h->tune[prec]);
 }
 
 selinv_status selinv_run(selinv_handle h, selinv_precision prec, void *stream) {
@@ -1755,6 +1840,7 @@ selinv_status selinv_run(selinv_handle h, selinv_precision prec, void *stream) {
     h->last_sweep = &S;
     h->last_prec = prec;
     h->last_stream = s;
+    h->last_profiled = ev != nullptr;
     h->state = 2;
     return SELINV_OK;
 }
@@ -1783,6 +1869,7 @@ selinv_status selinv_run_graph(selinv_handle h, selinv_precision prec, void *str
     h->last_sweep = &S;
     h->last_prec = prec;
     h->last_stream = s;
+    h->last_profiled = false;
     h->state = 2;
     return SELINV_OK;
 }
@@ -1825,8 +1912,12 @@ selinv_status selinv_set_profiling(selinv_handle h, int32_t on) {
 
 selinv_status selinv_timings(selinv_handle h, double *ms, int32_t count) {
     if (!h || !ms) return SELINV_E_INVALID_ARG;
-    if (h->state < 2 || h->last_prec < 0 || !h->profiling) return SELINV_E_STATE;
-    const Sweep &S = *h->sweep[h->last_prec];
+    // the events belong to the last run only if it was this handle's own
+    // profiled run and its sweep still exists
+    if (h->state < 2 || h->last_prec < 0 || !h->last_profiled || !h->last_sweep ||
+        h->last_sweep != h->sweep[h->last_prec].get())
+        return SELINV_E_STATE;
+    const Sweep &S = *h->last_sweep;
     size_t nev = 4 + 4 * S.gat.size();
     if (h->events.size() < nev) return SELINV_E_STATE;
     HIPCHK(h->err, hipEventSynchronize(h->events[nev - 1]), "event sync");
@@ -2107,8 +2198,17 @@ selinv_status selinv_set_tuning(selinv_handle h, selinv_precision prec, const in
 }
 
 selinv_status selinv_level_stats(selinv_handle h, int32_t level, double *stats) {
-    if (!h || !stats || h->last_prec < 0) return SELINV_E_INVALID_ARG;
-    const Sweep &S = *h->sweep[h->last_prec];
+    if (!h || !stats) return SELINV_E_INVALID_ARG;
+    if (!h->last_sweep) return SELINV_E_STATE;  // no run yet, or its sweep was dropped
+    const Sweep &S = *h->last_sweep;
+    if (level == -1) {
+        for (int k = 0; k < 19; k++) stats[k] = 0;
+        for (int k = 0; k < 3; k++) {
+            stats[2 * k] = S.pro_flops[k];
+            stats[2 * k + 1] = S.pro_bytes[k];
+        }
+        return SELINV_OK;
+    }
     if (level < 0 || level >= (int32_t)S.gat.size()) return SELINV_E_INVALID_ARG;
     stats[0] = S.lev_nsup[level];
     stats[1] = S.lev_maxs[level];
@@ -2124,6 +2224,11 @@ selinv_status selinv_level_stats(selinv_handle h, int32_t level, double *stats) 
     stats[11] = S.lev_small_flops[level];
     stats[12] = S.lev_small_elems[level];
     stats[13] = S.fused[level];
+    stats[14] = S.lev_bytes35[level];
+    stats[15] = S.lev_bytes4[level];
+    stats[16] = S.lev_bytes_gather[level];
+    stats[17] = S.lev_bytes_small[level];
+    stats[18] = S.lev_max_prod[level];
     return SELINV_OK;
 }
 
@@ -2184,6 +2289,80 @@ static selinv_status get_real(selinv_handle h, int64_t i, int64_t j, double *out
     return SELINV_OK;
 }
 
+selinv_status selinv_set_allocator(selinv_alloc_fn alloc, selinv_free_fn dealloc, void *ctx) {
+    if ((alloc == nullptr) != (dealloc == nullptr)) return SELINV_E_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    g_alloc.alloc = alloc;
+    g_alloc.dealloc = dealloc;
+    g_alloc.ctx = alloc ? ctx : nullptr;
+    return SELINV_OK;
+}
+
+selinv_status selinv_get_many(selinv_handle h, int64_t count, const int64_t *i, const int64_t *j, double *out) {
+    if (!h || count < 0 || (count > 0 && (!i || !j || !out))) return SELINV_E_INVALID_ARG;
+    if (h->state < 0) return SELINV_E_STATE;
+    if (count == 0) return SELINV_OK;
+    const Plan &P = h->P;
+    const int64_t nn = h->cplx ? h->n_c : P.n;
+    const int64_t per = h->cplx ? 2 : 1;
+    std::vector<int64_t> loc;
+    try {
+        loc.resize(count * per);
+    } catch (const std::bad_alloc &) {
+        h->err = "host allocation failed in get_many";
+        return SELINV_E_NOMEM;
+    }
+    for (int64_t k = 0; k < count; k++) {
+        if (i[k] < 0 || j[k] < 0 || i[k] >= nn || j[k] >= nn) {
+            h->err = "get_many: position " + std::to_string(k) + " outside the matrix";
+            return SELINV_E_INVALID_ARG;
+        }
+        // A^{-1}(i, j) = At^{-T}(q[j], q[i]); complex: the real form's (2i, 2j) and (2i + 1, 2j)
+        for (int64_t c = 0; c < per; c++) {
+            const int64_t ii = h->cplx ? 2 * i[k] + c : i[k], jj = h->cplx ? 2 * j[k] : j[k];
+            const int64_t l = P.locate(P.q[jj], P.q[ii]);
+            if (l < 0) {
+                h->err = "get_many: position " + std::to_string(k) + " outside the computed set";
+                return SELINV_E_NOT_SELECTED;
+            }
+            loc[k * per + c] = l;
+        }
+    }
+    selinv_status st = sync_last(h);
+    if (st) return st;
+    const int64_t m = count * per;
+    int64_t *d_loc = nullptr;
+    double *d_out = nullptr;
+    hipError_t e = upload(h->al, &d_loc, loc);
+    if (e == hipSuccess) e = alloc_bytes(h->al, (void **)&d_out, m * 8);
+    if (e == hipSuccess) {
+        const PrecBufs &b = h->pb[h->last_prec];
+        ExtractArgs a{d_loc, b.Zd, b.ZL, b.ZU, d_out, m};
+        e = launch_extract(h->last_prec == SELINV_FP64, a, h->last_stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(h->last_stream);
+    if (e == hipSuccess) e = hipMemcpy(out, d_out, m * 8, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) st = dev_fail(h->err, e, "get_many");
+    h->al.put(d_loc);
+    h->al.put(d_out);
+    return st;
+}
+
+selinv_status selinv_set_gather_code_budget(selinv_handle h, int64_t entries) {
+    if (!h) return SELINV_E_INVALID_ARG;
+    if (h->d_diag) {
+        h->err = "the gather code budget must be set before the first factor call";
+        return SELINV_E_STATE;
+    }
+    try {
+        build_gather_codes(h->P, h->sn, h->gcL, h->gcU, entries < 0 ? kCodeBudget : entries);
+    } catch (const std::bad_alloc &) {
+        h->err = "host allocation failed in set_gather_code_budget";
+        return SELINV_E_NOMEM;
+    }
+    return SELINV_OK;
+}
+
 selinv_status selinv_get_selected_device(selinv_handle h, double *out, void *stream) {
     if (!h || !out) return SELINV_E_INVALID_ARG;
     if (h->state < 2 || h->last_prec < 0) return SELINV_E_STATE;
@@ -2200,14 +2379,14 @@ selinv_status selinv_get_selected(selinv_handle h, double *out) {
     if (st) return st;
     double *d = nullptr;
     const int64_t cnt = h->cplx ? 2 * h->nnz_c : h->P.nnz_a;
-    HIPCHK(h->err, alloc_bytes((void **)&d, cnt * 8), "alloc extract");
+    HIPCHK(h->err, alloc_bytes(h->al, (void **)&d, cnt * 8), "alloc extract");
     st = selinv_get_selected_device(h, d, h->last_stream);
     if (!st) {
         hipError_t e = hipStreamSynchronize(h->last_stream);
         if (e == hipSuccess) e = hipMemcpy(out, d, cnt * 8, hipMemcpyDeviceToHost);
         if (e != hipSuccess) st = dev_fail(h->err, e, "extract copy");
     }
-    (void)hipFree(d);
+    h->al.put(d);
     return st;
 }
 
@@ -2369,12 +2548,7 @@ void selinv_destroy(selinv_handle h) {
     for (int p = 0; p < NPREC; p++) {
         h->sweep[p].reset();
         PrecBufs &b = h->pb[p];
-        (void)hipFree(b.Zd);
-        (void)hipFree(b.ZL);
-        (void)hipFree(b.ZU);
-        (void)hipFree(b.Lh);
-        (void)hipFree(b.Uh);
-        (void)hipFree(b.G);
+        for (void *q : {(void *)b.Zd, b.ZL, b.ZU, b.Lh, b.Uh, b.G}) h->al.put(q);
     }
     h->lu.reset();
     for (void *q : {(void *)h->d_diag, (void *)h->d_lpan, (void *)h->d_upan, (void *)h->d_Linv, (void *)h->d_Uinv,
@@ -2382,7 +2556,7 @@ void selinv_destroy(selinv_handle h) {
                     (void *)h->d_sn, (void *)h->d_supof, (void *)h->d_rl, (void *)h->d_ru, (void *)h->d_mapL,
                     (void *)h->d_mapU, (void *)h->d_lcol, (void *)h->d_urow, (void *)h->d_aloc, (void *)h->d_aloc_c,
                     (void *)h->d_kids_ptr, (void *)h->d_kids, (void *)h->d_push_off, (void *)h->d_push_pos, (void *)h->d_gcL, (void *)h->d_gcU})
-        (void)hipFree(q);
+        h->al.put(q);
     for (auto e : h->events) (void)hipEventDestroy(e);
     if (h->own_stream) (void)hipStreamDestroy(h->own_stream);
     delete h;
@@ -2395,6 +2569,7 @@ selinv_status selinv_batch_create(selinv_handle *hs, int32_t count, selinv_batch
         if (!hs[i] || hs[i]->state < 1) return SELINV_E_STATE;
     selinv_batch b = new (std::nothrow) selinv_batch_s();
     if (!b) return SELINV_E_NOMEM;
+    b->al = current_alloc();
     b->hs.assign(hs, hs + count);
     *out = b;
     return SELINV_OK;
@@ -2407,7 +2582,7 @@ selinv_status selinv_batch_run(selinv_batch b, selinv_precision prec, void *stre
         if (st) return st;
     }
     if (!b->sweep[prec]) {
-        selinv_status st = build_sweep(b->hs, prec, b->sweep_mode, b->sweep[prec], b->err);
+        selinv_status st = build_sweep(b->hs, b->al, prec, b->sweep_mode, b->sweep[prec], b->err);
         if (st) return st;
     }
     hipError_t e = launch_sweep(*b->sweep[prec], (hipStream_t)stream, nullptr);
@@ -2416,6 +2591,7 @@ selinv_status selinv_batch_run(selinv_batch b, selinv_precision prec, void *stre
         h->last_prec = prec;
         h->last_stream = (hipStream_t)stream;
         h->last_sweep = b->sweep[prec].get();
+        h->last_profiled = false;
         h->state = 2;
     }
     return SELINV_OK;

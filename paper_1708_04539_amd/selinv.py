@@ -31,7 +31,7 @@ EXPORTED = ["selinv_analyze", "selinv_factor", "selinv_factor_device", "selinv_r
             "selinv_set_profiling", "selinv_timings", "selinv_level_stats", "selinv_last_error",
             "selinv_status_string", "selinv_destroy", "selinv_check_plan", "selinv_set_sweep_mode",
             "selinv_sweep_is_persistent", "selinv_batch_set_sweep_mode", "selinv_tune", "selinv_get_tuning",
-            "selinv_set_tuning"]
+            "selinv_set_tuning", "selinv_set_allocator", "selinv_get_many", "selinv_set_gather_code_budget"]
 
 
 class SelinvError(RuntimeError):
@@ -60,6 +60,11 @@ class Opts(C.Structure):
 
 # analysis forms: pattern of At + At^T (R_L = R_U), or the exact pattern of L and U
 SYMBOLIC = {"symmetrized": 0, "exact": 1}
+
+
+# device-memory hooks of selinv_set_allocator: (bytes, ctx) -> pointer, (pointer, ctx) -> None
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
 
 def _load():
@@ -96,6 +101,9 @@ def _load():
         "selinv_tune": ([vp, C.c_int, i32, vp, P(dbl), P(dbl)], C.c_int),
         "selinv_get_tuning": ([vp, C.c_int, P(i32), i32, P(i32)], C.c_int),
         "selinv_set_tuning": ([vp, C.c_int, P(i32), i32], C.c_int),
+        "selinv_set_allocator": ([ALLOC_FN, FREE_FN, vp], C.c_int),
+        "selinv_get_many": ([vp, i64, P(i64), P(i64), P(dbl)], C.c_int),
+        "selinv_set_gather_code_budget": ([vp, i64], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -109,6 +117,44 @@ _lib = _load()
 
 def lib():
     return _lib
+
+
+def _torch_alloc(nbytes, ctx):
+    try:
+        return torch.cuda.caching_allocator_alloc(int(nbytes), torch.cuda.current_device())
+    except Exception:  # out of memory (or interpreter shutdown): the library reports NOMEM
+        return None
+
+
+def _torch_free(ptr, ctx):
+    try:
+        torch.cuda.caching_allocator_delete(ptr)
+    except Exception:
+        pass
+
+
+_hooks = {"torch": (ALLOC_FN(_torch_alloc), FREE_FN(_torch_free)),
+          "hip": (ALLOC_FN(), FREE_FN())}  # NULL hooks: hipMalloc / hipFree
+_user_hooks = []  # keeps caller-supplied hooks alive
+
+
+def set_allocator(kind="torch", alloc=None, free=None):
+    """Source of the device memory of handles and batches created from now on:
+    "torch" (torch's caching allocator, the default), "hip" (hipMalloc/hipFree),
+    or "custom" with Python callables alloc(nbytes) -> int pointer or None and
+    free(pointer)."""
+    if kind == "custom":
+        a = ALLOC_FN(lambda nb, ctx: alloc(int(nb)))
+        f = FREE_FN(lambda ptr, ctx: free(ptr))
+        _user_hooks.append((a, f))
+    else:
+        a, f = _hooks[kind]
+    rc = _lib.selinv_set_allocator(a, f, None)
+    if rc:
+        raise SelinvError(rc, "set_allocator")
+
+
+set_allocator("torch")
 
 
 def _p(a, t):
@@ -184,6 +230,22 @@ class SelInv:
         self._check(_lib.selinv_get(self._h, int(i), int(j), out), "get")
         return complex(out[0], out[1]) if self.is_complex else out[0]
 
+    def get_many(self, i, j) -> np.ndarray:
+        """A^{-1}(i[k], j[k]) for every k (one device gather)."""
+        ii = np.ascontiguousarray(i, dtype=np.int64)
+        jj = np.ascontiguousarray(j, dtype=np.int64)
+        if ii.shape != jj.shape:
+            raise ValueError("i and j must have the same length")
+        out = np.empty(ii.size * (2 if self.is_complex else 1), dtype=np.float64)
+        self._check(_lib.selinv_get_many(self._h, ii.size, _p(ii, C.c_int64), _p(jj, C.c_int64),
+                                         _p(out, C.c_double)), "get_many")
+        return out.view(np.complex128) if self.is_complex else out
+
+    def set_gather_code_budget(self, entries=-1):
+        """Precomputed gather source codes: -1 default budget, 0 off (before factor)."""
+        self._check(_lib.selinv_set_gather_code_budget(self._h, int(entries)), "set_gather_code_budget")
+        return self
+
     def get_selected(self) -> np.ndarray:
         out = np.empty(self.nnz * (2 if self.is_complex else 1), dtype=np.float64)
         self._check(_lib.selinv_get_selected(self._h, _p(out, C.c_double)), "get_selected")
@@ -196,13 +258,18 @@ class SelInv:
                     "get_selected_device")
         return out
 
-    def export(self):
+    def export(self, sort=True):
+        """Every computed entry (row, col, A^{-1}(row, col)): sorted by (col, row),
+        or in the library's storage order (sort=False; the same order for every
+        run of the handle)."""
         m = int(self.info["nnz_lu"])
         r = np.empty(m, np.int32)
         c = np.empty(m, np.int32)
         v = np.empty(m, np.float64)
         self._check(_lib.selinv_export(self._h, _p(r, C.c_int32), _p(c, C.c_int32), _p(v, C.c_double)), "export")
-        order = np.lexsort((r, c))
+        if not sort:
+            return r, c, v
+        order = np.argsort(c.astype(np.int64) * int(self.info["n"]) + r)
         return r[order], c[order], v[order]
 
     def structure(self) -> dict:
@@ -278,10 +345,15 @@ class SelInv:
         return out
 
     def level_stats(self, level):
-        out = np.zeros(14, np.float64)
+        """Work of one level of the last run's sweep; level = -1: the prologue."""
+        out = np.zeros(19, np.float64)
         self._check(_lib.selinv_level_stats(self._h, int(level), _p(out, C.c_double)), "level_stats")
-        keys = ["nsup", "max_s", "flops35", "flops4", "gather_elems", "gather_tiles", "tiles35", "tiles4",
-                "tile35", "tile4", "small_count", "small_flops", "small_elems", "gather_fused"]
+        if level == -1:
+            keys = ["tri_flops", "tri_bytes", "norm_flops", "norm_bytes", "dt_flops", "dt_bytes"]
+        else:
+            keys = ["nsup", "max_s", "flops35", "flops4", "gather_elems", "gather_tiles", "tiles35", "tiles4",
+                    "tile35", "tile4", "small_count", "small_flops", "small_elems", "gather_fused",
+                    "bytes35", "bytes4", "bytes_gather", "bytes_small", "max_prod_flops"]
         return dict(zip(keys, out.tolist()))
 
     @property

@@ -378,3 +378,65 @@ def test_complex_error_paths(si):
     with pytest.raises(si.SelinvError) as e:
         si.SelInv(2, cp, np.array([1, 0, 0, 1], np.int32), complex_values=True)
     assert e.value.status == "BAD_PATTERN"
+
+
+def test_allocator_hook_arguments(si):
+    """selinv_set_allocator: both hooks or neither (NULL, NULL restores
+    hipMalloc); the binding installs torch's caching allocator by default."""
+    lib = si.lib()
+    alloc, free = si._hooks["torch"]
+    assert lib.selinv_set_allocator(si.ALLOC_FN(), free, None) == 1
+    assert lib.selinv_set_allocator(alloc, si.FREE_FN(), None) == 1
+    assert lib.selinv_set_allocator(si.ALLOC_FN(), si.FREE_FN(), None) == 0
+    si.set_allocator("torch")
+
+
+def test_get_many_host_checks(si):
+    """Positions are checked on the host before any device work: outside the
+    matrix -> INVALID_ARG, outside the computed set -> NOT_SELECTED, and a
+    valid list without a completed run -> STATE."""
+    w = config_c0()
+    s = si.SelInv(w.n, w.colptr, w.rowind, w.perm, w.max_super, w.relax, w.pad_pct)
+    with pytest.raises(si.SelinvError) as e:
+        s.get_many([0, w.n], [0, 0])
+    assert e.value.status == "INVALID_ARG"
+    # the first and last nodes of the 32x32 grid are far apart in the
+    # nested-dissection tree: (0, n-1) is outside the computed set
+    st = s.structure()
+    q = np.empty(w.n, np.int64)
+    q[st["perm"]] = np.arange(w.n)
+    r, c = int(st["perm"][0]), int(st["perm"][1])  # two leaf-box neighbours: inside
+    with pytest.raises(si.SelinvError) as e:
+        s.get_many([r, 0], [c, w.n - 1])
+    assert e.value.status == "NOT_SELECTED"
+    with pytest.raises(si.SelinvError) as e:
+        s.get_many([r], [c])
+    assert e.value.status == "STATE"
+    assert s.get_many([], []).size == 0
+
+
+def test_gather_code_budget(si):
+    """The gather's source codes can be limited or switched off before the
+    first factor; the plan stays consistent either way."""
+    w = config_c1()
+    for budget in (0, 4096, -1):
+        s = si.SelInv(w.n, w.colptr, w.rowind, w.perm, w.max_super, w.relax, w.pad_pct)
+        s.set_gather_code_budget(budget)
+        assert s.check_plan() == 0
+    with pytest.raises(si.SelinvError) as e:
+        s._check(si.lib().selinv_set_gather_code_budget(None, 0), "x")
+    assert e.value.status == "INVALID_ARG"
+
+
+def test_level_stats_and_timings_without_a_run(si):
+    """Introspection before any run reports STATE instead of reading a sweep
+    that does not exist."""
+    w = config_c0()
+    s = si.SelInv(w.n, w.colptr, w.rowind, w.perm, w.max_super, w.relax, w.pad_pct)
+    with pytest.raises(si.SelinvError) as e:
+        s.level_stats(0)
+    assert e.value.status == "STATE"
+    s.set_profiling(True)
+    with pytest.raises(si.SelinvError) as e:
+        s.timings()
+    assert e.value.status == "STATE"
