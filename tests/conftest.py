@@ -18,3 +18,11 @@ def oracle_mod():
     import oracle
     oracle.build(force=False)
     return oracle
+
+
+def pytest_terminal_summary(terminalreporter):
+    from records import RECORDS
+    if RECORDS:
+        terminalreporter.write_sep("-", "parity record: max errors against the oracle")
+        for line in RECORDS:
+            terminalreporter.write_line(line)
