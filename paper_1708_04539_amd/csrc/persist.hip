@@ -112,9 +112,10 @@ __global__ __launch_bounds__(256) void sweep_kernel(const PersistArgs a) {
 //      kept in LDS;
 //   3. the step-4 product from that LDS copy and the Uhat registers.
 // When s < 49 several wavefronts share a column block and split its row
-// blocks.  Products run on v_mfma_*_16x16x4 with the k order and operand
-// roles of the grouped GEMM, so FP64 and FP32 results are bitwise those of the
-// per-phase launches; the split-BF16 form runs these small products in FP32.
+// blocks.  Products run with the k order, operand roles and operand split of
+// the grouped GEMM (v_mfma_f64/f32_16x16x4; split-BF16: per 32-wide k chunk
+// B_lo A_hi, B_hi A_lo, B_hi A_hi on v_mfma_f32_16x16x32_bf16), so that the
+// results are bitwise those of the per-phase launches in every form.
 template <typename T>
 struct SmallSmem {
     // G_K while steps 3 and 5 read it, then A^{-T}(K, R_U)^T for step 4
@@ -179,6 +180,103 @@ __device__ __forceinline__ typename SmallMfma<T>::Acc small_tile(GetA getA, cons
     }
     return acc;
 }
+
+// Split-BF16 operands of the small products, as the grouped GEMM splits
+// them: x = hi + lo, hi = bf16(x), lo = bf16(x - hi).  Lane l holds k =
+// 32 c + 8 (l / 16) + e, e < 8, of chunk c (K <= 64: two chunks).
+struct SplitB {
+    v8bf h[2], l[2];
+};
+
+__device__ __forceinline__ void split_bf16(float v, __bf16 &h, __bf16 &l) {
+    h = (__bf16)v;
+    l = (__bf16)(v - (float)h);
+}
+
+// op(B)(k, n0 + lane % 16) of a K x N column-major FP32 operand, split
+__device__ __forceinline__ void small_loadB_split(SplitB &b, const float *Bp, int64_t ldb, int N, int K, int n0) {
+    const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+    float v[2][8];
+    if (!Bp || K <= 0) {
+#pragma unroll
+        for (int c = 0; c < 2; c++)
+#pragma unroll
+            for (int e = 0; e < 8; e++) v[c][e] = 0.0f;
+    } else {
+        const SELINV_GLOBAL float *B = gptr(Bp);
+        const int n = n0 + li;
+        const int64_t nc = min(n, N - 1);
+#pragma unroll
+        for (int c = 0; c < 2; c++)
+#pragma unroll
+            for (int e = 0; e < 8; e++) v[c][e] = B[min(32 * c + 8 * lk + e, K - 1) + nc * ldb];
+#pragma unroll
+        for (int c = 0; c < 2; c++)
+#pragma unroll
+            for (int e = 0; e < 8; e++) v[c][e] = (n < N && 32 * c + 8 * lk + e < K) ? v[c][e] : 0.0f;
+    }
+#pragma unroll
+    for (int c = 0; c < 2; c++)
+#pragma unroll
+        for (int e = 0; e < 8; e++) {
+            __bf16 h, l;
+            split_bf16(v[c][e], h, l);
+            b.h[c][e] = h;
+            b.l[c][e] = l;
+        }
+}
+
+// One 16x16 tile (rows m0..) of op(A) op(B) in split-BF16: op(A)(m, k) from
+// getA (LDS), op(B) split in registers, k < K <= 64.
+template <typename GetA>
+__device__ __forceinline__ v4f small_tile_split(GetA getA, const SplitB &b, int M, int K, int m0) {
+    const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+    v4f acc = {0, 0, 0, 0};
+    const int m = m0 + li;
+#pragma unroll
+    for (int c = 0; c < 2; c++) {
+        if (32 * c >= K) break;
+        v8bf ah, al;
+#pragma unroll
+        for (int e = 0; e < 8; e++) {
+            const int k = 32 * c + 8 * lk + e;
+            const float a = (m < M && k < K) ? getA(m, k) : 0.0f;
+            __bf16 h, l;
+            split_bf16(a, h, l);
+            ah[e] = h;
+            al[e] = l;
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b.l[c], ah, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b.h[c], al, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b.h[c], ah, acc, 0, 0, 0);
+    }
+    return acc;
+}
+
+// op(B) registers of one wavefront's column block, in the form's arithmetic
+template <int MODE>
+struct SmallB {
+    typedef typename Mode<MODE>::T T;
+    T v[16];
+    __device__ __forceinline__ void load(const T *Bp, int64_t ldb, int N, int K, int n0) {
+        small_loadB<T>(v, Bp, ldb, N, K, n0);
+    }
+    template <typename GetA>
+    __device__ __forceinline__ typename SmallMfma<T>::Acc tile(GetA getA, int M, int K, int m0) const {
+        return small_tile<T>(getA, v, M, K, m0);
+    }
+};
+template <>
+struct SmallB<CMP_BF16X3> {
+    SplitB v;
+    __device__ __forceinline__ void load(const float *Bp, int64_t ldb, int N, int K, int n0) {
+        small_loadB_split(v, Bp, ldb, N, K, n0);
+    }
+    template <typename GetA>
+    __device__ __forceinline__ v4f tile(GetA getA, int M, int K, int m0) const {
+        return small_tile_split(getA, v, M, K, m0);
+    }
+};
 
 // G_K of a small supernode (c_L, c_U <= 64) into tileS[b][a] from its source
 // codes.  The threads walk the codes in storage order (both code arrays are
@@ -246,10 +344,10 @@ __global__ __launch_bounds__(256, 4) void small_kernel(const MatDev *__restrict_
     const GemmProb *pzu = it.pzu >= 0 ? &probs[it.pzu] : nullptr;
     const GemmProb *pzl = it.pzl >= 0 ? &probs[it.pzl] : nullptr;
     const GemmProb *pg4 = it.pg4 >= 0 ? &probs[it.pg4] : nullptr;
-    T bL[16], bU[16];
-    small_loadB<T>(bL, pzu ? (const T *)pzu->B : nullptr, pzu ? pzu->ldb : 1, s, cl, n0);
+    SmallB<MODE> bL, bU;
+    bL.load(pzu ? (const T *)pzu->B : nullptr, pzu ? pzu->ldb : 1, s, cl, n0);
     const GemmProb *pu = pzl ? pzl : pg4;  // Uhat: op(B) of steps 5 and 4
-    small_loadB<T>(bU, pu ? (const T *)pu->B : nullptr, pu ? pu->ldb : 1, s, cu, n0);
+    bU.load(pu ? (const T *)pu->B : nullptr, pu ? pu->ldb : 1, s, cu, n0);
 
     // (a small supernode with a non-empty G_K always has source codes)
     if (cl > 0 && cu > 0) gather_small_codes<T>(mats[it.mat], cl, cu, it.c_off, sm.g.tileS);
@@ -265,7 +363,7 @@ __global__ __launch_bounds__(256, 4) void small_kernel(const MatDev *__restrict_
             for (int i = 0; i < 4; i++) {
                 const int mb = mfirst + i * per;
                 if (16 * mb >= cu) break;
-                zacc[i] = small_tile<T>([&](int m, int k) { return G[m][k]; }, bL, cu, cl, 16 * mb);
+                zacc[i] = bL.tile([&](int m, int k) { return G[m][k]; }, cu, cl, 16 * mb);
                 const int m = 16 * mb + li;
 #pragma unroll
                 for (int v = 0; v < 4; v++) {
@@ -279,7 +377,7 @@ __global__ __launch_bounds__(256, 4) void small_kernel(const MatDev *__restrict_
         if (pzl) {
             SELINV_GLOBAL T *C = gptr_w((T *)pzl->C);
             for (int mb = mfirst; 16 * mb < cl; mb += per) {
-                const typename MF::Acc acc = small_tile<T>([&](int m, int k) { return G[k][m]; }, bU, cl, cu, 16 * mb);
+                const typename MF::Acc acc = bU.tile([&](int m, int k) { return G[k][m]; }, cl, cu, 16 * mb);
                 const int m = 16 * mb + li;
 #pragma unroll
                 for (int v = 0; v < 4; v++) {
@@ -310,8 +408,7 @@ __global__ __launch_bounds__(256, 4) void small_kernel(const MatDev *__restrict_
     if (active && pg4) {
         SELINV_GLOBAL double *C = gptr_w((double *)pg4->C);
         for (int mb = mfirst; 16 * mb < s; mb += per) {
-            const typename MF::Acc acc =
-                small_tile<T>([&](int m, int k) { return G[k][m]; }, bU, s, cu, 16 * mb);
+            const typename MF::Acc acc = bU.tile([&](int m, int k) { return G[k][m]; }, s, cu, 16 * mb);
             const int m = 16 * mb + li;
             double cin[4];
 #pragma unroll
