@@ -259,7 +259,8 @@ selinv_status selinv_set_sweep_mode(selinv_handle h, int32_t mode);
  * events, whole-sweep comparisons from replays of the sweep's HIP graph.  When the measured choices are not faster
  * than the built-in size policy, the policy is kept.  ms_policy and ms_tuned
  * (nullable) receive the two sweep times.  Needs a factored handle; the runs
- * leave the results of an ordinary run behind.  Batches use the size policy. */
+ * leave the results of an ordinary run behind.  Batches have their own
+ * tables (selinv_batch_tune). */
 selinv_status selinv_tune(selinv_handle h, selinv_precision prec, int32_t reps, void *stream,
                           double *ms_policy, double *ms_tuned);
 
@@ -290,11 +291,39 @@ int32_t selinv_sweep_is_persistent(selinv_handle h, selinv_precision prec);
 
 /* Batches: several factored handles processed by one level sweep, levels
  * aligned at the roots (section on inter-supernode parallelism: supernodes
- * with the same priority run together).  The batch keeps pointers to the
- * handles; destroy the batch before its handles. */
+ * with the same priority run together, here those of every matrix).  Every
+ * launch of the sweep covers the supernodes of one level of all matrices.
+ * The batch keeps pointers to the handles (each may appear once; else
+ * SELINV_E_INVALID_ARG; unfactored: SELINV_E_STATE); destroy the batch before
+ * its handles.  Its device memory (work lists) comes from the allocator in
+ * effect at selinv_batch_create.  Results land in each handle's own buffers
+ * and are read with the handle's get/export calls, as after selinv_run; the
+ * FP64 results equal those of single runs bit for bit.
+ *   selinv_batch_run         eager launches on `stream`;
+ *   selinv_batch_run_graph   the sweep recorded once into a HIP graph per
+ *                            (batch, precision) and replayed;
+ *   selinv_batch_set_sweep_mode, selinv_batch_tune, selinv_batch_get_tuning,
+ *   selinv_batch_set_tuning  as for a handle (selinv_set_sweep_mode,
+ *                            selinv_tune, ...), over the batch's aligned
+ *                            levels (nlevels = the deepest matrix's);
+ *   selinv_batch_set_profiling, selinv_batch_timings, selinv_batch_level_stats
+ *                            as for a handle, for the batch's last eager run;
+ *   selinv_batch_query       matrices, aligned levels and the total
+ *                            algorithmic flops (any pointer may be NULL). */
 selinv_status selinv_batch_create(selinv_handle *hs, int32_t count, selinv_batch *out);
 selinv_status selinv_batch_run(selinv_batch b, selinv_precision prec, void *stream);
+selinv_status selinv_batch_run_graph(selinv_batch b, selinv_precision prec, void *stream);
 selinv_status selinv_batch_set_sweep_mode(selinv_batch b, int32_t mode);
+selinv_status selinv_batch_tune(selinv_batch b, selinv_precision prec, int32_t reps, void *stream,
+                                double *ms_policy, double *ms_tuned);
+selinv_status selinv_batch_get_tuning(selinv_batch b, selinv_precision prec, int32_t *out, int32_t cap,
+                                      int32_t *count);
+selinv_status selinv_batch_set_tuning(selinv_batch b, selinv_precision prec, const int32_t *in, int32_t count);
+selinv_status selinv_batch_set_profiling(selinv_batch b, int32_t on);
+selinv_status selinv_batch_timings(selinv_batch b, double *ms, int32_t count);
+selinv_status selinv_batch_level_stats(selinv_batch b, int32_t level, double *stats);
+selinv_status selinv_batch_query(selinv_batch b, int32_t *count, int32_t *nlevels, double *flops);
+const char *selinv_batch_last_error(selinv_batch b);
 void selinv_batch_destroy(selinv_batch b);
 
 /* A^{-1}(i, j) = At^{-T}(q[j], q[i]), q = perm^{-1} (step 6; eq. unpermute).

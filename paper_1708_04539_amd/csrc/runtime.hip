@@ -178,6 +178,29 @@ struct Tuning {
 
 constexpr int NPREC = 3;
 
+// What one level sweep runs over: a handle alone, or the handles of a batch
+// with their levels aligned at the roots.  Per precision the work lists (and
+// the HIP graph recorded from them) and the tuning table; the events of the
+// last profiled eager run.
+struct Runner {
+    DevAlloc al;
+    std::vector<selinv_handle> hs;
+    std::unique_ptr<Sweep> sweep[3];
+    Tuning tune[3];
+    int sweep_mode = 0;
+    bool profiling = false;
+    std::vector<hipEvent_t> events;
+    hipStream_t own_stream = nullptr;
+    int last_prec = -1;          // precision of the last run through this runner
+    bool last_profiled = false;  // that run recorded its phase events
+    int depth() const;
+    ~Runner() {
+        for (int p = 0; p < 3; p++) sweep[p].reset();
+        for (auto e : events) (void)hipEventDestroy(e);
+        if (own_stream) (void)hipStreamDestroy(own_stream);
+    }
+};
+
 // Work lists of the device LU (selinv_factor_device), built once per handle:
 // per level (deepest first) and per 64-column step of the diagonal blocks one
 // launch each of tile LUs, tile inverses, solves (products with the
@@ -245,26 +268,23 @@ struct selinv_handle_s {
     uint32_t *d_gcL = nullptr, *d_gcU = nullptr;
     int64_t *d_push_off = nullptr;
     PrecBufs pb[NPREC];
-    std::unique_ptr<Sweep> sweep[NPREC];
+    Runner run;  // the handle's own sweeps (hs = {this})
     int last_prec = -1;
     hipStream_t last_stream = nullptr;
     const Sweep *last_sweep = nullptr;  // sweep of the last run (own or a batch's)
-    hipStream_t own_stream = nullptr;
-    bool profiling = false;
-    bool last_profiled = false;  // the last run recorded its phase events
-    int sweep_mode = SWEEP_AUTO;
-    Tuning tune[NPREC];
+    bool last_profiled = false;         // the last run was a profiled eager run of that sweep
     std::unique_ptr<LuPlan> lu;
-    std::vector<hipEvent_t> events;
-    std::vector<double> times;
 };
 
+int Runner::depth() const {
+    int d = 0;
+    for (auto h : hs) d = std::max(d, h->P.nlevels);
+    return d;
+}
+
 struct selinv_batch_s {
-    DevAlloc al;
-    std::vector<selinv_handle> hs;
-    std::unique_ptr<Sweep> sweep[NPREC];
+    Runner run;
     std::string err;
-    int sweep_mode = SWEEP_AUTO;
 };
 
 namespace {
@@ -1375,6 +1395,8 @@ selinv_status selinv_analyze(int64_t n, const int64_t *colptr, const int32_t *ro
     selinv_handle h = new (std::nothrow) selinv_handle_s();
     if (!h) return SELINV_E_NOMEM;
     h->al = current_alloc();
+    h->run.al = h->al;
+    h->run.hs.assign(1, h);
     const int32_t symbolic = opts ? opts->symbolic : SELINV_SYMBOLIC_SYMMETRIZED;
     if (symbolic != SELINV_SYMBOLIC_SYMMETRIZED && symbolic != SELINV_SYMBOLIC_EXACT) {
         g_analyze_err = "opts->symbolic must be SELINV_SYMBOLIC_SYMMETRIZED or SELINV_SYMBOLIC_EXACT";
@@ -1813,198 +1835,191 @@ static selinv_status check_run(selinv_handle h, int prec) {
     return SELINV_OK;
 }
 
-static selinv_status ensure_sweep(selinv_handle h, int prec) {
-    if (h->sweep[prec]) return SELINV_OK;
-    std::vector<selinv_handle> one{h};
-    return build_sweep(one, h->al, prec, h->sweep_mode, h->sweep[prec], h->err, &h->tune[prec]);
+// ---------------------------------------------------------------------------
+// runs over a Runner (one handle, or a batch)
+// ---------------------------------------------------------------------------
+static selinv_status runner_ensure(Runner &R, int prec, std::string &err) {
+    if (R.sweep[prec]) return SELINV_OK;
+    return build_sweep(R.hs, R.al, prec, R.sweep_mode, R.sweep[prec], err, &R.tune[prec]);
 }
 
-selinv_status selinv_run(selinv_handle h, selinv_precision prec, void *stream) {
-    selinv_status st = check_run(h, prec);
+static void runner_drop(Runner &R, int prec) {
+    for (auto h : R.hs)
+        if (h->last_sweep == R.sweep[prec].get()) h->last_sweep = nullptr;
+    R.sweep[prec].reset();
+    if (R.last_prec == prec) R.last_profiled = false;
+}
+
+// One sweep of `prec` on stream s: eager launches (with one event after each
+// phase while profiling is on) or a replay of the HIP graph recorded from
+// them at the first graph run.
+static selinv_status runner_launch(Runner &R, int prec, hipStream_t s, bool graph, std::string &err) {
+    selinv_status st = runner_ensure(R, prec, err);
     if (st) return st;
-    if ((st = ensure_sweep(h, prec))) return st;
-    hipStream_t s = (hipStream_t)stream;
-    const Sweep &S = *h->sweep[prec];
-    std::vector<hipEvent_t> *ev = nullptr;
-    if (h->profiling) {
-        size_t need = 4 + 4 * S.gat.size();
-        while (h->events.size() < need) {
-            hipEvent_t e;
-            HIPCHK(h->err, hipEventCreate(&e), "hipEventCreate");
-            h->events.push_back(e);
+    Sweep &S = *R.sweep[prec];
+    bool profiled = false;
+    if (graph) {
+        if (!s) {  // graphs are not captured on the legacy null stream
+            if (!R.own_stream) HIPCHK(err, hipStreamCreateWithFlags(&R.own_stream, hipStreamNonBlocking), "stream");
+            s = R.own_stream;
         }
-        ev = &h->events;
-    }
-    hipError_t e = launch_sweep(S, s, ev);
-    if (e != hipSuccess) return dev_fail(h->err, e, "kernel launch");
-    h->last_sweep = &S;
-    h->last_prec = prec;
-    h->last_stream = s;
-    h->last_profiled = ev != nullptr;
-    h->state = 2;
-    return SELINV_OK;
-}
-
-selinv_status selinv_run_graph(selinv_handle h, selinv_precision prec, void *stream) {
-    selinv_status st = check_run(h, prec);
-    if (st) return st;
-    if ((st = ensure_sweep(h, prec))) return st;
-    Sweep &S = *h->sweep[prec];
-    hipStream_t s = (hipStream_t)stream;
-    if (!s) {
-        if (!h->own_stream) HIPCHK(h->err, hipStreamCreateWithFlags(&h->own_stream, hipStreamNonBlocking), "stream");
-        s = h->own_stream;
-    }
-    if (!S.gexec) {
-        HIPCHK(h->err, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
-        hipError_t e = launch_sweep(S, s, nullptr);
-        hipGraph_t g = nullptr;
-        hipError_t e2 = hipStreamEndCapture(s, &g);
-        if (e != hipSuccess) return dev_fail(h->err, e, "capture launch");
-        if (e2 != hipSuccess) return dev_fail(h->err, e2, "end capture");
-        S.graph = g;
-        HIPCHK(h->err, hipGraphInstantiate(&S.gexec, g, nullptr, nullptr, 0), "graph instantiate");
-    }
-    HIPCHK(h->err, hipGraphLaunch(S.gexec, s), "graph launch");
-    h->last_sweep = &S;
-    h->last_prec = prec;
-    h->last_stream = s;
-    h->last_profiled = false;
-    h->state = 2;
-    return SELINV_OK;
-}
-
-selinv_status selinv_set_sweep_mode(selinv_handle h, int32_t mode) {
-    if (!h || mode < SWEEP_AUTO || mode > SWEEP_PERSISTENT) return SELINV_E_INVALID_ARG;
-    if (mode != h->sweep_mode) {
-        h->sweep_mode = mode;
-        for (int p = 0; p < NPREC; p++) {
-            if (h->last_sweep == h->sweep[p].get()) h->last_sweep = nullptr;
-            h->sweep[p].reset();
+        if (!S.gexec) {
+            HIPCHK(err, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
+            hipError_t e = launch_sweep(S, s, nullptr);
+            hipGraph_t g = nullptr;
+            hipError_t e2 = hipStreamEndCapture(s, &g);
+            if (e != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                return dev_fail(err, e, "capture launch");
+            }
+            if (e2 != hipSuccess) return dev_fail(err, e2, "end capture");
+            S.graph = g;
+            HIPCHK(err, hipGraphInstantiate(&S.gexec, g, nullptr, nullptr, 0), "graph instantiate");
         }
-    }
-    return SELINV_OK;
-}
-
-selinv_status selinv_batch_set_sweep_mode(selinv_batch b, int32_t mode) {
-    if (!b || mode < SWEEP_AUTO || mode > SWEEP_PERSISTENT) return SELINV_E_INVALID_ARG;
-    if (mode != b->sweep_mode) {
-        b->sweep_mode = mode;
-        for (int p = 0; p < NPREC; p++) {
-            for (auto h : b->hs)
-                if (h->last_sweep == b->sweep[p].get()) h->last_sweep = nullptr;
-            b->sweep[p].reset();
+        HIPCHK(err, hipGraphLaunch(S.gexec, s), "graph launch");
+    } else {
+        std::vector<hipEvent_t> *ev = nullptr;
+        if (R.profiling) {
+            const size_t need = 4 + 4 * S.gat.size();
+            while (R.events.size() < need) {
+                hipEvent_t e;
+                HIPCHK(err, hipEventCreate(&e), "hipEventCreate");
+                R.events.push_back(e);
+            }
+            ev = &R.events;
+            profiled = true;
         }
+        hipError_t e = launch_sweep(S, s, ev);
+        if (e != hipSuccess) return dev_fail(err, e, "kernel launch");
     }
+    for (auto h : R.hs) {
+        h->last_sweep = &S;
+        h->last_prec = prec;
+        h->last_stream = s;
+        h->last_profiled = profiled && R.hs.size() == 1;
+        h->state = 2;
+    }
+    R.last_prec = prec;
+    R.last_profiled = profiled;
     return SELINV_OK;
 }
 
-int32_t selinv_sweep_is_persistent(selinv_handle h, selinv_precision prec) {
-    if (!h || !valid_prec(prec) || !h->sweep[prec]) return -1;
-    return h->sweep[prec]->persistent ? 1 : 0;
-}
-
-selinv_status selinv_set_profiling(selinv_handle h, int32_t on) {
-    if (!h) return SELINV_E_INVALID_ARG;
-    h->profiling = on != 0;
-    return SELINV_OK;
-}
-
-selinv_status selinv_timings(selinv_handle h, double *ms, int32_t count) {
-    if (!h || !ms) return SELINV_E_INVALID_ARG;
-    // the events belong to the last run only if it was this handle's own
-    // profiled run and its sweep still exists
-    if (h->state < 2 || h->last_prec < 0 || !h->last_profiled || !h->last_sweep ||
-        h->last_sweep != h->sweep[h->last_prec].get())
+// Event intervals of the runner's last profiled run (see selinv_timings).
+static selinv_status runner_timings(Runner &R, double *ms, int32_t count, std::string &err) {
+    if (R.last_prec < 0 || !R.last_profiled || !R.sweep[R.last_prec]) {
+        err = "no profiled run";
         return SELINV_E_STATE;
-    const Sweep &S = *h->last_sweep;
+    }
+    const Sweep &S = *R.sweep[R.last_prec];
     size_t nev = 4 + 4 * S.gat.size();
-    if (h->events.size() < nev) return SELINV_E_STATE;
-    HIPCHK(h->err, hipEventSynchronize(h->events[nev - 1]), "event sync");
+    if (R.events.size() < nev) return SELINV_E_STATE;
+    HIPCHK(err, hipEventSynchronize(R.events[nev - 1]), "event sync");
     for (int32_t i = 0; i < count; i++) {
         if ((size_t)i + 1 >= nev) {
             ms[i] = 0;
             continue;
         }
         float t = 0;
-        HIPCHK(h->err, hipEventElapsedTime(&t, h->events[i], h->events[i + 1]), "elapsed");
+        HIPCHK(err, hipEventElapsedTime(&t, R.events[i], R.events[i + 1]), "elapsed");
         ms[i] = t;
     }
     return SELINV_OK;
 }
 
-// ---------------------------------------------------------------------------
-// autotuner
-// ---------------------------------------------------------------------------
-static void drop_sweep(selinv_handle h, int prec) {
-    if (h->last_sweep == h->sweep[prec].get()) h->last_sweep = nullptr;
-    h->sweep[prec].reset();
+static void level_stats_of(const Sweep &S, int32_t level, double *stats) {
+    stats[0] = S.lev_nsup[level];
+    stats[1] = S.lev_maxs[level];
+    stats[2] = S.lev_flops35[level];
+    stats[3] = S.lev_flops4[level];
+    stats[4] = S.lev_gather_elems[level];
+    stats[5] = S.gat[level].count;
+    stats[6] = S.g35[level].count;
+    stats[7] = S.g4[level].count;
+    stats[8] = S.g35[level].tile;
+    stats[9] = S.g4[level].tile;
+    stats[10] = S.small[level].count;
+    stats[11] = S.lev_small_flops[level];
+    stats[12] = S.lev_small_elems[level];
+    stats[13] = S.fused[level];
+    stats[14] = S.lev_bytes35[level];
+    stats[15] = S.lev_bytes4[level];
+    stats[16] = S.lev_bytes_gather[level];
+    stats[17] = S.lev_bytes_small[level];
+    stats[18] = S.lev_max_prod[level];
+}
+
+static selinv_status sweep_level_stats(const Sweep &S, int32_t level, double *stats) {
+    if (level == -1) {
+        for (int k = 0; k < 19; k++) stats[k] = 0;
+        for (int k = 0; k < 3; k++) {
+            stats[2 * k] = S.pro_flops[k];
+            stats[2 * k + 1] = S.pro_bytes[k];
+        }
+        return SELINV_OK;
+    }
+    if (level < 0 || level >= (int32_t)S.gat.size()) return SELINV_E_INVALID_ARG;
+    level_stats_of(S, level, stats);
+    return SELINV_OK;
 }
 
 // Runs the sweep of `prec` reps + 1 times (the first untimed) under the
-// handle's current tuning.  total: fastest run in ms (HIP events on `s`
+// runner's current tuning.  total: fastest run in ms (HIP events on `s`
 // around a replay of the sweep's HIP graph, or around the eager launches of a
 // profiled run); phase (profiled runs): fastest time of every event interval
 // of the profiled sweep.
-static selinv_status tune_measure(selinv_handle h, int prec, hipStream_t s, int reps, bool profiled, double &total,
-                                  std::vector<double> *phase) {
-    drop_sweep(h, prec);
-    selinv_status st = ensure_sweep(h, prec);
+static selinv_status tune_measure(Runner &R, int prec, hipStream_t s, int reps, bool profiled, double &total,
+                                  std::vector<double> *phase, std::string &err) {
+    runner_drop(R, prec);
+    selinv_status st = runner_ensure(R, prec, err);
     if (st) return st;
-    const bool was = h->profiling;
-    h->profiling = profiled;
+    const bool was = R.profiling;
+    R.profiling = profiled;
     hipEvent_t a = nullptr, b = nullptr;
     auto done = [&](selinv_status r) {
-        h->profiling = was;
+        R.profiling = was;
         if (a) (void)hipEventDestroy(a);
         if (b) (void)hipEventDestroy(b);
         return r;
     };
     hipError_t ec = hipEventCreate(&a);
     if (ec == hipSuccess) ec = hipEventCreate(&b);
-    if (ec != hipSuccess) return done(dev_fail(h->err, ec, "hipEventCreate"));
-    const int nint = 3 + 4 * (int)h->sweep[prec]->gat.size();
+    if (ec != hipSuccess) return done(dev_fail(err, ec, "hipEventCreate"));
+    const int nint = 3 + 4 * (int)R.sweep[prec]->gat.size();
     total = 1e300;
     if (phase) phase->assign(nint, 1e300);
     std::vector<double> t(nint);
     hipError_t e;
     for (int r = 0; r <= reps; r++) {
-        if ((e = hipEventRecord(a, s)) != hipSuccess) return done(dev_fail(h->err, e, "event record"));
-        st = profiled ? selinv_run(h, (selinv_precision)prec, s) : selinv_run_graph(h, (selinv_precision)prec, s);
-        if (st) return done(st);
-        if ((e = hipEventRecord(b, s)) != hipSuccess) return done(dev_fail(h->err, e, "event record"));
-        if ((e = hipEventSynchronize(b)) != hipSuccess) return done(dev_fail(h->err, e, "event sync"));
+        if ((e = hipEventRecord(a, s)) != hipSuccess) return done(dev_fail(err, e, "event record"));
+        if ((st = runner_launch(R, prec, s, !profiled, err))) return done(st);
+        if ((e = hipEventRecord(b, s)) != hipSuccess) return done(dev_fail(err, e, "event record"));
+        if ((e = hipEventSynchronize(b)) != hipSuccess) return done(dev_fail(err, e, "event sync"));
         if (r == 0) continue;
         float ms = 0;
-        if ((e = hipEventElapsedTime(&ms, a, b)) != hipSuccess) return done(dev_fail(h->err, e, "elapsed"));
+        if ((e = hipEventElapsedTime(&ms, a, b)) != hipSuccess) return done(dev_fail(err, e, "elapsed"));
         total = std::min(total, (double)ms);
         if (phase) {
-            if ((st = selinv_timings(h, t.data(), nint))) return done(st);
+            if ((st = runner_timings(R, t.data(), nint, err))) return done(st);
             for (int i = 0; i < nint; i++) (*phase)[i] = std::min((*phase)[i], t[i]);
         }
     }
     return done(SELINV_OK);
 }
 
-selinv_status selinv_tune(selinv_handle h, selinv_precision prec, int32_t reps, void *stream, double *ms_policy,
-                          double *ms_tuned) {
-    selinv_status st = check_run(h, prec);
-    if (st) return st;
+// The autotuner (selinv_tune / selinv_batch_tune); stream s is not the null stream.
+static selinv_status runner_tune(Runner &R, int prec, int32_t reps, hipStream_t s, double *ms_policy,
+                                 double *ms_tuned, std::string &err) {
     if (reps < 1 || reps > 100) {
-        h->err = "reps must be in 1..100";
+        err = "reps must be in 1..100";
         return SELINV_E_INVALID_ARG;
     }
-    hipStream_t s = (hipStream_t)stream;
-    if (!s) {  // graphs are not captured on the legacy null stream
-        if (!h->own_stream) HIPCHK(h->err, hipStreamCreateWithFlags(&h->own_stream, hipStreamNonBlocking), "stream");
-        s = h->own_stream;
-    }
-    const int L = h->P.nlevels;
-    const bool can_persist = h->sweep_mode == SWEEP_AUTO;
-    // the size policy, in the handle's own sweep form
-    h->tune[prec] = Tuning();
+    selinv_status st;
+    const int L = R.depth();
+    const bool can_persist = R.sweep_mode == SWEEP_AUTO;
+    // the size policy, in the runner's own sweep form
+    R.tune[prec] = Tuning();
     double t_policy = 0, t = 0;
-    if ((st = tune_measure(h, prec, s, reps, false, t_policy, nullptr))) return st;
+    if ((st = tune_measure(R, prec, s, reps, false, t_policy, nullptr, err))) return st;
 
     // 1. tile edge of every launch class: the whole level sweep profiled once
     //    per candidate edge, every class keeps its fastest edge
@@ -2013,7 +2028,7 @@ selinv_status selinv_tune(selinv_handle h, selinv_precision prec, int32_t reps, 
     best.t35.assign(L, 0);
     best.t4.assign(L, 0);
     best.no_small.assign(L, 0);
-    best.sweep = h->sweep_mode == SWEEP_AUTO ? SWEEP_LEVELS : SWEEP_AUTO;
+    best.sweep = R.sweep_mode == SWEEP_AUTO ? SWEEP_LEVELS : SWEEP_AUTO;
     const int cand[3] = {GEMM_TILE_32, GEMM_TILE_64, GEMM_TILE_128};
     std::vector<double> bt(3 + 2 * L, 1e300);
     std::vector<double> ph;
@@ -2023,8 +2038,8 @@ selinv_status selinv_tune(selinv_handle h, selinv_precision prec, int32_t reps, 
         std::fill(tn.t35.begin(), tn.t35.end(), c);
         std::fill(tn.t4.begin(), tn.t4.end(), c);
         tn.sweep = SWEEP_LEVELS;
-        h->tune[prec] = tn;
-        if ((st = tune_measure(h, prec, s, reps, true, t, &ph))) return st;
+        R.tune[prec] = tn;
+        if ((st = tune_measure(R, prec, s, reps, true, t, &ph, err))) return st;
         auto keep = [&](int k, double v, int &slot) {
             if (v < bt[k]) {
                 bt[k] = v;
@@ -2049,10 +2064,10 @@ selinv_status selinv_tune(selinv_handle h, selinv_precision prec, int32_t reps, 
         on.sweep = off.sweep = SWEEP_LEVELS;
         std::fill(off.no_small.begin(), off.no_small.end(), 1);
         std::vector<double> pon, poff;
-        h->tune[prec] = on;
-        if ((st = tune_measure(h, prec, s, reps, true, t, &pon))) return st;
-        h->tune[prec] = off;
-        if ((st = tune_measure(h, prec, s, reps, true, t, &poff))) return st;
+        R.tune[prec] = on;
+        if ((st = tune_measure(R, prec, s, reps, true, t, &pon, err))) return st;
+        R.tune[prec] = off;
+        if ((st = tune_measure(R, prec, s, reps, true, t, &poff, err))) return st;
         for (int d = 0; d < L; d++) {
             auto lev = [&](const std::vector<double> &p) {
                 double v = 0;
@@ -2064,14 +2079,14 @@ selinv_status selinv_tune(selinv_handle h, selinv_precision prec, int32_t reps, 
         }
     }
     // 3. the sweep form, where the persistent sweep is available
-    h->tune[prec] = best;
+    R.tune[prec] = best;
     double t_best = 0;
-    if ((st = tune_measure(h, prec, s, reps, false, t_best, nullptr))) return st;
+    if ((st = tune_measure(R, prec, s, reps, false, t_best, nullptr, err))) return st;
     if (can_persist) {
         Tuning pe = best;
         pe.sweep = SWEEP_PERSISTENT;
-        h->tune[prec] = pe;
-        if ((st = tune_measure(h, prec, s, reps, false, t, nullptr))) return st;
+        R.tune[prec] = pe;
+        if ((st = tune_measure(R, prec, s, reps, false, t, nullptr, err))) return st;
         if (t < t_best) {
             best = pe;
             t_best = t;
@@ -2082,8 +2097,8 @@ selinv_status selinv_tune(selinv_handle h, selinv_precision prec, int32_t reps, 
     {
         Tuning nf = best;
         nf.no_fork = 1;
-        h->tune[prec] = nf;
-        if ((st = tune_measure(h, prec, s, reps, false, t, nullptr))) return st;
+        R.tune[prec] = nf;
+        if ((st = tune_measure(R, prec, s, reps, false, t, nullptr, err))) return st;
         if (t < t_best) {
             best = nf;
             t_best = t;
@@ -2092,18 +2107,18 @@ selinv_status selinv_tune(selinv_handle h, selinv_precision prec, int32_t reps, 
     // 5. with a side stream: its tile inversions in chunks of a multiple of
     //    the compute-unit count, or in one launch
     if (!best.no_fork) {
-        h->tune[prec] = best;
-        drop_sweep(h, prec);
-        if ((st = ensure_sweep(h, prec))) return st;
+        R.tune[prec] = best;
+        runner_drop(R, prec);
+        if ((st = runner_ensure(R, prec, err))) return st;
         int cus = 0;
-        HIPCHK(h->err, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device),
+        HIPCHK(err, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, R.hs[0]->device),
                "device attribute");
-        if (h->sweep[prec]->split > 0 && cus > 0) {
+        if (R.sweep[prec]->split > 0 && cus > 0) {
             for (int q : {5, 6, 7, 8, 10, 12}) {
                 Tuning ch = best;
                 ch.side_chunk = q * cus / 4;
-                h->tune[prec] = ch;
-                if ((st = tune_measure(h, prec, s, reps, false, t, nullptr))) return st;
+                R.tune[prec] = ch;
+                if ((st = tune_measure(R, prec, s, reps, false, t, nullptr, err))) return st;
                 if (t < t_best) {
                     best = ch;
                     t_best = t;
@@ -2121,8 +2136,8 @@ selinv_status selinv_tune(selinv_handle h, selinv_precision prec, int32_t reps, 
         best = pol;
         t_best = t_policy;
     }
-    h->tune[prec] = best;
-    drop_sweep(h, prec);
+    R.tune[prec] = best;
+    runner_drop(R, prec);
     if (ms_policy) *ms_policy = t_policy;
     if (ms_tuned) *ms_tuned = t_best;
     return SELINV_OK;
@@ -2131,15 +2146,14 @@ selinv_status selinv_tune(selinv_handle h, selinv_precision prec, int32_t reps, 
 // flat form: [3, nlevels, sweep, tri, norm, dt, no_fork, side_chunk, then per
 // level: t35, t4, no_small] (tables of the earlier layouts, without
 // side_chunk (2) or without no_fork as well (1), are still accepted)
-selinv_status selinv_get_tuning(selinv_handle h, selinv_precision prec, int32_t *out, int32_t cap,
-                                int32_t *count) {
-    if (!h || !valid_prec(prec) || !count) return SELINV_E_INVALID_ARG;
-    const Tuning &tn = h->tune[prec];
-    const int L = h->P.nlevels;
+static selinv_status runner_get_tuning(const Runner &R, int prec, int32_t *out, int32_t cap, int32_t *count,
+                                       std::string &err) {
+    const Tuning &tn = R.tune[prec];
+    const int L = R.depth();
     *count = tn.set ? 8 + 3 * L : 0;
     if (!tn.set || !out) return SELINV_OK;
     if (cap < *count) {
-        h->err = "tuning buffer too small";
+        err = "tuning buffer too small";
         return SELINV_E_INVALID_ARG;
     }
     int32_t *o = out;
@@ -2159,14 +2173,13 @@ selinv_status selinv_get_tuning(selinv_handle h, selinv_precision prec, int32_t 
     return SELINV_OK;
 }
 
-selinv_status selinv_set_tuning(selinv_handle h, selinv_precision prec, const int32_t *in, int32_t count) {
-    if (!h || !valid_prec(prec)) return SELINV_E_INVALID_ARG;
+static selinv_status runner_set_tuning(Runner &R, int prec, const int32_t *in, int32_t count, std::string &err) {
     if (count == 0) {  // back to the size policy
-        h->tune[prec] = Tuning();
-        drop_sweep(h, prec);
+        R.tune[prec] = Tuning();
+        runner_drop(R, prec);
         return SELINV_OK;
     }
-    const int L = h->P.nlevels;
+    const int L = R.depth();
     auto tile_ok = [](int v) { return v == 0 || v == GEMM_TILE_32 || v == GEMM_TILE_64 || v == GEMM_TILE_128; };
     const int ver = in && count > 0 ? in[0] : 0, hd = ver == 3 ? 8 : ver == 2 ? 7 : 6;
     bool ok = in && ver >= 1 && ver <= 3 && count == hd + 3 * L && in[1] == L && in[2] >= SWEEP_AUTO &&
@@ -2176,7 +2189,7 @@ selinv_status selinv_set_tuning(selinv_handle h, selinv_precision prec, const in
         ok = tile_ok(in[hd + 3 * d]) && tile_ok(in[hd + 1 + 3 * d]) &&
              (in[hd + 2 + 3 * d] == 0 || in[hd + 2 + 3 * d] == 1);
     if (!ok) {
-        h->err = "tuning table does not fit this handle (layout, level count, tile edges or sweep form)";
+        err = "tuning table does not fit (layout, level count, tile edges or sweep form)";
         return SELINV_E_INVALID_ARG;
     }
     Tuning tn;
@@ -2192,44 +2205,89 @@ selinv_status selinv_set_tuning(selinv_handle h, selinv_precision prec, const in
         tn.t4.push_back(in[hd + 1 + 3 * d]);
         tn.no_small.push_back((char)in[hd + 2 + 3 * d]);
     }
-    h->tune[prec] = tn;
-    drop_sweep(h, prec);
+    R.tune[prec] = tn;
+    runner_drop(R, prec);
     return SELINV_OK;
+}
+
+static selinv_status runner_set_mode(Runner &R, int32_t mode) {
+    if (mode < SWEEP_AUTO || mode > SWEEP_PERSISTENT) return SELINV_E_INVALID_ARG;
+    if (mode != R.sweep_mode) {
+        R.sweep_mode = mode;
+        for (int p = 0; p < NPREC; p++) runner_drop(R, p);
+    }
+    return SELINV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI: runs of one handle
+// ---------------------------------------------------------------------------
+selinv_status selinv_run(selinv_handle h, selinv_precision prec, void *stream) {
+    selinv_status st = check_run(h, prec);
+    if (st) return st;
+    return runner_launch(h->run, prec, (hipStream_t)stream, false, h->err);
+}
+
+selinv_status selinv_run_graph(selinv_handle h, selinv_precision prec, void *stream) {
+    selinv_status st = check_run(h, prec);
+    if (st) return st;
+    return runner_launch(h->run, prec, (hipStream_t)stream, true, h->err);
+}
+
+selinv_status selinv_set_sweep_mode(selinv_handle h, int32_t mode) {
+    if (!h) return SELINV_E_INVALID_ARG;
+    return runner_set_mode(h->run, mode);
+}
+
+int32_t selinv_sweep_is_persistent(selinv_handle h, selinv_precision prec) {
+    if (!h || !valid_prec(prec) || !h->run.sweep[prec]) return -1;
+    return h->run.sweep[prec]->persistent ? 1 : 0;
+}
+
+selinv_status selinv_set_profiling(selinv_handle h, int32_t on) {
+    if (!h) return SELINV_E_INVALID_ARG;
+    h->run.profiling = on != 0;
+    return SELINV_OK;
+}
+
+selinv_status selinv_timings(selinv_handle h, double *ms, int32_t count) {
+    if (!h || !ms) return SELINV_E_INVALID_ARG;
+    // the events belong to the last run only if it was this handle's own
+    // profiled run and its sweep still exists
+    if (h->state < 2 || h->last_prec < 0 || !h->last_profiled || !h->last_sweep ||
+        h->last_sweep != h->run.sweep[h->last_prec].get())
+        return SELINV_E_STATE;
+    return runner_timings(h->run, ms, count, h->err);
+}
+
+selinv_status selinv_tune(selinv_handle h, selinv_precision prec, int32_t reps, void *stream, double *ms_policy,
+                          double *ms_tuned) {
+    selinv_status st = check_run(h, prec);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    if (!s) {  // graphs are not captured on the legacy null stream
+        if (!h->run.own_stream)
+            HIPCHK(h->err, hipStreamCreateWithFlags(&h->run.own_stream, hipStreamNonBlocking), "stream");
+        s = h->run.own_stream;
+    }
+    return runner_tune(h->run, prec, reps, s, ms_policy, ms_tuned, h->err);
+}
+
+selinv_status selinv_get_tuning(selinv_handle h, selinv_precision prec, int32_t *out, int32_t cap,
+                                int32_t *count) {
+    if (!h || !valid_prec(prec) || !count) return SELINV_E_INVALID_ARG;
+    return runner_get_tuning(h->run, prec, out, cap, count, h->err);
+}
+
+selinv_status selinv_set_tuning(selinv_handle h, selinv_precision prec, const int32_t *in, int32_t count) {
+    if (!h || !valid_prec(prec)) return SELINV_E_INVALID_ARG;
+    return runner_set_tuning(h->run, prec, in, count, h->err);
 }
 
 selinv_status selinv_level_stats(selinv_handle h, int32_t level, double *stats) {
     if (!h || !stats) return SELINV_E_INVALID_ARG;
     if (!h->last_sweep) return SELINV_E_STATE;  // no run yet, or its sweep was dropped
-    const Sweep &S = *h->last_sweep;
-    if (level == -1) {
-        for (int k = 0; k < 19; k++) stats[k] = 0;
-        for (int k = 0; k < 3; k++) {
-            stats[2 * k] = S.pro_flops[k];
-            stats[2 * k + 1] = S.pro_bytes[k];
-        }
-        return SELINV_OK;
-    }
-    if (level < 0 || level >= (int32_t)S.gat.size()) return SELINV_E_INVALID_ARG;
-    stats[0] = S.lev_nsup[level];
-    stats[1] = S.lev_maxs[level];
-    stats[2] = S.lev_flops35[level];
-    stats[3] = S.lev_flops4[level];
-    stats[4] = S.lev_gather_elems[level];
-    stats[5] = S.gat[level].count;
-    stats[6] = S.g35[level].count;
-    stats[7] = S.g4[level].count;
-    stats[8] = S.g35[level].tile;
-    stats[9] = S.g4[level].tile;
-    stats[10] = S.small[level].count;
-    stats[11] = S.lev_small_flops[level];
-    stats[12] = S.lev_small_elems[level];
-    stats[13] = S.fused[level];
-    stats[14] = S.lev_bytes35[level];
-    stats[15] = S.lev_bytes4[level];
-    stats[16] = S.lev_bytes_gather[level];
-    stats[17] = S.lev_bytes_small[level];
-    stats[18] = S.lev_max_prod[level];
-    return SELINV_OK;
+    return sweep_level_stats(*h->last_sweep, level, stats);
 }
 
 static selinv_status check_sweep_error(std::string &err, const Sweep *S) {
@@ -2546,7 +2604,7 @@ selinv_status selinv_query(selinv_handle h, selinv_info *info) {
 void selinv_destroy(selinv_handle h) {
     if (!h) return;
     for (int p = 0; p < NPREC; p++) {
-        h->sweep[p].reset();
+        h->run.sweep[p].reset();
         PrecBufs &b = h->pb[p];
         for (void *q : {(void *)b.Zd, b.ZL, b.ZU, b.Lh, b.Uh, b.G}) h->al.put(q);
     }
@@ -2557,8 +2615,6 @@ void selinv_destroy(selinv_handle h) {
                     (void *)h->d_mapU, (void *)h->d_lcol, (void *)h->d_urow, (void *)h->d_aloc, (void *)h->d_aloc_c,
                     (void *)h->d_kids_ptr, (void *)h->d_kids, (void *)h->d_push_off, (void *)h->d_push_pos, (void *)h->d_gcL, (void *)h->d_gcU})
         h->al.put(q);
-    for (auto e : h->events) (void)hipEventDestroy(e);
-    if (h->own_stream) (void)hipStreamDestroy(h->own_stream);
     delete h;
 }
 
@@ -2567,41 +2623,105 @@ selinv_status selinv_batch_create(selinv_handle *hs, int32_t count, selinv_batch
     *out = nullptr;
     for (int32_t i = 0; i < count; i++)
         if (!hs[i] || hs[i]->state < 1) return SELINV_E_STATE;
+    for (int32_t i = 0; i < count; i++)
+        for (int32_t k = 0; k < i; k++)
+            if (hs[k] == hs[i]) return SELINV_E_INVALID_ARG;  // a matrix appears once
     selinv_batch b = new (std::nothrow) selinv_batch_s();
     if (!b) return SELINV_E_NOMEM;
-    b->al = current_alloc();
-    b->hs.assign(hs, hs + count);
+    b->run.al = current_alloc();
+    b->run.hs.assign(hs, hs + count);
     *out = b;
     return SELINV_OK;
 }
 
-selinv_status selinv_batch_run(selinv_batch b, selinv_precision prec, void *stream) {
+static selinv_status check_batch(selinv_batch b, int prec) {
     if (!b || !valid_prec(prec)) return SELINV_E_INVALID_ARG;
-    for (auto h : b->hs) {
+    for (auto h : b->run.hs) {
         selinv_status st = check_run(h, prec);
-        if (st) return st;
-    }
-    if (!b->sweep[prec]) {
-        selinv_status st = build_sweep(b->hs, b->al, prec, b->sweep_mode, b->sweep[prec], b->err);
-        if (st) return st;
-    }
-    hipError_t e = launch_sweep(*b->sweep[prec], (hipStream_t)stream, nullptr);
-    if (e != hipSuccess) return dev_fail(b->err, e, "batch launch");
-    for (auto h : b->hs) {
-        h->last_prec = prec;
-        h->last_stream = (hipStream_t)stream;
-        h->last_sweep = b->sweep[prec].get();
-        h->last_profiled = false;
-        h->state = 2;
+        if (st) {
+            b->err = h->err;
+            return st;
+        }
     }
     return SELINV_OK;
 }
 
+selinv_status selinv_batch_run(selinv_batch b, selinv_precision prec, void *stream) {
+    selinv_status st = check_batch(b, prec);
+    if (st) return st;
+    return runner_launch(b->run, prec, (hipStream_t)stream, false, b->err);
+}
+
+selinv_status selinv_batch_run_graph(selinv_batch b, selinv_precision prec, void *stream) {
+    selinv_status st = check_batch(b, prec);
+    if (st) return st;
+    return runner_launch(b->run, prec, (hipStream_t)stream, true, b->err);
+}
+
+selinv_status selinv_batch_set_sweep_mode(selinv_batch b, int32_t mode) {
+    if (!b) return SELINV_E_INVALID_ARG;
+    return runner_set_mode(b->run, mode);
+}
+
+selinv_status selinv_batch_tune(selinv_batch b, selinv_precision prec, int32_t reps, void *stream,
+                                double *ms_policy, double *ms_tuned) {
+    selinv_status st = check_batch(b, prec);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    if (!s) {
+        if (!b->run.own_stream)
+            HIPCHK(b->err, hipStreamCreateWithFlags(&b->run.own_stream, hipStreamNonBlocking), "stream");
+        s = b->run.own_stream;
+    }
+    return runner_tune(b->run, prec, reps, s, ms_policy, ms_tuned, b->err);
+}
+
+selinv_status selinv_batch_get_tuning(selinv_batch b, selinv_precision prec, int32_t *out, int32_t cap,
+                                      int32_t *count) {
+    if (!b || !valid_prec(prec) || !count) return SELINV_E_INVALID_ARG;
+    return runner_get_tuning(b->run, prec, out, cap, count, b->err);
+}
+
+selinv_status selinv_batch_set_tuning(selinv_batch b, selinv_precision prec, const int32_t *in, int32_t count) {
+    if (!b || !valid_prec(prec)) return SELINV_E_INVALID_ARG;
+    return runner_set_tuning(b->run, prec, in, count, b->err);
+}
+
+selinv_status selinv_batch_set_profiling(selinv_batch b, int32_t on) {
+    if (!b) return SELINV_E_INVALID_ARG;
+    b->run.profiling = on != 0;
+    return SELINV_OK;
+}
+
+selinv_status selinv_batch_timings(selinv_batch b, double *ms, int32_t count) {
+    if (!b || !ms) return SELINV_E_INVALID_ARG;
+    return runner_timings(b->run, ms, count, b->err);
+}
+
+selinv_status selinv_batch_level_stats(selinv_batch b, int32_t level, double *stats) {
+    if (!b || !stats) return SELINV_E_INVALID_ARG;
+    const Runner &R = b->run;
+    if (R.last_prec < 0 || !R.sweep[R.last_prec]) return SELINV_E_STATE;
+    return sweep_level_stats(*R.sweep[R.last_prec], level, stats);
+}
+
+selinv_status selinv_batch_query(selinv_batch b, int32_t *count, int32_t *nlevels, double *flops) {
+    if (!b) return SELINV_E_INVALID_ARG;
+    if (count) *count = (int32_t)b->run.hs.size();
+    if (nlevels) *nlevels = b->run.depth();
+    if (flops) {
+        double f = 0;
+        for (auto h : b->run.hs) f += h->P.flops;
+        *flops = f;
+    }
+    return SELINV_OK;
+}
+
+const char *selinv_batch_last_error(selinv_batch b) { return b ? b->err.c_str() : ""; }
+
 void selinv_batch_destroy(selinv_batch b) {
     if (!b) return;
-    for (int p = 0; p < NPREC; p++)
-        for (auto h : b->hs)
-            if (h->last_sweep == b->sweep[p].get()) h->last_sweep = nullptr;
+    for (int p = 0; p < NPREC; p++) runner_drop(b->run, p);
     delete b;
 }
 

@@ -31,7 +31,10 @@ EXPORTED = ["selinv_analyze", "selinv_factor", "selinv_factor_device", "selinv_r
             "selinv_set_profiling", "selinv_timings", "selinv_level_stats", "selinv_last_error",
             "selinv_status_string", "selinv_destroy", "selinv_check_plan", "selinv_set_sweep_mode",
             "selinv_sweep_is_persistent", "selinv_batch_set_sweep_mode", "selinv_tune", "selinv_get_tuning",
-            "selinv_set_tuning", "selinv_set_allocator", "selinv_get_many", "selinv_set_gather_code_budget"]
+            "selinv_set_tuning", "selinv_set_allocator", "selinv_get_many", "selinv_set_gather_code_budget",
+            "selinv_batch_run_graph", "selinv_batch_tune", "selinv_batch_get_tuning", "selinv_batch_set_tuning",
+            "selinv_batch_set_profiling", "selinv_batch_timings", "selinv_batch_level_stats", "selinv_batch_query",
+            "selinv_batch_last_error"]
 
 
 class SelinvError(RuntimeError):
@@ -104,6 +107,15 @@ def _load():
         "selinv_set_allocator": ([ALLOC_FN, FREE_FN, vp], C.c_int),
         "selinv_get_many": ([vp, i64, P(i64), P(i64), P(dbl)], C.c_int),
         "selinv_set_gather_code_budget": ([vp, i64], C.c_int),
+        "selinv_batch_run_graph": ([vp, C.c_int, vp], C.c_int),
+        "selinv_batch_tune": ([vp, C.c_int, i32, vp, P(dbl), P(dbl)], C.c_int),
+        "selinv_batch_get_tuning": ([vp, C.c_int, P(i32), i32, P(i32)], C.c_int),
+        "selinv_batch_set_tuning": ([vp, C.c_int, P(i32), i32], C.c_int),
+        "selinv_batch_set_profiling": ([vp, i32], C.c_int),
+        "selinv_batch_timings": ([vp, P(dbl), i32], C.c_int),
+        "selinv_batch_level_stats": ([vp, i32, P(dbl)], C.c_int),
+        "selinv_batch_query": ([vp, P(i32), P(i32), P(dbl)], C.c_int),
+        "selinv_batch_last_error": ([vp], C.c_char_p),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -348,6 +360,10 @@ class SelInv:
         """Work of one level of the last run's sweep; level = -1: the prologue."""
         out = np.zeros(19, np.float64)
         self._check(_lib.selinv_level_stats(self._h, int(level), _p(out, C.c_double)), "level_stats")
+        return self._stats_dict(level, out)
+
+    @staticmethod
+    def _stats_dict(level, out):
         if level == -1:
             keys = ["tri_flops", "tri_bytes", "norm_flops", "norm_bytes", "dt_flops", "dt_bytes"]
         else:
@@ -382,19 +398,59 @@ class Batch:
         rc = _lib.selinv_batch_create(arr, len(self.mats), C.byref(self._b))
         if rc:
             raise SelinvError(rc, "batch_create")
+        n, L, F = C.c_int32(), C.c_int32(), C.c_double()
+        self._check(_lib.selinv_batch_query(self._b, C.byref(n), C.byref(L), C.byref(F)), "batch_query")
+        self.info = {"count": n.value, "nlevels": L.value, "flops": F.value}
+
+    def _check(self, rc, what):
+        if rc:
+            raise SelinvError(rc, f"{what}: {_lib.selinv_batch_last_error(self._b).decode()}")
 
     def set_sweep_mode(self, mode="auto"):
         m = SelInv.SWEEP_MODES[mode] if isinstance(mode, str) else int(mode)
-        rc = _lib.selinv_batch_set_sweep_mode(self._b, m)
-        if rc:
-            raise SelinvError(rc, "batch_set_sweep_mode")
+        self._check(_lib.selinv_batch_set_sweep_mode(self._b, m), "batch_set_sweep_mode")
         return self
 
-    def run(self, precision="fp64", stream=None):
-        rc = _lib.selinv_batch_run(self._b, _prec(precision), _stream_ptr(stream))
-        if rc:
-            raise SelinvError(rc, "batch_run")
+    def run(self, precision="fp64", stream=None, graph=False):
+        f = _lib.selinv_batch_run_graph if graph else _lib.selinv_batch_run
+        self._check(f(self._b, _prec(precision), _stream_ptr(stream)), "batch_run")
         return self
+
+    def tune(self, precision="fp64", reps=5, stream=None):
+        a, b = C.c_double(), C.c_double()
+        self._check(_lib.selinv_batch_tune(self._b, _prec(precision), int(reps), _stream_ptr(stream), C.byref(a),
+                                           C.byref(b)), "batch_tune")
+        return a.value, b.value
+
+    def get_tuning(self, precision="fp64") -> list:
+        n = C.c_int32()
+        self._check(_lib.selinv_batch_get_tuning(self._b, _prec(precision), None, 0, C.byref(n)), "get_tuning")
+        if n.value == 0:
+            return []
+        out = np.empty(n.value, np.int32)
+        self._check(_lib.selinv_batch_get_tuning(self._b, _prec(precision), _p(out, C.c_int32), n.value,
+                                                 C.byref(n)), "get_tuning")
+        return out.tolist()
+
+    def set_tuning(self, table, precision="fp64"):
+        t = np.ascontiguousarray(table, dtype=np.int32)
+        self._check(_lib.selinv_batch_set_tuning(self._b, _prec(precision), _p(t, C.c_int32) if t.size else None,
+                                                 int(t.size)), "set_tuning")
+        return self
+
+    def set_profiling(self, on=True):
+        self._check(_lib.selinv_batch_set_profiling(self._b, 1 if on else 0), "set_profiling")
+
+    def timings(self):
+        k = 3 + 4 * self.info["nlevels"]
+        out = np.zeros(k, np.float64)
+        self._check(_lib.selinv_batch_timings(self._b, _p(out, C.c_double), k), "timings")
+        return out
+
+    def level_stats(self, level):
+        out = np.zeros(19, np.float64)
+        self._check(_lib.selinv_batch_level_stats(self._b, int(level), _p(out, C.c_double)), "level_stats")
+        return SelInv._stats_dict(level, out)
 
     def close(self):
         if getattr(self, "_b", None) is not None and self._b.value:
