@@ -39,7 +39,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="c4", choices=["c0", "c1", "c2", "c4", "u1", "u4", "z1"])
+    ap.add_argument("--config", default="c4", choices=["c0", "c1", "c2", "c3", "c4", "u1", "u4", "z1"])
     ap.add_argument("--symbolic", default=None, choices=["symmetrized", "exact"],
                     help="analysis form (default: symmetrized for c*, exact for the upwind u* configs)")
     ap.add_argument("--precision", default="fp64", help="form of the headline value")
@@ -64,6 +64,8 @@ WORKLOADS = {
     "c0": "2D 32x32 5-point asymmetric convection-diffusion, n=1024, ND, supernodes<=32",
     "c1": "2D 256x256 9-point asymmetric stencil, n=65536, ND, supernodes<=128",
     "c2": "3D 48^3 7-point asymmetric convection-diffusion, n=110592, ND, supernodes<=256",
+    "c3": "batch of 32 2D 5-point asymmetric convection-diffusion matrices, grid sides uniform in 64..256 "
+          "(n 4k..64k), ND, supernodes<=128, one level-batched sweep",
     "c4": "3D 64^3 27-point asymmetric stencil, n=262144, ND, supernodes<=512",
     "u1": "2D 256x256 9-point upwind stencil (non-symmetric pattern), n=65536, ND, supernodes<=128",
     "u4": "3D 64^3 27-point upwind stencil (non-symmetric pattern), n=262144, ND, supernodes<=512",
@@ -356,6 +358,140 @@ def cpu_baseline(config, budget_s):
                       f"mean of {len(times)} runs, {t * 1e3:.1f} ms each"}, (w, o, sel)
 
 
+def bench_c3(args, prec, mixed_forms):
+    """Batch of 32 matrices: one level-batched sweep (HIP graph, tuned per
+    form) plus the extraction of every matrix's selected entries per step;
+    the same matrices run one by one are timed beside it."""
+    import numpy as np
+    import torch
+    from paper_1708_04539_amd.selinv import Batch, SelInv
+    from workloads import config_c3
+
+    ws = config_c3()
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    t0 = time.perf_counter()
+    mats = [SelInv(w.n, w.colptr, w.rowind, w.perm, w.max_super, w.relax, w.pad_pct).factor(w.values) for w in ws]
+    t_setup = time.perf_counter() - t0
+    b = Batch(mats)
+    F = b.info["flops"]
+    offs = np.concatenate([[0], np.cumsum([w.nnz for w in ws])])
+    out = torch.empty(int(offs[-1]), dtype=torch.float64, device="cuda")
+    views = [out[int(offs[k]):int(offs[k + 1])] for k in range(len(ws))]
+    graph = not args.no_graph
+    tuning = {"tuned": False}
+    if not args.no_tune:
+        from paper_1708_04539_amd.autotune import describe
+        t0 = time.perf_counter()
+        for p in [prec] + mixed_forms:
+            ms_pol, ms_tun = b.tune(p, args.tune_reps, stream)
+            tuning[p] = dict(describe(b.get_tuning(p)), ms_policy_graph=ms_pol, ms_tuned_graph=ms_tun)
+        tuning["tuned"] = True
+        tuning["tune_s"] = time.perf_counter() - t0
+
+    class Step:  # one step: the batched sweep and every matrix's extraction
+        def __init__(self):
+            self.info = b.info
+
+        def run(self, p, stream=None, graph=False):
+            b.run(p, stream=stream, graph=graph)
+
+        def get_selected_device(self, _out, stream=None):
+            for m, v in zip(mats, views):
+                m.get_selected_device(v, stream=stream)
+
+    st = Step()
+    forms = {}
+    for p in [prec] + mixed_forms:
+        dev, wall = timed_steps(st, p, args.steps, args.warmup, graph, out, stream)
+        forms[p] = {"ms_per_batch": 1e3 * dev / args.steps, "ms_per_matrix": 1e3 * dev / args.steps / len(ws),
+                    "gflops": F / (dev / args.steps) / 1e9}
+        if p == prec:
+            wall_main = wall
+        print(f"# {p}: {forms[p]['ms_per_matrix']:.4f} ms per matrix", file=sys.stderr, flush=True)
+    ms = forms[prec]["ms_per_matrix"]
+    for p in mixed_forms:
+        forms[p]["speedup_vs_" + prec] = ms / forms[p]["ms_per_matrix"]
+    # the same matrices one by one (each its own graph, tuned by the size policy)
+    for m in mats:
+        m.run(prec, stream=stream, graph=True)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        for m, v in zip(mats, views):
+            m.run(prec, stream=stream, graph=True)
+            m.get_selected_device(v, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_single = e0.elapsed_time(e1) / args.steps / len(ws)
+
+    ph = phase_profile(b, prec, stream)
+    roof = roofline(ph, prec)
+    roof["traffic"] = load_traffic("c3", prec, roof["kernel"])
+    roof["traffic_unit"] = "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)"
+    forms[prec]["largest_product_launch"] = largest_product(ph, prec)
+    for p in mixed_forms:
+        php = phase_profile(b, p, stream)
+        forms[p]["largest_product_launch"] = largest_product(php, p)
+        forms[p]["roofline"] = roofline(php, p)
+    res = {
+        "metric": "selinv GFLOP/s & ms/matrix, mixed vs FP64 on 1 MI355X at stated max rel err",
+        "value": forms[prec]["gflops"], "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": forms[prec]["ms_per_batch"], "ms_per_matrix": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if prec == "fp64" else ("f32" if prec == "mixed_fp32" else "bf16x3/f32"),
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS["c3"], "matrices": len(ws), "n_total": int(sum(w.n for w in ws)),
+                   "nnz_total": int(offs[-1]), "precision": prec, "gflop": F / 1e9,
+                   "aligned_levels": b.info["nlevels"], "hip_graph": graph, "parallelism": "single GPU"},
+        "forms": forms,
+        "unbatched_ms_per_matrix": ms_single,
+        "batching_speedup": ms_single / ms,
+        "wall_s_timed": wall_main,
+        "setup_s": {"analyze_and_host_lu": t_setup, "tune": tuning.get("tune_s", 0.0)},
+        "tuning": tuning,
+        "roofline": roof,
+    }
+    if mixed_forms:
+        best = max(mixed_forms, key=lambda p: forms[p]["gflops"])
+        res["mixed_best"] = best
+        res["mixed_speedup_vs_fp64"] = forms[best]["speedup_vs_" + prec] if prec == "fp64" else None
+    if not args.no_cpu_baseline:
+        print("# cpu baseline", file=sys.stderr, flush=True)
+        import oracle
+        from oracle import Oracle
+        oracle.build(force=False)
+        done, t_cpu, f_cpu, refs = 0, 0.0, 0.0, []
+        for k, w in enumerate(ws):  # matrices in order while the budget lasts
+            o = Oracle(w.n, w.colptr, w.rowind, w.perm, w.max_super, w.relax, 0, w.pad_pct).factor(w.values)
+            t0 = time.perf_counter()
+            o.selinv()
+            refs.append(o.get_selected())
+            t_cpu += time.perf_counter() - t0
+            f_cpu += mats[k].info["flops"]
+            done += 1
+            o.close()
+            if t_cpu > args.cpu_seconds:
+                break
+        res["cpu_baseline"] = {"value": f_cpu / t_cpu / 1e9, "unit": "GFLOP/s", "cores": oracle.get_threads(),
+                               "kind": "oracle",
+                               "sample": f"the first {done} of the 32 matrices, one oracle pass each (steps 2-6), "
+                                         f"{f_cpu / 1e9:.2f} GFLOP in {t_cpu:.1f} s"}
+        if not args.no_errors:
+            errs = {}
+            for p in [prec] + mixed_forms:
+                b.run(p, stream=stream, graph=graph)
+                e = 0.0
+                for k in range(done):
+                    got = mats[k].get_selected()
+                    e = max(e, float(np.abs(got - refs[k]).max() / np.abs(refs[k]).max()))
+                errs[p] = e
+            res["max_rel_err"] = errs
+            res["max_rel_err_on"] = f"every selected entry of the first {done} matrices, against the FP64 oracle"
+    print(json.dumps(res))
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -376,6 +512,8 @@ def main():
     for p in [prec] + mixed_forms:
         if p not in FORMS:
             raise SystemExit(f"unknown form {p}")
+    if args.config == "c3":
+        return bench_c3(args, prec, mixed_forms)
     w = get_config(args.config)
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()  # graphs cannot be captured on the legacy null stream

@@ -182,42 +182,88 @@ def test_c1_get_and_extraction(si, c1_pair):
 
 
 # --------------------------------------------------------------------------
-# batches (C3 shape): one sweep over several matrices
+# batches (C3): one sweep over all 32 matrices
 # --------------------------------------------------------------------------
-def test_c3_batch_matches_single_runs(si):
-    ws = config_c3(count=4)
-    say("c3 batch", [w.n for w in ws])
+@pytest.fixture(scope="module")
+def c3_all(si):
+    ws = config_c3()
+    say("c3 setup", len(ws), "matrices, n", min(w.n for w in ws), "..", max(w.n for w in ws))
     mats = [si.SelInv(w.n, w.colptr, w.rowind, w.perm, w.max_super, w.relax, w.pad_pct).factor(w.values)
             for w in ws]
-    single = []
-    for m in mats:
-        m.run("fp64")
-        single.append(m.get_selected())
+    single = {}
+    for prec in ["fp64", "mixed_fp32", "mixed_bf16x3"]:
+        single[prec] = []
+        for m in mats:
+            m.run(prec)
+            single[prec].append(m.get_selected())
+    return ws, mats, single
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed_fp32", "mixed_bf16x3"])
+def test_c3_batch_of_32_equals_single_runs(si, c3_all, prec):
+    """Every launch of the batch covers one level of all 32 matrices; each
+    matrix's results equal its single run bit for bit (every output entry is
+    formed by the same products in the same order), eagerly and from the
+    batch's HIP graph, with eager single runs between the replays."""
+    import torch
+    ws, mats, single = c3_all
+    say("c3 batch", prec)
     b = si.Batch(mats)
-    for prec in ["fp64", "mixed_fp32"]:
-        b.run(prec)
-        for m, ref in zip(mats, single):
-            got = m.get_selected()
-            if prec == "fp64":
-                assert np.array_equal(got, ref)
-            else:
-                assert np.abs(got - ref).max() / np.abs(ref).max() < 1e-5
-    o = Oracle(ws[1].n, ws[1].colptr, ws[1].rowind, ws[1].perm, ws[1].max_super, ws[1].relax, 0,
-               ws[1].pad_pct).factor(ws[1].values).selinv()
-    b.run("fp64")
-    compare_superset(mats[1], o, TOL["fp64"])
+    assert b.info["count"] == 32
+    b.run(prec)
+    for k, m in enumerate(mats):
+        assert np.array_equal(m.get_selected(), single[prec][k]), k
+    st = torch.cuda.Stream()
+    for rep in range(3):
+        b.run(prec, stream=st, graph=True)
+        for k, m in enumerate(mats):
+            assert np.array_equal(m.get_selected(), single[prec][k]), (rep, k)
+        torch.cuda.synchronize()
+        mats[rep].run(prec)  # eager work between replays
+        assert np.array_equal(mats[rep].get_selected(), single[prec][rep])
     b.close()
 
 
-# --------------------------------------------------------------------------
-# full-size 3D cases: identities on the selected set + sampled exact columns
-# --------------------------------------------------------------------------
-def identity_residuals(w, sel):
-    cols = np.repeat(np.arange(w.n), np.diff(w.colptr))
-    prod = w.values * sel
-    row = np.bincount(w.rowind, weights=prod, minlength=w.n)
-    col = np.bincount(cols, weights=prod, minlength=w.n)
-    return np.abs(row - 1).max(), np.abs(col - 1).max()
+def test_c3_batch_against_the_oracle(si, c3_all):
+    """Four matrices of the batch (the smallest, the largest and two between)
+    over their whole computed set, in all three forms, after batch runs."""
+    ws, mats, _ = c3_all
+    order = np.argsort([w.n for w in ws])
+    pick = [int(order[0]), int(order[len(order) // 3]), int(order[2 * len(order) // 3]), int(order[-1])]
+    say("c3 oracle", [ws[k].n for k in pick])
+    b = si.Batch(mats)
+    for k in pick:
+        w = ws[k]
+        o = Oracle(w.n, w.colptr, w.rowind, w.perm, w.max_super, w.relax, 0, w.pad_pct).factor(w.values).selinv()
+        for prec in ["fp64", "mixed_fp32", "mixed_bf16x3"]:
+            b.run(prec)
+            en, ed = compare_superset(mats[k], o, TOL[prec])
+            record(f"c3 matrix {k} (n={w.n}) whole set, batch", prec, "err_norm", en, "err_diag", ed)
+    b.close()
+
+
+def test_c3_batch_tuned_and_profiled(si, c3_all):
+    """The batch's own tuning table changes launch shapes only: FP64 results
+    stay equal to the single runs bit for bit; its profiled run reports the
+    work of every aligned level."""
+    ws, mats, single = c3_all
+    say("c3 batch tune")
+    b = si.Batch(mats)
+    ms_pol, ms_tun = b.tune("fp64", reps=2)
+    table = b.get_tuning("fp64")
+    assert ms_tun <= ms_pol and len(table) == 8 + 3 * b.info["nlevels"]
+    b.run("fp64", graph=True)
+    for k, m in enumerate(mats):
+        assert np.array_equal(m.get_selected(), single["fp64"][k]), k
+    b.set_profiling(True)
+    b.run("fp64")
+    t = b.timings()
+    assert t.shape == (3 + 4 * b.info["nlevels"],) and (t >= 0).all()
+    work = sum(b.level_stats(d)["flops35"] + b.level_stats(d)["flops4"] + b.level_stats(d)["small_flops"]
+               for d in range(b.info["nlevels"]))
+    assert work > 0
+    b.set_tuning([], "fp64")
+    b.close()
 
 
 def identity_tol(w, sel, bar):
