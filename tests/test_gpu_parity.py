@@ -266,6 +266,15 @@ def test_c3_batch_tuned_and_profiled(si, c3_all):
     b.close()
 
 
+def identity_residuals(w, sel):
+    """max_i |(A A^{-1})_ii - 1| and max_j |(A^{-1} A)_jj - 1| from the selected entries."""
+    cols = np.repeat(np.arange(w.n), np.diff(w.colptr))
+    prod = w.values * sel
+    row = np.bincount(w.rowind, weights=prod, minlength=w.n)
+    col = np.bincount(cols, weights=prod, minlength=w.n)
+    return np.abs(row - 1).max(), np.abs(col - 1).max()
+
+
 def identity_tol(w, sel, bar):
     """Bound on the identity residuals implied by the entry bar:
     |sum_j A_ij (X_ji - R_ji)| <= ||A|| max|X - R| <= ||A|| bar max|R|."""
