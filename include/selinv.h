@@ -345,6 +345,17 @@ selinv_status selinv_get_many(selinv_handle h, int64_t count, const int64_t *i, 
  * nnz(A) doubles).  Tr[B A^{-1}] = sum_p B_p out[p] for any B on A's pattern. */
 selinv_status selinv_get_selected(selinv_handle h, double *out);
 
+/* selinv_get_selected without any allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments and result as
+ * selinv_get_selected; the entries are staged through a fixed device array of
+ * 2^20 doubles (8 MiB, one per device, held until the process ends) in chunks
+ * of at most that many, so any nnz(A) is served; the call makes no hipMalloc,
+ * hipFree or allocator-hook call.  It synchronises the run's stream once per
+ * chunk.  Calls that overlap on one device (other threads, or another handle
+ * on the same device) share that array and race: serialise them. */
+selinv_status selinv_get_selected_noalloc(selinv_handle h, double *out);
+
 /* Device version: `out` is a device buffer of nnz(A) doubles; the extraction
  * kernel runs asynchronously on `stream`. */
 selinv_status selinv_get_selected_device(selinv_handle h, double *out, void *stream);

@@ -2431,6 +2431,64 @@ selinv_status selinv_get_selected_device(selinv_handle h, double *out, void *str
     return SELINV_OK;
 }
 
+// Staging of selinv_get_selected_noalloc: the extraction writes one chunk of
+// the selected entries here and the host copy reads it back.  A file-scope
+// device array: each device the library runs on holds its own copy until the
+// process ends.  Host code never passes its name to a kernel or a copy (on
+// the host it only stands for the symbol): the array's device address comes
+// from hipGetSymbolAddress, once per device, with that device current.
+constexpr int64_t kScratchEntries = int64_t(1) << 20;  // 8 MiB of doubles
+static __device__ __align__(256) double scratch[kScratchEntries];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double *g_scratch_ptr[kMaxDevices];
+
+static selinv_status scratch_of_device(int dev, double **out, std::string &err) {
+    if (dev < 0 || dev >= kMaxDevices) {
+        err = "device ordinal beyond the staging table";
+        return SELINV_E_DEVICE;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return dev_fail(err, e != hipSuccess ? e : hipErrorInvalidSymbol,
+                                                   "hipGetSymbolAddress(scratch)");
+        g_scratch_ptr[dev] = (double *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return SELINV_OK;
+}
+
+selinv_status selinv_get_selected_noalloc(selinv_handle h, double *out) {
+    if (!h || !out) return SELINV_E_INVALID_ARG;
+    selinv_status st = sync_last(h);
+    if (st) return st;
+    int dev = 0;
+    HIPCHK(h->err, hipGetDevice(&dev), "hipGetDevice");
+    if (dev != h->device) {
+        h->err = "get_selected_noalloc on a different device than factor";
+        return SELINV_E_STATE;
+    }
+    double *buf = nullptr;
+    if ((st = scratch_of_device(dev, &buf, h->err))) return st;
+    const PrecBufs &b = h->pb[h->last_prec];
+    const int64_t cnt = h->cplx ? 2 * h->nnz_c : h->P.nnz_a;
+    const int64_t *loc = h->cplx ? h->d_aloc_c : h->d_aloc;
+    hipStream_t s = h->last_stream;
+    // chunks of at most kScratchEntries: extraction into the array, copy to
+    // the host, and the stream drained before the next chunk reuses it
+    for (int64_t p0 = 0; p0 < cnt; p0 += kScratchEntries) {
+        const int64_t m = std::min(kScratchEntries, cnt - p0);
+        ExtractArgs a{loc + p0, b.Zd, b.ZL, b.ZU, buf, m};
+        HIPCHK(h->err, launch_extract(h->last_prec == SELINV_FP64, a, s), "extract launch");
+        HIPCHK(h->err, hipMemcpyAsync(out + p0, buf, m * 8, hipMemcpyDeviceToHost, s), "extract copy");
+        HIPCHK(h->err, hipStreamSynchronize(s), "extract copy");
+    }
+    return SELINV_OK;
+}
+
 selinv_status selinv_get_selected(selinv_handle h, double *out) {
     if (!h || !out) return SELINV_E_INVALID_ARG;
     selinv_status st = sync_last(h);

@@ -34,7 +34,7 @@ EXPORTED = ["selinv_analyze", "selinv_factor", "selinv_factor_device", "selinv_r
             "selinv_set_tuning", "selinv_set_allocator", "selinv_get_many", "selinv_set_gather_code_budget",
             "selinv_batch_run_graph", "selinv_batch_tune", "selinv_batch_get_tuning", "selinv_batch_set_tuning",
             "selinv_batch_set_profiling", "selinv_batch_timings", "selinv_batch_level_stats", "selinv_batch_query",
-            "selinv_batch_last_error"]
+            "selinv_batch_last_error", "selinv_get_selected_noalloc"]
 
 
 class SelinvError(RuntimeError):
@@ -116,6 +116,7 @@ def _load():
         "selinv_batch_level_stats": ([vp, i32, P(dbl)], C.c_int),
         "selinv_batch_query": ([vp, P(i32), P(i32), P(dbl)], C.c_int),
         "selinv_batch_last_error": ([vp], C.c_char_p),
+        "selinv_get_selected_noalloc": ([vp, P(dbl)], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -261,6 +262,13 @@ class SelInv:
     def get_selected(self) -> np.ndarray:
         out = np.empty(self.nnz * (2 if self.is_complex else 1), dtype=np.float64)
         self._check(_lib.selinv_get_selected(self._h, _p(out, C.c_double)), "get_selected")
+        return out.view(np.complex128) if self.is_complex else out
+
+    def get_selected_noalloc(self) -> np.ndarray:
+        """As get_selected, staged through the library's fixed device array
+        (no device allocation)."""
+        out = np.empty(self.nnz * (2 if self.is_complex else 1), dtype=np.float64)
+        self._check(_lib.selinv_get_selected_noalloc(self._h, _p(out, C.c_double)), "get_selected_noalloc")
         return out.view(np.complex128) if self.is_complex else out
 
     def get_selected_device(self, out: "torch.Tensor", stream=None):
