@@ -69,6 +69,18 @@ struct GemmProb {
     // final entries of A^{-T}(P,P) are also written into G of P's children,
     // whose gather skips them
     int32_t push_sn, push_mat;
+    // zero structure of the operands: bit 0 op(B)(k, n) = 0 for k < n, bit 1
+    // op(A)(m, k) = 0 for k < m (products with the triangular inverses); a
+    // tile then starts its k loop at the chunk holding max(n0, m0) (the
+    // skipped chunks would add exact zeros)
+    int32_t ktri;
+    // cpx != 0: a product of a complex matrix in its real form whose result
+    // is made of 2x2 blocks of one complex entry (rows 2i, 2i+1, columns 2j,
+    // 2j+1), [[x, -y], [y, x]] or its transpose.  The problem lists only the
+    // even columns (N halved, ldb, ldc and ldcin doubled); every stored entry
+    // (m, 2j) also gives the entry (m ^ 1, 2j + 1), at ldc / 2 past it: the
+    // same value for even m, its negative for odd m (in either orientation)
+    int32_t cpx;
     double alpha, beta;
 };
 
@@ -110,7 +122,11 @@ struct ReduceItem {
     const double *P;
     int32_t M, N, ldc, nparts;
     int64_t pstride;
-    int32_t push_sn, push_mat, g_f32, pad;
+    int32_t push_sn, push_mat, g_f32;
+    // cpx != 0: the parts hold the even columns of a complex block (N of
+    // them); column n of the sum is column 2n of C, and column 2n + 1 follows
+    // from it as for GemmProb::cpx
+    int32_t cpx;
 };
 
 // device LU: one 64x64 diagonal tile (rows / columns j0 ..) of the s x s

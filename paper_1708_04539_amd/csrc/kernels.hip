@@ -289,11 +289,16 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(const ReduceItem *__
     const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x, mn = (int64_t)it.M * it.N;
     if (e >= mn) return;
     const int m = (int)(e % it.M), n = (int)(e / it.M);
-    SELINV_GLOBAL double *C = gptr_w(it.C) + m + (int64_t)n * it.ldc;
+    // complex blocks: column n of the parts is column 2n of C, which gives
+    // entry (m ^ 1, 2n + 1)
+    const int nc = it.cpx ? 2 * n : n;
+    SELINV_GLOBAL double *C = gptr_w(it.C) + m + (int64_t)nc * it.ldc;
     const SELINV_GLOBAL double *P = gptr(it.P) + e;
     double acc = *C;
     for (int p = 0; p < it.nparts; p++) acc += P[p * it.pstride];
     *C = acc;
+    const double csign = (m & 1) ? -1.0 : 1.0;
+    if (it.cpx) gptr_w(it.C)[(m ^ 1) + (int64_t)(nc + 1) * it.ldc] = csign * acc;
     if (it.push_sn < 0) return;
     // the final entry (m, n) of A^{-T}(P,P) into G_K of every child K of P
     // (the children's gathers skip these entries)
@@ -305,13 +310,17 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(const ReduceItem *__
     for (int q = kp[Pa]; q < kp[Pa + 1]; q++) {
         const int32_t K = kids[q];
         const SELINV_GLOBAL int32_t *posL = gptr(Md.push_pos) + gptr(Md.push_off)[K];
-        const int a = posL[m], b = posL[sP + n];
-        if (a < 0 || b < 0) continue;
-        const int64_t g = sn[K].g_off + a + (int64_t)b * sn[K].cl;
-        if (it.g_f32)
-            gptr_w((float *)Md.G)[g] = (float)acc;
-        else
-            gptr_w((double *)Md.G)[g] = acc;
+        for (int h = 0; h < (it.cpx ? 2 : 1); h++) {
+            // h = 1: the odd-column entry that this one gives
+            const int a = posL[h ? (m ^ 1) : m], b = posL[sP + nc + h];
+            if (a < 0 || b < 0) continue;
+            const double v = h ? csign * acc : acc;
+            const int64_t g = sn[K].g_off + a + (int64_t)b * sn[K].cl;
+            if (it.g_f32)
+                gptr_w((float *)Md.G)[g] = (float)v;
+            else
+                gptr_w((double *)Md.G)[g] = v;
+        }
     }
 }
 

@@ -255,6 +255,10 @@ struct selinv_handle_s {
     // the pattern of A (n_c, colptr_c) and, per entry p of A, the
     // locations of Re and Im of A^{-1}(j, i) (aloc_c[2p], aloc_c[2p + 1])
     bool cplx = false;
+    // the supernodes and the block row / column sets of the real form come in
+    // node pairs (2i, 2i + 1): the products of steps 3-5 then form only the
+    // even columns of their results (GemmProb::cpx)
+    bool cpx_ok = false;
     int64_t n_c = 0, nnz_c = 0;
     std::vector<int64_t> colptr_c, aloc_c;
     int64_t *d_aloc_c = nullptr;
@@ -409,7 +413,7 @@ struct Extents {
 
 int add_prob(std::vector<GemmProb> &probs, const void *A, int opA, int lda,
              const void *B, int opB, int ldb, void *C, int ldc, const void *Cin, int ldcin, int M, int N, int K,
-             double alpha, double beta, Extents *ext = nullptr, int ein = 8, int eout = 8) {
+             double alpha, double beta, Extents *ext = nullptr, int ein = 8, int eout = 8, int ktri = 0) {
     if (M <= 0 || N <= 0) return 0;
     if (ext) {
         if (K > 0) {
@@ -437,6 +441,8 @@ int add_prob(std::vector<GemmProb> &probs, const void *A, int opA, int lda,
     p.opB = opB;
     p.push_sn = -1;
     p.push_mat = -1;
+    p.ktri = ktri;
+    p.cpx = 0;
     p.alpha = alpha;
     p.beta = beta;
     probs.push_back(p);
@@ -482,6 +488,19 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, const DevAlloc &al, in
     std::vector<GatherTile> gts;
     int depth = 0;
     Extents X;
+    // a product of a complex handle's real form that forms only the even
+    // columns of its result C (rows x cols) and derives the odd ones from the
+    // 2x2 complex blocks (GemmProb::cpx)
+    auto halve = [&](int pi, const void *C, int64_t rows, int64_t cols, int esz) {
+        if (pi < 0) return;
+        GemmProb &q = probs[pi];
+        q.N /= 2;
+        q.ldb *= 2;
+        q.ldc *= 2;
+        if (q.Cin) q.ldcin *= 2;
+        q.cpx = 1;
+        X.check(C, rows, cols, q.ldc / 2, esz);
+    };
     for (auto h : hs) {
         selinv_status st = ensure_prec(h, prec);
         if (st) {
@@ -661,10 +680,12 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, const DevAlloc &al, in
                 const SnRec &r = h->sn[K];
                 char *Lh = (char *)b.Lh + r.off_l * e;
                 char *Uh = (char *)b.Uh + r.off_u * e;
+                // op(B) = (L_KK)^{-1} and (U_KK)^{-T} are lower triangular: a
+                // tile of output columns n0.. needs k >= n0 only
                 add_prob(probs, h->d_lpan + r.off_l, 0, r.cl, h->d_Linv + r.off_d, 0, r.s, Lh, r.cl, nullptr, 1, r.cl,
-                         r.s, r.s, 1.0, 0.0, &X, 8, e);
+                         r.s, r.s, 1.0, 0.0, &X, 8, e, 1);
                 add_prob(probs, h->d_upan + r.off_u, 0, r.cu, h->d_Uinv + r.off_d, 1, r.s, Uh, r.cu, nullptr, 1, r.cu,
-                         r.s, r.s, 1.0, 0.0, &X, 8, e);
+                         r.s, r.s, 1.0, 0.0, &X, 8, e, 1);
             }
         }
         // In the FP64 form the normalisation and the diagonal initialisation
@@ -681,8 +702,9 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, const DevAlloc &al, in
             for (int32_t K = 0; K < h->P.ns; K++) {
                 if (part[mi][K] != pp || fused_prologue(h->sn[K])) continue;
                 const SnRec &r = h->sn[K];
+                // op(A) = (L_KK)^{-T} upper, op(B) = (U_KK)^{-T} lower: k >= max(m0, n0)
                 add_prob(probs, h->d_Linv + r.off_d, 1, r.s, h->d_Uinv + r.off_d, 1, r.s, b.Zd + r.off_d, r.s,
-                         nullptr, 1, r.s, r.s, r.s, 1.0, 0.0, &X, 8, 8);
+                         nullptr, 1, r.s, r.s, r.s, 1.0, 0.0, &X, 8, 8, 3);
             }
         }
         if (prec == SELINV_FP64)
@@ -839,7 +861,14 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, const DevAlloc &al, in
                                             -1.0, 0.0, &X, e, e)
                                        ? (int)probs.size() - 1
                                        : -1;
-                    (pass == 0 ? S->lev_flops35[d] : S->lev_small_flops[d]) += 4.0 * r.s * (double)r.cl * r.cu;
+                    // complex handles: the even columns of both results
+                    const bool half = pass == 0 && h->cpx_ok;
+                    if (half) {
+                        halve(prob_zu[gid], ZU, r.cu, r.s, e);
+                        halve(prob_zl[gid], ZL, r.cl, r.s, e);
+                    }
+                    (pass == 0 ? S->lev_flops35[d] : S->lev_small_flops[d]) +=
+                        4.0 * r.s * (double)r.cl * r.cu / (half ? 2 : 1);
                     (pass == 0 ? S->lev_bytes35[d] : S->lev_bytes_small[d]) +=
                         e * ((double)r.cl * r.cu + 2.0 * r.s * ((double)r.cl + r.cu));
                     if (pass == 0) S->lev_max_prod[d] = std::max(S->lev_max_prod[d], 2.0 * r.s * (double)r.cl * r.cu);
@@ -867,7 +896,10 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, const DevAlloc &al, in
                                             r.s, r.s, r.s, r.cu, -1.0, 1.0, &X, e, 8)
                                        ? (int)probs.size() - 1
                                        : -1;
-                    (pass == 0 ? S->lev_flops4[d] : S->lev_small_flops[d]) += 2.0 * r.s * (double)r.s * r.cu;
+                    const bool half = pass == 0 && h->cpx_ok;
+                    if (half && prob_g4[gid] >= 0 && parts4[gid] < 2) halve(prob_g4[gid], b.Zd + r.off_d, r.s, r.s, 8);
+                    (pass == 0 ? S->lev_flops4[d] : S->lev_small_flops[d]) +=
+                        2.0 * r.s * (double)r.s * r.cu / (half ? 2 : 1);
                     if (pass == 0)
                         S->lev_bytes4[d] += 2.0 * e * r.s * (double)r.cu + 16.0 * r.s * (double)r.s;
                     else
@@ -886,13 +918,18 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, const DevAlloc &al, in
                         add_prob(probs, ZU + (int64_t)k0 * e, 1, r.cu, Uh + (int64_t)k0 * e, 0, r.cu,
                                  P0 + (int64_t)np * r.s * r.s, r.s, nullptr, 1, r.s, r.s, std::min(kc, r.cu - k0),
                                  -1.0, 0.0, &X, e, 8);
+                        if (half) {  // the even columns only, packed s x s/2; the reduction gives the rest
+                            GemmProb &q = probs.back();
+                            q.N /= 2;
+                            q.ldb *= 2;
+                        }
                         lst.push_back((int)probs.size() - 1);
                     }
                     X.check(b.Zd + r.off_d, r.s, r.s, r.s, 8);
                     X.check(P0, (int64_t)r.s * r.s, np, (int64_t)r.s * r.s, 8);
                     red_of[gid] = (int)reds.size();
-                    reds.push_back(ReduceItem{b.Zd + r.off_d, P0, r.s, r.s, r.s, np, (int64_t)r.s * r.s, -1, -1,
-                                              e == 4, 0});
+                    reds.push_back(ReduceItem{b.Zd + r.off_d, P0, r.s, half ? r.s / 2 : r.s, r.s, np,
+                                              (int64_t)r.s * r.s, -1, -1, e == 4, half ? 1 : 0});
                     S->red4_mn[d] = std::max<int64_t>(S->red4_mn[d], (int64_t)r.s * r.s);
                 }
             }
@@ -1462,6 +1499,19 @@ selinv_status selinv_analyze(int64_t n, const int64_t *colptr, const int32_t *ro
         // levels, so blocks are not reused from one level to the next
         r.g_off = h->g_elems;
         h->g_elems += (int64_t)r.cl * r.cu;
+    }
+    if (h->cplx) {
+        bool ok = true;
+        for (int32_t K = 0; K <= P.ns && ok; K++) ok = P.xsup[K] % 2 == 0;
+        auto pairs = [&](const std::vector<int64_t> &ptr, const std::vector<int32_t> &idx) {
+            for (int32_t K = 0; K < P.ns; K++) {
+                if ((ptr[K + 1] - ptr[K]) % 2) return false;
+                for (int64_t x = ptr[K]; x < ptr[K + 1]; x += 2)
+                    if (idx[x] % 2 || idx[x + 1] != idx[x] + 1) return false;
+            }
+            return true;
+        };
+        h->cpx_ok = ok && pairs(P.rl_ptr, P.rl) && pairs(P.ru_ptr, P.ru);
     }
     try {
         build_push_maps(P, h->kids_ptr, h->kids, h->push_off, h->push_pos);

@@ -5,6 +5,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "device_types.hpp"
 
 namespace selinv {
@@ -76,6 +78,115 @@ struct Smem<CMP_BF16X3, BM, BN, BK> {
     __bf16 bh[2][BN][P], bl[2][BN][P];
 };
 
+// An operand of the split-BF16 form that is contiguous along k (A with
+// op = T, B with op = N): each thread moves 4 consecutive k of R / 32 rows of
+// every 32-wide chunk, with one 16-byte load (two for FP64 operands) per row
+// and one 8-byte LDS store per plane and row.  The split and the zero padding
+// are those of the scalar path: v = (float) x, hi = bf16(v), lo = bf16(v - hi).
+template <int R, typename TA>
+struct SplitKRows {
+    static constexpr int NT = R / 32;
+    typedef TA v4 __attribute__((ext_vector_type(4), aligned(sizeof(TA))));
+    typedef __bf16 v4b __attribute__((ext_vector_type(4)));
+    const SELINV_GLOBAL TA *ptr[NT];
+    v4 reg[NT];
+    __device__ __forceinline__ int row(int t) const { return (int)(threadIdx.x >> 3) + 32 * t; }
+    __device__ __forceinline__ int kk() const { return 4 * (int)(threadIdx.x & 7); }
+    // row r of the operand starts at base + r ld (rows clamped into [0, rows))
+    __device__ __forceinline__ void init(const void *base, int64_t ld, int r0, int rows) {
+        const SELINV_GLOBAL TA *B = gptr((const TA *)base);
+#pragma unroll
+        for (int t = 0; t < NT; t++) ptr[t] = B + (int64_t)min(r0 + row(t), rows - 1) * ld + kk();
+    }
+    __device__ __forceinline__ void load(int k0, int K) {
+        if (k0 + 32 <= K) {
+#pragma unroll
+            for (int t = 0; t < NT; t++) reg[t] = *(const SELINV_GLOBAL v4 *)(ptr[t] + k0);
+        } else {
+            // last, partial chunk: k clamped into the operand
+#pragma unroll
+            for (int t = 0; t < NT; t++)
+#pragma unroll
+                for (int e = 0; e < 4; e++) reg[t][e] = ptr[t][min(k0 + kk() + e, K - 1) - kk()];
+        }
+    }
+    template <int P>
+    __device__ __forceinline__ void store(__bf16 (&hi)[R][P], __bf16 (&lo)[R][P], int r0, int rows, int k0,
+                                          int K) const {
+#pragma unroll
+        for (int t = 0; t < NT; t++) {
+            v4b h4, l4;
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const float v = (r0 + row(t) < rows && k0 + kk() + e < K) ? (float)reg[t][e] : 0.0f;
+                const __bf16 h = (__bf16)v;
+                h4[e] = h;
+                l4[e] = (__bf16)(v - (float)h);
+            }
+            *(v4b *)&hi[row(t)][kk()] = h4;
+            *(v4b *)&lo[row(t)][kk()] = l4;
+        }
+    }
+};
+
+// An operand of the split-BF16 form that is contiguous along its rows (A with
+// op = N, B with op = T): each thread owns a block of 4 consecutive rows by
+// KB = R / 32 consecutive k (4, 2 or 1) of every 32-wide chunk, loads it as KB
+// 16-byte row quads (one per k) and writes it transposed, one store of KB
+// values per row and plane.
+template <int R, typename TA>
+struct SplitMRows {
+    static constexpr int KB = R / 32;
+    static constexpr int TPK = R / 4;  // threads along the rows
+    typedef TA v4 __attribute__((ext_vector_type(4), aligned(sizeof(TA))));
+    typedef __bf16 vkb __attribute__((ext_vector_type(KB)));
+    const SELINV_GLOBAL TA *ptr;  // row r0 + r4 (0 when the quad is not whole) of k = kq
+    int64_t ld;
+    int r0, rows;
+    bool full;  // all 4 rows of the quad inside the operand
+    v4 reg[KB];
+    __device__ __forceinline__ int r4() const { return 4 * (int)(threadIdx.x % TPK); }
+    __device__ __forceinline__ int kq() const { return KB * (int)(threadIdx.x / TPK); }
+    // element (r, k) of the operand at base + r + k ld
+    __device__ __forceinline__ void init(const void *base, int64_t ld_, int r0_, int rows_) {
+        ld = ld_;
+        r0 = r0_;
+        rows = rows_;
+        full = r0 + r4() + 3 < rows;
+        ptr = gptr((const TA *)base) + (full ? r0 + r4() : 0) + (int64_t)kq() * ld;
+    }
+    __device__ __forceinline__ void load(int k0, int K) {
+        const bool kin = k0 + 32 <= K;
+#pragma unroll
+        for (int e = 0; e < KB; e++) {
+            // k offset from kq; the last, partial chunk clamps k into the operand
+            const int64_t kc = kin ? (int64_t)(k0 + e) : (int64_t)(min(k0 + kq() + e, K - 1) - kq());
+            if (full) {
+                reg[e] = *(const SELINV_GLOBAL v4 *)(ptr + kc * ld);
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; q++) reg[e][q] = ptr[min(r0 + r4() + q, rows - 1) + kc * ld];
+            }
+        }
+    }
+    template <int P>
+    __device__ __forceinline__ void store(__bf16 (&hi)[R][P], __bf16 (&lo)[R][P], int k0, int K) const {
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            vkb h, l;
+#pragma unroll
+            for (int e = 0; e < KB; e++) {
+                const float v = (r0 + r4() + q < rows && k0 + kq() + e < K) ? (float)reg[e][q] : 0.0f;
+                const __bf16 b = (__bf16)v;
+                h[e] = b;
+                l[e] = (__bf16)(v - (float)b);
+            }
+            *(vkb *)&hi[r4() + q][kq()] = h;
+            *(vkb *)&lo[r4() + q][kq()] = l;
+        }
+    }
+};
+
 // One BM x BN output tile of C = alpha op(A) op(B) + beta Cin, computed by
 // the 256 threads of the calling workgroup (see gemm.hip for the design),
 // for fixed operand forms OPA, OPB (0: N, 1: T).
@@ -114,6 +225,16 @@ __device__ __forceinline__ void gemm_tile_op(const GemmProb &p, const int m0, co
     const int64_t ksa = OPA == 0 ? lda : 1;  // address step per unit of k
     const int64_t ksb = OPB == 0 ? 1 : ldb;
 
+    // split-BF16 operands take the vector paths: along k (A with op = T, B
+    // with op = N) or along the rows (A with op = N, B with op = T)
+    constexpr bool VA = MODE == CMP_BF16X3, VB = MODE == CMP_BF16X3;
+    typedef std::conditional_t<OPA == 1, SplitKRows<BM, TA>, SplitMRows<BM, TA>> VecA;
+    typedef std::conditional_t<OPB == 0, SplitKRows<BN, TA>, SplitMRows<BN, TA>> VecB;
+    VecA va;
+    VecB vb;
+    if constexpr (VA) va.init(p.A, lda, m0, M);
+    if constexpr (VB) vb.init(p.B, ldb, n0, N);
+
     const SELINV_GLOBAL TA *pa[LA];
     const SELINV_GLOBAL TA *pb[LB];
     {
@@ -137,24 +258,40 @@ __device__ __forceinline__ void gemm_tile_op(const GemmProb &p, const int m0, co
 #pragma unroll
         for (int j = 0; j < TN; j++) acc[i][j] = Acc{0, 0, 0, 0};
 
-    TA ra[LA], rb[LB];
+    TA ra[VA ? 1 : LA], rb[VB ? 1 : LB];
     auto gload = [&](int c) {
         const int k0 = c * BK;
+        if constexpr (VA) va.load(k0, K);
+        if constexpr (VB) vb.load(k0, K);
         if (k0 + BK <= K) {
+            if constexpr (!VA) {
 #pragma unroll
-            for (int t = 0; t < LA; t++) ra[t] = pa[t][k0 * ksa];
+                for (int t = 0; t < LA; t++) ra[t] = pa[t][k0 * ksa];
+            }
+            if constexpr (!VB) {
 #pragma unroll
-            for (int t = 0; t < LB; t++) rb[t] = pb[t][k0 * ksb];
+                for (int t = 0; t < LB; t++) rb[t] = pb[t][k0 * ksb];
+            }
         } else {
             // last, partial chunk: k clamped into the operand
+            if constexpr (!VA) {
 #pragma unroll
-            for (int t = 0; t < LA; t++) ra[t] = pa[t][(int64_t)(min(k0 + ak(t), K - 1) - ak(t)) * ksa];
+                for (int t = 0; t < LA; t++) ra[t] = pa[t][(int64_t)(min(k0 + ak(t), K - 1) - ak(t)) * ksa];
+            }
+            if constexpr (!VB) {
 #pragma unroll
-            for (int t = 0; t < LB; t++) rb[t] = pb[t][(int64_t)(min(k0 + bk(t), K - 1) - bk(t)) * ksb];
+                for (int t = 0; t < LB; t++) rb[t] = pb[t][(int64_t)(min(k0 + bk(t), K - 1) - bk(t)) * ksb];
+            }
         }
     };
     auto sstore = [&](int buf, int c) {
         const int k0 = c * BK;
+        if constexpr (VA) {
+            if constexpr (OPA == 1)
+                va.store(sm.ah[buf], sm.al[buf], m0, M, k0, K);
+            else
+                va.store(sm.ah[buf], sm.al[buf], k0, K);
+        } else {
 #pragma unroll
         for (int t = 0; t < LA; t++) {
             const int i = ai(t), k = ak(t);
@@ -167,6 +304,13 @@ __device__ __forceinline__ void gemm_tile_op(const GemmProb &p, const int m0, co
                 sm.a[buf][k][i] = v;
             }
         }
+        }
+        if constexpr (VB) {
+            if constexpr (OPB == 0)
+                vb.store(sm.bh[buf], sm.bl[buf], n0, N, k0, K);
+            else
+                vb.store(sm.bh[buf], sm.bl[buf], k0, K);
+        } else {
 #pragma unroll
         for (int t = 0; t < LB; t++) {
             const int j = bj(t), k = bk(t);
@@ -178,6 +322,7 @@ __device__ __forceinline__ void gemm_tile_op(const GemmProb &p, const int m0, co
             } else {
                 sm.b[buf][k][j] = v;
             }
+        }
         }
     };
     auto compute = [&](int buf) {
@@ -229,14 +374,18 @@ __device__ __forceinline__ void gemm_tile_op(const GemmProb &p, const int m0, co
         }
     };
 
-    // K == 0 (C = beta Cin): no chunk, no operand read
+    // K == 0 (C = beta Cin): no chunk, no operand read.  Chunks whose
+    // products are all zero by the operands' triangular structure are
+    // skipped (p.ktri).
     const int nch = (K + BK - 1) / BK;
-    if (nch > 0) {
-        gload(0);
-        sstore(0, 0);
+    const int klo = max((p.ktri & 1) ? n0 : 0, (p.ktri & 2) ? m0 : 0);
+    const int c0 = min(klo / BK, nch);
+    if (c0 < nch) {
+        gload(c0);
+        sstore(c0 & 1, c0);
     }
     __syncthreads();
-    for (int c = 0; c < nch; c++) {
+    for (int c = c0; c < nch; c++) {
         const int buf = c & 1;
         const bool more = c + 1 < nch;
         if (more) gload(c + 1);
@@ -274,6 +423,8 @@ __device__ __forceinline__ void gemm_tile_op(const GemmProb &p, const int m0, co
         }
         const int gm = m0 + wm * WM + i * 16 + (lane & 15);
         if (gm >= M) continue;
+        // complex blocks: the entry of the odd column that this one gives
+        const double csign = (gm & 1) ? -1.0 : 1.0;
 #pragma unroll
         for (int j = 0; j < TN; j++)
 #pragma unroll
@@ -283,6 +434,7 @@ __device__ __forceinline__ void gemm_tile_op(const GemmProb &p, const int m0, co
                 double r = alpha * (double)acc[i][j][v];
                 if (has_cin) r += beta * cin[j][v];
                 C[gm + (int64_t)gn * ldc] = (TC)r;
+                if (p.cpx) C[(gm ^ 1) + (int64_t)gn * ldc + ldc / 2] = (TC)(csign * r);
                 if constexpr (PUSH) acc[i][j][v] = (TC)r;  // the stored value, for the push below
             }
     }
@@ -305,15 +457,23 @@ __device__ __forceinline__ void gemm_tile_op(const GemmProb &p, const int m0, co
                     const int gm = m0 + wm * WM + i * 16 + (lane & 15);
                     if (gm >= M) continue;
                     const int a = posL[gm];
-                    if (a < 0) continue;
+                    // complex blocks: column gn of the problem is column 2 gn
+                    // of A^{-T}(P,P), and it gives entry (gm ^ 1, 2 gn + 1)
+                    const int a1 = p.cpx ? posL[gm ^ 1] : -1;
+                    const TG csign = (gm & 1) ? (TG)-1 : (TG)1;
 #pragma unroll
                     for (int j = 0; j < TN; j++)
 #pragma unroll
                         for (int v = 0; v < 4; v++) {
                             const int gn = row_n(j, v);
                             if (gn >= N) continue;
-                            const int b = posU[gn];
-                            if (b >= 0) G[a + b * clK] = (TG)acc[i][j][v];
+                            const int c = p.cpx ? 2 * gn : gn;
+                            const int b = posU[c];
+                            if (a >= 0 && b >= 0) G[a + b * clK] = (TG)acc[i][j][v];
+                            if (p.cpx) {
+                                const int b1 = posU[c + 1];
+                                if (a1 >= 0 && b1 >= 0) G[a1 + b1 * clK] = csign * (TG)acc[i][j][v];
+                            }
                         }
                 }
             }
