@@ -295,6 +295,30 @@ def column_entries(st, r):
     return np.concatenate(parts).astype(np.int64)
 
 
+def reference_columns_complex(s, w):
+    """As reference_columns for a complex matrix (held in its real form of
+    order 2n): columns of A^{-1} solved from the definition with a sparse
+    complex LU and refinement (oracle.complex_ref); the computed entries of
+    complex column j are the nodes of the real form's computed entries in row
+    q[2j]."""
+    import numpy as np
+    from oracle.complex_ref import solve_columns
+    st = s.structure()
+    xsup, lev, cl = st["xsup"], st["level"], np.diff(st["rl_ptr"])
+    ns = len(xsup) - 1
+    rows = [int(xsup[ns - 1]), int(xsup[ns]) - 2]
+    for d in (int(lev.max()) // 2, int(lev.max())):
+        ks = np.nonzero(lev == d)[0]
+        rows.append(int(xsup[ks[np.argmax(cl[ks])]]))
+    perm = st["perm"].astype(np.int64)
+    js = [int(perm[r]) // 2 for r in rows]
+    out = []
+    for r, j, x in zip(rows, js, solve_columns(w.n, w.colptr, w.rowind, w.values, js)):
+        i = np.unique(perm[column_entries(st, r)] // 2)
+        out.append((j, i, x[i], float("nan")))
+    return out
+
+
 def reference_columns(s, w):
     """Error reference at full size: a few columns of A^{-1} solved from the
     definition A x = e_j (oracle.sampled, certified bounds): the first and last
@@ -319,7 +343,7 @@ def reference_columns(s, w):
     return out
 
 
-def cpu_baseline(config, budget_s):
+def cpu_baseline(config, budget_s, w_full):
     """The oracle (steps 2-6: selected inversion and extraction) timed on the
     host cores.  Full matrix for the 2D configurations; for the 3D ones a
     smaller grid of the same recipe, so that the leg stays within about
@@ -338,7 +362,7 @@ def cpu_baseline(config, budget_s):
         w = config_grid("c2-sample", (32, 32, 32), "star", "convection", 0.1, None, 256, 64)
         sample = "32^3 7-point stencil of the 48^3 recipe (n=32768, supernodes<=256)"
     else:
-        w = get_config(config)
+        w = w_full
         sample = "full matrix"
     F = SelInv(w.n, w.colptr, w.rowind, w.perm, w.max_super, w.relax, w.pad_pct).info["flops"]
     o = Oracle(w.n, w.colptr, w.rowind, w.perm, w.max_super, w.relax, 0, w.pad_pct).factor(w.values)
@@ -636,9 +660,27 @@ def main():
         s.factor(w.values)  # back to the host factors for the error measurement
 
     # CPU baseline and error reference (the only leg that uses the oracle)
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and cplx:
+        # the supernodal oracle is real: complex matrices are checked against
+        # columns from the definition and have no CPU-baseline timing
+        if not args.no_errors:
+            cols = reference_columns_complex(s, w)
+            errs = {}
+            for p in [prec] + mixed_forms:
+                s.run(p, stream=stream, graph=graph)
+                X = np.concatenate([s.get_many(i, np.full(len(i), j)) for j, i, _, _ in cols])
+                R = np.concatenate([c[2] for c in cols])
+                D = np.concatenate([c[1] == c[0] for c in cols])
+                en = np.abs(X - R).max() / np.abs(R).max()
+                ed = (np.abs(X[D] - R[D]) / np.abs(R[D])).max()
+                errs[p] = float(max(en, ed))
+            res["max_rel_err"] = errs
+            res["max_rel_err_on"] = (f"every computed entry of {len(cols)} complex columns of A^-1 "
+                                     f"({sum(len(c[1]) for c in cols)} entries) against sparse complex LU "
+                                     f"solves with refinement; max(err_norm, err_diag)")
+    elif not args.no_cpu_baseline:
         print("# cpu baseline", file=sys.stderr, flush=True)
-        cb, (wo, o, sel_ref) = cpu_baseline(args.config, args.cpu_seconds)
+        cb, (wo, o, sel_ref) = cpu_baseline(args.config, args.cpu_seconds, w)
         res["cpu_baseline"] = cb
         if not args.no_errors:
             errs = {}
