@@ -236,6 +236,25 @@ selinv_status selinv_run_graph(selinv_handle h, selinv_precision prec, void *str
  * of that precision uses (-1: none built yet). */
 selinv_status selinv_set_sweep_mode(selinv_handle h, int32_t mode);
 
+/* Where the level sweep takes G_K = At^{-T}(R_L(K), R_U(K)) from (Fig. 3:
+ * the supernode's products need only those rows and columns of the blocks
+ * computed before it; Theorem 1 names the blocks they lie in).
+ *   0 (default): the tuning's choice per level (selinv_tune), a stored G
+ *     without a tuning;
+ *   1: a stored G: gather tiles copy G_K into a workspace that the products
+ *     of steps 3 and 5 then read;
+ *   2: no stored G on any level of large supernodes: the products of steps
+ *     3 and 5 read every entry of G_K from the diagonal block, L panel or U
+ *     panel that holds it, through a 32-bit source code per entry (built on
+ *     the first such run, c_L c_U codes per supernode, 4 bytes each, in
+ *     device memory from the handle's allocator; SELINV_E_NOMEM when that
+ *     fails).  Levels run by the fused small-supernode launch keep G_K in
+ *     LDS, and the persistent sweep always gathers into G.
+ * The results of forms 1 and 2 are equal bit for bit (the same values in the
+ * same order).  form outside 0..2: SELINV_E_INVALID_ARG.  Changing the form
+ * drops the cached work lists (and HIP graphs) of the handle. */
+selinv_status selinv_set_gather_form(selinv_handle h, int32_t form);
+
 /* Autotuner (the section on inter-supernode parallelism leaves the schedule
  * of a level's supernodes to the implementation).  Measures the launch
  * choices of the level sweep of one precision on the current device and on
@@ -247,6 +266,9 @@ selinv_status selinv_set_sweep_mode(selinv_handle h, int32_t mode);
  *     HIP events; every class keeps its fastest edge;
  *   - per level made only of small supernodes, the fused small-supernode
  *     launch or the per-phase launches;
+ *   - with gather form 0 and a level sweep, per level of large supernodes a
+ *     stored G or G_K read from its sources by the products (see
+ *     selinv_set_gather_form);
  *   - with sweep mode 0, the level sweep or the persistent sweep;
  *   - the prologue of the wide lower levels on a side stream beside the
  *     upper levels, or all of the prologue before the sweep;
@@ -265,19 +287,22 @@ selinv_status selinv_tune(selinv_handle h, selinv_precision prec, int32_t reps, 
                           double *ms_policy, double *ms_tuned);
 
 /* The tuning table of `prec` as int32 values:
- *   [3, nlevels, sweep form (0: the handle's mode, 1: levels, 2: persistent),
+ *   [4, nlevels, sweep form (0: the handle's mode, 1: levels, 2: persistent),
  *    tile of the inversion rounds, of the normalisation, of the diagonal
  *    initialisation, 1 if the whole prologue runs before the sweep (no side
  *    stream), tile-inversion items per launch on the side stream (0: one
  *    launch; at most 2^20), then for every level d = 0 .. nlevels-1: tile of
  *    steps 3+5, tile of step 4, 1 if the level's small supernodes use the
- *    per-phase launches],
- * tile 0 meaning the size policy.  *count receives 8 + 3 nlevels (0 when the
+ *    per-phase launches, 1 if its steps 3/5 read G_K from its sources
+ *    (gather form 0)],
+ * tile 0 meaning the size policy.  *count receives 8 + 4 nlevels (0 when the
  * handle is untuned; nothing written); out = NULL queries the count;
  * cap < count gives SELINV_E_INVALID_ARG.  selinv_set_tuning also takes the
- * earlier layouts [2, nlevels, sweep, tri, norm, dt, no_fork, per level ...]
- * (7 + 3 nlevels values, one side launch) and [1, nlevels, sweep, tri, norm,
- * dt, per level ...] (6 + 3 nlevels values, side stream kept). */
+ * earlier layouts, all with a stored G: [3, ... as above, per level the first
+ * three values] (8 + 3 nlevels values), [2, nlevels, sweep, tri, norm, dt,
+ * no_fork, per level ...] (7 + 3 nlevels values, one side launch) and [1,
+ * nlevels, sweep, tri, norm, dt, per level ...] (6 + 3 nlevels values, side
+ * stream kept). */
 selinv_status selinv_get_tuning(selinv_handle h, selinv_precision prec, int32_t *out, int32_t cap,
                                 int32_t *count);
 
@@ -302,9 +327,11 @@ int32_t selinv_sweep_is_persistent(selinv_handle h, selinv_precision prec);
  *   selinv_batch_run         eager launches on `stream`;
  *   selinv_batch_run_graph   the sweep recorded once into a HIP graph per
  *                            (batch, precision) and replayed;
- *   selinv_batch_set_sweep_mode, selinv_batch_tune, selinv_batch_get_tuning,
+ *   selinv_batch_set_sweep_mode, selinv_batch_set_gather_form,
+ *   selinv_batch_tune, selinv_batch_get_tuning,
  *   selinv_batch_set_tuning  as for a handle (selinv_set_sweep_mode,
- *                            selinv_tune, ...), over the batch's aligned
+ *                            selinv_set_gather_form, selinv_tune, ...),
+ *                            over the batch's aligned
  *                            levels (nlevels = the deepest matrix's);
  *   selinv_batch_set_profiling, selinv_batch_timings, selinv_batch_level_stats
  *                            as for a handle, for the batch's last eager run;
@@ -314,6 +341,7 @@ selinv_status selinv_batch_create(selinv_handle *hs, int32_t count, selinv_batch
 selinv_status selinv_batch_run(selinv_batch b, selinv_precision prec, void *stream);
 selinv_status selinv_batch_run_graph(selinv_batch b, selinv_precision prec, void *stream);
 selinv_status selinv_batch_set_sweep_mode(selinv_batch b, int32_t mode);
+selinv_status selinv_batch_set_gather_form(selinv_batch b, int32_t form);
 selinv_status selinv_batch_tune(selinv_batch b, selinv_precision prec, int32_t reps, void *stream,
                                 double *ms_policy, double *ms_tuned);
 selinv_status selinv_batch_get_tuning(selinv_batch b, selinv_precision prec, int32_t *out, int32_t cap,
@@ -414,11 +442,13 @@ selinv_status selinv_timings(selinv_handle h, double *ms, int32_t count);
  * small-supernode launch [10] supernodes, [11] flops of steps 3-5, [12]
  * entries of G gathered; [13] 1 when the level's gather tiles run in the
  * step-4 launch of the level above (the parent's step-4 product then writes
- * its diagonal block into the children's G), so that [5] is 0.  Algorithmic
+ * its diagonal block into the children's G), 2 when the level's step-3/5
+ * products read G_K from its sources (no stored G); [5] is 0 in both cases.  Algorithmic
  * HBM bytes (every operand read once, every result written once, e bytes per
  * element of the run's storage precision, 8 for diagonal blocks; a
  * materialised G is not counted, the sources it is gathered from are):
- * [14] of the steps-3+5 launch, e (c_L c_U + 2 s (c_L + c_U)) per supernode;
+ * [14] of the steps-3+5 launch, e (c_L c_U + 2 s (c_L + c_U)) per supernode,
+ * plus 4 c_L c_U (the source codes) when [13] is 2;
  * [15] of the step-4 launch, 2 e s c_U + 16 s^2 per supernode, plus
  * e c_L c_U for each supernode of the next level whose gather runs in it;
  * [16] of the standalone gather, e c_L c_U per supernode; [17] of the

@@ -1,7 +1,8 @@
 """Cache of the library's measured launch choices (selinv_tune).
 
 The tuning table of a handle (tile edge per launch class, fused or per-phase
-launches for the levels of small supernodes, sweep form) depends on the
+launches for the levels of small supernodes, stored G or G read from its
+sources per level, sweep form) depends on the
 plan's shape, the precision, the device and the library build.  ``tuned``
 looks the table up in a JSON file under that key and installs it, or runs
 the tuner and stores the result.
@@ -77,11 +78,13 @@ def describe(table: list) -> dict:
     if not table:
         return {"tuned": False}
     L = table[1]
-    hd = {3: 8, 2: 7}.get(table[0], 6)
-    per = [table[hd + 3 * d: hd + 3 + 3 * d] for d in range(L)]
+    hd = {4: 8, 3: 8, 2: 7}.get(table[0], 6)
+    pl = 4 if table[0] == 4 else 3
+    per = [table[hd + pl * d: hd + pl + pl * d] for d in range(L)]
     return {"tuned": True, "sweep": {0: "handle", 1: "levels", 2: "persistent"}[table[2]],
             "prologue_tiles": {"tri": table[3], "norm": table[4], "diag_init": table[5]},
             "prologue_side_stream": not (hd >= 7 and table[6] == 1),
             "side_inversion_chunk": table[7] if hd == 8 else 0,
             "steps35_tiles": [p[0] for p in per], "step4_tiles": [p[1] for p in per],
-            "small_per_phase_levels": [d for d, p in enumerate(per) if p[2]]}
+            "small_per_phase_levels": [d for d, p in enumerate(per) if p[2]],
+            "gather_in_products_levels": [d for d, p in enumerate(per) if pl == 4 and p[3]]}

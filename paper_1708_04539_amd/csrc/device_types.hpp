@@ -42,6 +42,10 @@ struct MatDev {
     // gcL[c_off + a + b cl] for the diagonal-block and L-side entries,
     // gcU[c_off + b + a cu] for the U-side entries of G_K(a, b)
     const uint32_t *gcL, *gcU;
+    // source codes of every entry of G_K in the layout of G_K itself (all
+    // three arrays, gcA[ca_off(K) + a + b c_L]), read by the step-3/5 products
+    // that take G_K from its sources instead of a stored G (GemmProb::gcode)
+    const uint32_t *gcA;
 };
 
 // gather: tile of G_K rows [a0, a0+64) x columns [b0, b0+64); entries from
@@ -81,6 +85,11 @@ struct GemmProb {
     // (m, 2j) also gives the entry (m ^ 1, 2j + 1), at ldc / 2 past it: the
     // same value for even m, its negative for odd m (in either orientation)
     int32_t cpx;
+    // gcode >= 0: op(A) is G_K of matrix gmat, not read from A: its entry
+    // (a, b) is the value that the code gcA[gcode + a + b lda] names (A is then
+    // unused; a step-3 or step-5 product, op(B) = B)
+    int32_t gmat;
+    int64_t gcode;
     double alpha, beta;
 };
 

@@ -54,6 +54,43 @@ __global__ __launch_bounds__(256) void gemm_v2(const GemmProb *__restrict__ prob
     gemm_tile<MODE, BM, BN, TA, TC, ROLE == 2>(probs[tl.prob], tl.m0, tl.n0, sm);
 }
 
+// Steps 3 and 5 of a level whose G_K are not stored: op(A) is read from the
+// ancestors' blocks through the source codes (see gemm_tile_g35).
+template <int MODE, int BM, int BN, typename TA>
+__global__ __launch_bounds__(256) void gemm_g35(const GemmProb *__restrict__ probs,
+                                                const GemmTile *__restrict__ tiles,
+                                                const MatDev *__restrict__ mats) {
+    __shared__ Smem<MODE, BM, BN> sm;
+    const GemmTile tl = tiles[xcd_tile(blockIdx.x, gridDim.x)];
+    gemm_tile_g35<MODE, BM, BN, TA>(probs[tl.prob], tl.m0, tl.n0, sm, mats);
+}
+
+template <int MODE, typename TA>
+static void launch_g35_mode(int tile, const GemmProb *probs, const GemmTile *tiles, int ntiles, const MatDev *mats,
+                            hipStream_t st) {
+    if (tile == GEMM_TILE_128)
+        hipLaunchKernelGGL((gemm_g35<MODE, 128, 128, TA>), dim3(ntiles), dim3(256), 0, st, probs, tiles, mats);
+    else if (tile == GEMM_TILE_64)
+        hipLaunchKernelGGL((gemm_g35<MODE, 64, 64, TA>), dim3(ntiles), dim3(256), 0, st, probs, tiles, mats);
+    else
+        hipLaunchKernelGGL((gemm_g35<MODE, 32, 32, TA>), dim3(ntiles), dim3(256), 0, st, probs, tiles, mats);
+}
+
+hipError_t launch_gemm_g35(int mode, int tile, const GemmProb *probs, const GemmTile *tiles, int ntiles,
+                           const MatDev *mats, hipStream_t st) {
+    if (ntiles <= 0) return hipSuccess;
+    if (tile != GEMM_TILE_32 && tile != GEMM_TILE_64 && tile != GEMM_TILE_128) return hipErrorInvalidValue;
+    if (mode == CMP_F64)
+        launch_g35_mode<CMP_F64, double>(tile, probs, tiles, ntiles, mats, st);
+    else if (mode == CMP_F32)
+        launch_g35_mode<CMP_F32, float>(tile, probs, tiles, ntiles, mats, st);
+    else if (mode == CMP_BF16X3)
+        launch_g35_mode<CMP_BF16X3, float>(tile, probs, tiles, ntiles, mats, st);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
 template <int MODE, typename TA, typename TC, int ROLE>
 static void launch_mode(int tile, const GemmProb *probs, const GemmTile *tiles, int ntiles, hipStream_t st) {
     if (tile == GEMM_TILE_128)

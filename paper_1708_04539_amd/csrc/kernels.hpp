@@ -31,6 +31,11 @@ enum : int {
 hipError_t launch_gemm(int role, int mode, int tile, const GemmProb *probs, const GemmTile *tiles, int ntiles,
                        hipStream_t st);
 hipError_t launch_gather(int f64, const MatDev *mats, const GatherTile *tiles, int ntiles, hipStream_t st);
+// steps 3 and 5 with G_K read from its sources through the codes of
+// mats[p.gmat].gcA (every problem has gcode >= 0 and opB = 0), results in the
+// storage precision of the mode (gemm.hip)
+hipError_t launch_gemm_g35(int mode, int tile, const GemmProb *probs, const GemmTile *tiles, int ntiles,
+                           const MatDev *mats, hipStream_t st);
 // step-4 product tiles of one level (pushing into the children's G) and the
 // next level's gather tiles in one launch (gemm.hip)
 hipError_t launch_step4_gather(int mode, int tile, const GemmProb *probs, const GemmTile *tiles, int ntiles,

@@ -16,11 +16,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <memory>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "device_types.hpp"
@@ -121,6 +123,9 @@ struct Sweep {
     // d (fused[d + 1]); those products push A^{-T}(P,P) into the children's G
     std::vector<Range> g4gat;
     std::vector<char> fused;
+    // levels whose steps 3/5 read G_K from its sources (launch_gemm_g35); they
+    // have no gather tiles and their parents push nothing
+    std::vector<char> vg;
     SmallItem *d_small = nullptr;
     std::vector<double> lev_flops35, lev_flops4, lev_gather_elems;  // launches of the large supernodes
     std::vector<double> lev_small_flops, lev_small_elems;          // the fused small-supernode launch
@@ -171,6 +176,7 @@ struct Tuning {
     int tri = 0, norm = 0, dt = 0;  // prologue: doubling rounds, normalisation, diagonal init
     std::vector<int> t35, t4;       // per level: steps 3+5, step 4 (+ the next level's gather)
     std::vector<char> no_small;     // per level: 1 = per-phase launches for its small supernodes
+    std::vector<char> vg;           // per level: 1 = steps 3/5 read G_K from its sources (no stored G)
     int sweep = SWEEP_AUTO;         // SWEEP_LEVELS / SWEEP_PERSISTENT, or the handle's own mode
     int no_fork = 0;                // 1: the whole prologue before the sweep, no side stream
     int side_chunk = 0;             // tile-inversion items per launch on the side stream (0: one launch)
@@ -188,6 +194,10 @@ struct Runner {
     std::unique_ptr<Sweep> sweep[3];
     Tuning tune[3];
     int sweep_mode = 0;
+    // where G_K comes from: 0 the tuning's choice per level (stored without
+    // one), 1 always a stored G, 2 its sources inside the step-3/5 products
+    // on every level that allows it
+    int gather_form = 0;
     bool profiling = false;
     std::vector<hipEvent_t> events;
     hipStream_t own_stream = nullptr;
@@ -270,6 +280,14 @@ struct selinv_handle_s {
     // source codes of the gather (see MatDev)
     std::vector<uint32_t> gcL, gcU;
     uint32_t *d_gcL = nullptr, *d_gcU = nullptr;
+    // codes of every G_K in the layout of G_K (MatDev::gcA) for the products
+    // that read G_K from its sources: built on first use (ca_state 0 not yet,
+    // 1 built, -1 unavailable: offsets beyond the code's 30 bits); ca_off[K]
+    // its first code (-1: c_L or c_U is 0), ca_total the code count
+    std::vector<int64_t> ca_off;
+    int64_t ca_total = 0;
+    uint32_t *d_gcA = nullptr;
+    int ca_state = 0;
     int64_t *d_push_off = nullptr;
     PrecBufs pb[NPREC];
     Runner run;  // the handle's own sweeps (hs = {this})
@@ -443,6 +461,8 @@ int add_prob(std::vector<GemmProb> &probs, const void *A, int opA, int lda,
     p.push_mat = -1;
     p.ktri = ktri;
     p.cpx = 0;
+    p.gmat = -1;
+    p.gcode = -1;
     p.alpha = alpha;
     p.beta = beta;
     probs.push_back(p);
@@ -464,6 +484,7 @@ bool persist_auto(const std::vector<selinv_handle> &hs) {
 }
 
 GatherTile gather_tile_of(selinv_handle h, int32_t mi, int32_t K, int a0, int b0, int32_t skip);
+selinv_status ensure_codes_all(selinv_handle h);
 
 // A supernode whose diagonal block, R_L and R_U all fit one 64-wide tile has
 // its normalisation and diagonal initialisation done by the workgroup that
@@ -472,11 +493,36 @@ inline bool fused_prologue(const SnRec &r) { return r.s <= 64 && r.cl <= 64 && r
 
 // Build the work lists of one sweep over a set of factored handles.
 selinv_status build_sweep(std::vector<selinv_handle> &hs, const DevAlloc &al, int prec, int sweep_mode,
-                          std::unique_ptr<Sweep> &out, std::string &err, const Tuning *tn = nullptr) {
+                          std::unique_ptr<Sweep> &out, std::string &err, const Tuning *tn = nullptr,
+                          int gather_form = 0) {
     if (tn && !tn->set) tn = nullptr;
     auto t35_of = [&](int d) { return tn && d < (int)tn->t35.size() ? tn->t35[d] : 0; };
     auto t4_of = [&](int d) { return tn && d < (int)tn->t4.size() ? tn->t4[d] : 0; };
     if (tn && sweep_mode == SWEEP_AUTO && tn->sweep != SWEEP_AUTO) sweep_mode = tn->sweep;
+    // Levels whose steps 3/5 read G_K from its sources (no stored G): those
+    // the gather form asks for (2 every level, 1 none, 0 the tuning's
+    // choice), in a level sweep only (the persistent sweep gathers), and
+    // never a level of the fused small-supernode launch (decided below).
+    bool vg_ok = sweep_mode == SWEEP_LEVELS || (sweep_mode == SWEEP_AUTO && !persist_auto(hs));
+    auto vg_wanted = [&](int d) {
+        return gather_form == 2 || (gather_form == 0 && tn && d < (int)tn->vg.size() && tn->vg[d]);
+    };
+    {
+        int dmax = 0;
+        for (auto h : hs) dmax = std::max(dmax, h->P.nlevels);
+        bool any = false;
+        for (int d = 0; vg_ok && d < dmax; d++) any |= vg_wanted(d);
+        vg_ok = vg_ok && any;
+        for (auto h : hs) {
+            if (!vg_ok) break;
+            selinv_status st = ensure_codes_all(h);
+            if (st) {
+                err = h->err;
+                return st;
+            }
+            vg_ok = h->ca_state == 1;
+        }
+    }
     std::unique_ptr<Sweep> S(new Sweep());
     S->al = al;
     S->prec = prec;
@@ -537,6 +583,7 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, const DevAlloc &al, in
         m.push_pos = h->d_push_pos;
         m.gcL = h->d_gcL;
         m.gcU = h->d_gcU;
+        m.gcA = h->d_gcA;
         m.Zd = b.Zd;
         m.ZL = b.ZL;
         m.ZU = b.ZU;
@@ -770,6 +817,11 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, const DevAlloc &al, in
         for (int d = 1; d < hs[mi]->P.nlevels; d++)
             for (int32_t K : hs[mi]->P.levels[d])
                 if (!hs[mi]->P.one_top[K]) S->fused[d] = 0;
+    S->vg.assign(depth, 0);
+    for (int d = 0; d < depth; d++) {
+        S->vg[d] = vg_ok && !level_small[d] && vg_wanted(d);
+        if (S->vg[d]) S->fused[d] = 0;
+    }
     // Split-K of the step-4 products (s x s, k = c_U) on levels whose step-4
     // launch cannot fill the device: the parts write FP64 partial products
     // that a reduction launch adds to A^{-T}(K,K) in a fixed order.  The next
@@ -823,7 +875,7 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, const DevAlloc &al, in
             for (int32_t K : h->P.levels[d]) {
                 const SnRec &r = h->sn[K];
                 if (!is_small(r)) {
-                    if (!S->fused[d])
+                    if (!S->fused[d] && !S->vg[d])
                         for (int b0 = 0; b0 < r.cu; b0 += 64)
                             for (int a0 = 0; a0 < r.cl; a0 += 64)
                                 gts.push_back(gather_tile_of(h, (int32_t)mi, K, a0, b0, -1));
@@ -866,6 +918,19 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, const DevAlloc &al, in
                     if (half) {
                         halve(prob_zu[gid], ZU, r.cu, r.s, e);
                         halve(prob_zl[gid], ZL, r.cl, r.s, e);
+                    }
+                    if (S->vg[d]) {
+                        // op(A) = G_K from its sources: gcA[ca_off(K) + a + b c_L]
+                        const int64_t co = h->ca_off.empty() ? -1 : h->ca_off[K];
+                        if (is_small(r) || (co >= 0 && co + (int64_t)r.cl * r.cu > h->ca_total)) X.violations++;
+                        for (int pi : {prob_zu[gid], prob_zl[gid]}) {
+                            if (pi < 0) continue;
+                            GemmProb &q = probs[pi];
+                            if (q.opB != 0 || q.lda != std::max(r.cl, 1) || (co < 0 && q.K > 0)) X.violations++;
+                            q.gmat = (int32_t)mi;
+                            q.gcode = co >= 0 ? co : 0;
+                        }
+                        S->lev_bytes35[d] += 4.0 * r.cl * (double)r.cu;  // the codes
                     }
                     (pass == 0 ? S->lev_flops35[d] : S->lev_small_flops[d]) +=
                         4.0 * r.s * (double)r.cl * r.cu / (half ? 2 : 1);
@@ -984,6 +1049,7 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, const DevAlloc &al, in
     }
     for (int d = 0; d < depth; d++) {
         const double src = e * S->lev_gather_elems[d];
+        if (S->vg[d]) continue;  // the sources are the G operand of the level's steps 3/5
         if (d > 0 && S->fused[d])
             S->lev_bytes4[d - 1] += src;
         else
@@ -1214,8 +1280,14 @@ hipError_t launch_sweep(const Sweep &S, hipStream_t st, std::vector<hipEvent_t> 
         mark(4 + 4 * d);
         if ((e = launch_gather(f64, S.d_mats, S.d_gt + S.gat[d].off, S.gat[d].count, st))) return e;
         mark(5 + 4 * d);
-        if ((e = launch_gemm(GEMM_STEP35, mode, S.g35[d].tile, S.d_probs, S.d_tiles + S.g35[d].off,
-                             S.g35[d].count, st))) return e;
+        if (S.vg[d]) {
+            if ((e = launch_gemm_g35(mode, S.g35[d].tile, S.d_probs, S.d_tiles + S.g35[d].off, S.g35[d].count,
+                                     S.d_mats, st)))
+                return e;
+        } else if ((e = launch_gemm(GEMM_STEP35, mode, S.g35[d].tile, S.d_probs, S.d_tiles + S.g35[d].off,
+                                    S.g35[d].count, st))) {
+            return e;
+        }
         mark(6 + 4 * d);
         if ((e = launch_step4_gather(mode, S.g4[d].tile, S.d_probs, S.d_tiles + S.g4[d].off, S.g4[d].count,
                                      S.d_mats, S.d_gt + S.g4gat[d].off, S.g4gat[d].count, st)))
@@ -1293,6 +1365,20 @@ selinv_status complex_embedding(int64_t n, const int64_t *colptr, const int32_t 
 // bits, else no codes at all.
 constexpr int64_t kCodeBudget = int64_t(1) << 26;
 
+// Source code of entry (a, b) of G_K, where column b of R_U(K) is node c of
+// supernode J (first node fJ): array << 30 | element offset.
+inline uint32_t gcode_of(const Plan &P, int32_t K, int64_t a, int64_t b, int32_t c, int32_t J, int32_t fJ) {
+    const int32_t r = P.rl[P.rl_ptr[K] + a], I = P.supof[r];
+    if (I == J)  // diagonal block of J
+        return (1u << GCODE_SHIFT) | (uint32_t)(P.off_d[J] + int64_t(c - fJ) * P.width(J) + (r - fJ));
+    if (I > J)  // row r in the L panel of J
+        return (2u << GCODE_SHIFT) |
+               (uint32_t)(P.off_l[J] + int64_t(c - fJ) * P.cl(J) + P.mapL[P.l_coloff[P.ru_ptr[K] + b] + a]);
+    // column c in the U panel of I
+    return (3u << GCODE_SHIFT) |
+           (uint32_t)(P.off_u[I] + int64_t(r - P.xsup[I]) * P.cu(I) + P.mapU[P.u_rowoff[P.rl_ptr[K] + a] + b]);
+}
+
 void build_gather_codes(const Plan &P, std::vector<SnRec> &sn, std::vector<uint32_t> &gcL,
                         std::vector<uint32_t> &gcU, int64_t budget) {
     gcL.clear();
@@ -1315,26 +1401,66 @@ void build_gather_codes(const Plan &P, std::vector<SnRec> &sn, std::vector<uint3
     for (int32_t K = 0; K < P.ns; K++) {
         const int64_t co = sn[K].c_off, cl = P.cl(K), cu = P.cu(K);
         if (co < 0) continue;
-        const int32_t *RL = P.rl.data() + P.rl_ptr[K], *RU = P.ru.data() + P.ru_ptr[K];
         for (int64_t b = 0; b < cu; b++) {
-            const int32_t c = RU[b], J = P.supof[c], fJ = P.xsup[J];
+            const int32_t c = P.ru[P.ru_ptr[K] + b], J = P.supof[c], fJ = P.xsup[J];
             for (int64_t a = 0; a < cl; a++) {
-                const int32_t r = RL[a], I = P.supof[r];
-                if (I == J) {
-                    const int64_t off = P.off_d[J] + int64_t(c - fJ) * P.width(J) + (r - fJ);
-                    gcL[co + a + b * cl] = (1u << GCODE_SHIFT) | (uint32_t)off;
-                } else if (I > J) {
-                    const int64_t m = P.l_coloff[P.ru_ptr[K] + b] + a;
-                    const int64_t off = P.off_l[J] + int64_t(c - fJ) * P.cl(J) + P.mapL[m];
-                    gcL[co + a + b * cl] = (2u << GCODE_SHIFT) | (uint32_t)off;
-                } else {
-                    const int64_t m = P.u_rowoff[P.rl_ptr[K] + a] + b;
-                    const int64_t off = P.off_u[I] + int64_t(r - P.xsup[I]) * P.cu(I) + P.mapU[m];
-                    gcU[co + b + a * cu] = (3u << GCODE_SHIFT) | (uint32_t)off;
-                }
+                const uint32_t code = gcode_of(P, K, a, b, c, J, fJ);
+                if ((code >> GCODE_SHIFT) == 3)
+                    gcU[co + b + a * cu] = code;
+                else
+                    gcL[co + a + b * cl] = code;
             }
         }
     }
+}
+
+// The codes of every G_K in its own layout (MatDev::gcA), built once per
+// handle on first use: filled by up to 16 host threads over the supernodes,
+// uploaded, and the host copy released.
+selinv_status ensure_codes_all(selinv_handle h) {
+    if (h->ca_state != 0) return SELINV_OK;
+    const Plan &P = h->P;
+    const int64_t lim = int64_t(GCODE_MASK) + 1;
+    if (P.tot_d > lim || P.tot_l > lim || P.tot_u > lim) {
+        h->ca_state = -1;
+        return SELINV_OK;
+    }
+    h->ca_off.assign(P.ns, -1);
+    int64_t used = 0;
+    for (int32_t K = 0; K < P.ns; K++) {
+        const int64_t cl = P.cl(K), cu = P.cu(K);
+        if (cl == 0 || cu == 0) continue;
+        h->ca_off[K] = used;
+        used += cl * cu;
+    }
+    std::vector<uint32_t> codes;
+    try {
+        codes.resize(std::max<int64_t>(used, 1));
+    } catch (const std::bad_alloc &) {
+        h->err = "host allocation failed for the gather codes";
+        return SELINV_E_NOMEM;
+    }
+    std::atomic<int32_t> next{0};
+    auto work = [&]() {
+        for (int32_t K; (K = next.fetch_add(1)) < P.ns;) {
+            const int64_t co = h->ca_off[K], cl = P.cl(K), cu = P.cu(K);
+            if (co < 0) continue;
+            for (int64_t b = 0; b < cu; b++) {
+                const int32_t c = P.ru[P.ru_ptr[K] + b], J = P.supof[c], fJ = P.xsup[J];
+                uint32_t *col = codes.data() + co + b * cl;
+                for (int64_t a = 0; a < cl; a++) col[a] = gcode_of(P, K, a, b, c, J, fJ);
+            }
+        }
+    };
+    const unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::vector<std::thread> pool;
+    for (unsigned t = 1; t < nt; t++) pool.emplace_back(work);
+    work();
+    for (auto &t : pool) t.join();
+    HIPCHK(h->err, upload(h->al, &h->d_gcA, codes), "upload gather codes");
+    h->ca_total = used;
+    h->ca_state = 1;
+    return SELINV_OK;
 }
 
 // Gather tile of supernode K of handle h (matrix mi of the sweep); skip: the
@@ -1890,7 +2016,7 @@ static selinv_status check_run(selinv_handle h, int prec) {
 // ---------------------------------------------------------------------------
 static selinv_status runner_ensure(Runner &R, int prec, std::string &err) {
     if (R.sweep[prec]) return SELINV_OK;
-    return build_sweep(R.hs, R.al, prec, R.sweep_mode, R.sweep[prec], err, &R.tune[prec]);
+    return build_sweep(R.hs, R.al, prec, R.sweep_mode, R.sweep[prec], err, &R.tune[prec], R.gather_form);
 }
 
 static void runner_drop(Runner &R, int prec) {
@@ -1990,7 +2116,7 @@ static void level_stats_of(const Sweep &S, int32_t level, double *stats) {
     stats[10] = S.small[level].count;
     stats[11] = S.lev_small_flops[level];
     stats[12] = S.lev_small_elems[level];
-    stats[13] = S.fused[level];
+    stats[13] = S.vg[level] ? 2 : S.fused[level];
     stats[14] = S.lev_bytes35[level];
     stats[15] = S.lev_bytes4[level];
     stats[16] = S.lev_bytes_gather[level];
@@ -2078,6 +2204,7 @@ static selinv_status runner_tune(Runner &R, int prec, int32_t reps, hipStream_t 
     best.t35.assign(L, 0);
     best.t4.assign(L, 0);
     best.no_small.assign(L, 0);
+    best.vg.assign(L, 0);
     best.sweep = R.sweep_mode == SWEEP_AUTO ? SWEEP_LEVELS : SWEEP_AUTO;
     const int cand[3] = {GEMM_TILE_32, GEMM_TILE_64, GEMM_TILE_128};
     std::vector<double> bt(3 + 2 * L, 1e300);
@@ -2126,6 +2253,29 @@ static selinv_status runner_tune(Runner &R, int prec, int32_t reps, hipStream_t 
                 return v;
             };
             best.no_small[d] = lev(poff) < 0.97 * lev(pon);
+        }
+    }
+    // 2b. levels of large supernodes: a stored G (gather launch or the gather
+    //     tiles in the step-4 launch above) or G_K read from its sources by
+    //     the step-3/5 products, compared as in 2.  Only under the tuning's
+    //     own choice of gather form, and only for a level sweep.
+    if (R.gather_form == 0 && R.sweep_mode != SWEEP_PERSISTENT) {
+        Tuning on = best, off = best;
+        on.sweep = off.sweep = SWEEP_LEVELS;
+        std::fill(on.vg.begin(), on.vg.end(), 1);
+        std::vector<double> pon, poff;
+        R.tune[prec] = on;
+        if ((st = tune_measure(R, prec, s, reps, true, t, &pon, err))) return st;
+        R.tune[prec] = off;
+        if ((st = tune_measure(R, prec, s, reps, true, t, &poff, err))) return st;
+        for (int d = 0; d < L; d++) {
+            auto lev = [&](const std::vector<double> &p) {
+                double v = 0;
+                for (int i = 0; i < 4; i++) v += p[3 + 4 * d + i];
+                if (d > 0) v += p[3 + 4 * (d - 1) + 3];
+                return v;
+            };
+            best.vg[d] = lev(pon) < 0.97 * lev(poff);
         }
     }
     // 3. the sweep form, where the persistent sweep is available
@@ -2183,6 +2333,7 @@ static selinv_status runner_tune(Runner &R, int prec, int32_t reps, hipStream_t 
         pol.t35.assign(L, 0);
         pol.t4.assign(L, 0);
         pol.no_small.assign(L, 0);
+        pol.vg.assign(L, 0);
         best = pol;
         t_best = t_policy;
     }
@@ -2193,21 +2344,21 @@ static selinv_status runner_tune(Runner &R, int prec, int32_t reps, hipStream_t 
     return SELINV_OK;
 }
 
-// flat form: [3, nlevels, sweep, tri, norm, dt, no_fork, side_chunk, then per
-// level: t35, t4, no_small] (tables of the earlier layouts, without
-// side_chunk (2) or without no_fork as well (1), are still accepted)
+// flat form: [4, nlevels, sweep, tri, norm, dt, no_fork, side_chunk, then per
+// level: t35, t4, no_small, vg] (tables of the earlier layouts are still
+// accepted: 3 without vg, 2 without side_chunk as well, 1 without no_fork)
 static selinv_status runner_get_tuning(const Runner &R, int prec, int32_t *out, int32_t cap, int32_t *count,
                                        std::string &err) {
     const Tuning &tn = R.tune[prec];
     const int L = R.depth();
-    *count = tn.set ? 8 + 3 * L : 0;
+    *count = tn.set ? 8 + 4 * L : 0;
     if (!tn.set || !out) return SELINV_OK;
     if (cap < *count) {
         err = "tuning buffer too small";
         return SELINV_E_INVALID_ARG;
     }
     int32_t *o = out;
-    *o++ = 3;
+    *o++ = 4;
     *o++ = L;
     *o++ = tn.sweep;
     *o++ = tn.tri;
@@ -2219,6 +2370,7 @@ static selinv_status runner_get_tuning(const Runner &R, int prec, int32_t *out, 
         *o++ = tn.t35[d];
         *o++ = tn.t4[d];
         *o++ = tn.no_small[d];
+        *o++ = d < (int)tn.vg.size() ? tn.vg[d] : 0;
     }
     return SELINV_OK;
 }
@@ -2231,13 +2383,14 @@ static selinv_status runner_set_tuning(Runner &R, int prec, const int32_t *in, i
     }
     const int L = R.depth();
     auto tile_ok = [](int v) { return v == 0 || v == GEMM_TILE_32 || v == GEMM_TILE_64 || v == GEMM_TILE_128; };
-    const int ver = in && count > 0 ? in[0] : 0, hd = ver == 3 ? 8 : ver == 2 ? 7 : 6;
-    bool ok = in && ver >= 1 && ver <= 3 && count == hd + 3 * L && in[1] == L && in[2] >= SWEEP_AUTO &&
+    const int ver = in && count > 0 ? in[0] : 0, hd = ver >= 3 ? 8 : ver == 2 ? 7 : 6, pl = ver == 4 ? 4 : 3;
+    bool ok = in && ver >= 1 && ver <= 4 && count == hd + pl * L && in[1] == L && in[2] >= SWEEP_AUTO &&
               in[2] <= SWEEP_PERSISTENT && tile_ok(in[3]) && tile_ok(in[4]) && tile_ok(in[5]) &&
               (ver == 1 || in[6] == 0 || in[6] == 1) && (ver < 3 || (in[7] >= 0 && in[7] <= (1 << 20)));
     for (int d = 0; ok && d < L; d++)
-        ok = tile_ok(in[hd + 3 * d]) && tile_ok(in[hd + 1 + 3 * d]) &&
-             (in[hd + 2 + 3 * d] == 0 || in[hd + 2 + 3 * d] == 1);
+        ok = tile_ok(in[hd + pl * d]) && tile_ok(in[hd + 1 + pl * d]) &&
+             (in[hd + 2 + pl * d] == 0 || in[hd + 2 + pl * d] == 1) &&
+             (pl == 3 || in[hd + 3 + pl * d] == 0 || in[hd + 3 + pl * d] == 1);
     if (!ok) {
         err = "tuning table does not fit (layout, level count, tile edges or sweep form)";
         return SELINV_E_INVALID_ARG;
@@ -2249,14 +2402,24 @@ static selinv_status runner_set_tuning(Runner &R, int prec, const int32_t *in, i
     tn.norm = in[4];
     tn.dt = in[5];
     tn.no_fork = ver >= 2 ? in[6] : 0;
-    tn.side_chunk = ver == 3 ? in[7] : 0;
+    tn.side_chunk = ver >= 3 ? in[7] : 0;
     for (int d = 0; d < L; d++) {
-        tn.t35.push_back(in[hd + 3 * d]);
-        tn.t4.push_back(in[hd + 1 + 3 * d]);
-        tn.no_small.push_back((char)in[hd + 2 + 3 * d]);
+        tn.t35.push_back(in[hd + pl * d]);
+        tn.t4.push_back(in[hd + 1 + pl * d]);
+        tn.no_small.push_back((char)in[hd + 2 + pl * d]);
+        tn.vg.push_back(pl == 4 ? (char)in[hd + 3 + pl * d] : 0);
     }
     R.tune[prec] = tn;
     runner_drop(R, prec);
+    return SELINV_OK;
+}
+
+static selinv_status runner_set_gather_form(Runner &R, int32_t form) {
+    if (form < 0 || form > 2) return SELINV_E_INVALID_ARG;
+    if (form != R.gather_form) {
+        R.gather_form = form;
+        for (int p = 0; p < NPREC; p++) runner_drop(R, p);
+    }
     return SELINV_OK;
 }
 
@@ -2287,6 +2450,11 @@ selinv_status selinv_run_graph(selinv_handle h, selinv_precision prec, void *str
 selinv_status selinv_set_sweep_mode(selinv_handle h, int32_t mode) {
     if (!h) return SELINV_E_INVALID_ARG;
     return runner_set_mode(h->run, mode);
+}
+
+selinv_status selinv_set_gather_form(selinv_handle h, int32_t form) {
+    if (!h) return SELINV_E_INVALID_ARG;
+    return runner_set_gather_form(h->run, form);
 }
 
 int32_t selinv_sweep_is_persistent(selinv_handle h, selinv_precision prec) {
@@ -2721,7 +2889,8 @@ void selinv_destroy(selinv_handle h) {
                     (void *)h->d_tl, (void *)h->d_tu,
                     (void *)h->d_sn, (void *)h->d_supof, (void *)h->d_rl, (void *)h->d_ru, (void *)h->d_mapL,
                     (void *)h->d_mapU, (void *)h->d_lcol, (void *)h->d_urow, (void *)h->d_aloc, (void *)h->d_aloc_c,
-                    (void *)h->d_kids_ptr, (void *)h->d_kids, (void *)h->d_push_off, (void *)h->d_push_pos, (void *)h->d_gcL, (void *)h->d_gcU})
+                    (void *)h->d_kids_ptr, (void *)h->d_kids, (void *)h->d_push_off, (void *)h->d_push_pos,
+                    (void *)h->d_gcL, (void *)h->d_gcU, (void *)h->d_gcA})
         h->al.put(q);
     delete h;
 }
@@ -2764,6 +2933,11 @@ selinv_status selinv_batch_run_graph(selinv_batch b, selinv_precision prec, void
     selinv_status st = check_batch(b, prec);
     if (st) return st;
     return runner_launch(b->run, prec, (hipStream_t)stream, true, b->err);
+}
+
+selinv_status selinv_batch_set_gather_form(selinv_batch b, int32_t form) {
+    if (!b) return SELINV_E_INVALID_ARG;
+    return runner_set_gather_form(b->run, form);
 }
 
 selinv_status selinv_batch_set_sweep_mode(selinv_batch b, int32_t mode) {

@@ -201,8 +201,13 @@ struct SplitMRows {
 // PUSH: a step-4 product with push_sn >= 0 also writes its final entries of
 // A^{-T}(P,P) into G of each child of P (converted to the storage type TG,
 // as the gather would), so that the children's gather can run beside it.
+// GA: op(A) is G_K, taken from its sources through its codes (GemmProb::gcode)
+// instead of a stored G.  The codes of chunk c + 1 are loaded with the values
+// of chunk c, so that the values' addresses are in registers one chunk ahead
+// and the loop keeps one round trip per chunk in flight, as for a stored
+// operand.  The staged values equal those the gather would have stored.
 template <int MODE, int BM, int BN, typename TA, typename TC, bool CIN, int BK, int OPA, int OPB, bool PUSH,
-          typename TG>
+          typename TG, bool GA = false>
 __device__ __forceinline__ void gemm_tile_op(const GemmProb &p, const int m0, const int n0,
                                              Smem<MODE, BM, BN, BK> &sm, const MatDev *mats) {
     typedef typename Mode<MODE>::T T;
@@ -227,7 +232,7 @@ __device__ __forceinline__ void gemm_tile_op(const GemmProb &p, const int m0, co
 
     // split-BF16 operands take the vector paths: along k (A with op = T, B
     // with op = N) or along the rows (A with op = N, B with op = T)
-    constexpr bool VA = MODE == CMP_BF16X3, VB = MODE == CMP_BF16X3;
+    constexpr bool VA = MODE == CMP_BF16X3 && !GA, VB = MODE == CMP_BF16X3;
     typedef std::conditional_t<OPA == 1, SplitKRows<BM, TA>, SplitMRows<BM, TA>> VecA;
     typedef std::conditional_t<OPB == 0, SplitKRows<BN, TA>, SplitMRows<BN, TA>> VecB;
     VecA va;
@@ -235,15 +240,26 @@ __device__ __forceinline__ void gemm_tile_op(const GemmProb &p, const int m0, co
     if constexpr (VA) va.init(p.A, lda, m0, M);
     if constexpr (VB) vb.init(p.B, ldb, n0, N);
 
-    const SELINV_GLOBAL TA *pa[LA];
+    const SELINV_GLOBAL TA *pa[GA ? 1 : LA];
+    const SELINV_GLOBAL uint32_t *pc[GA ? LA : 1];  // GA: codes of this thread's A elements
     const SELINV_GLOBAL TA *pb[LB];
     {
-        const SELINV_GLOBAL TA *A = gptr((const TA *)p.A);
         const SELINV_GLOBAL TA *B = gptr((const TA *)p.B);
+        if constexpr (GA) {
+            // G_K is c_L x c_U with ld = lda = c_L, laid out as a stored G would be
+            const SELINV_GLOBAL uint32_t *Cd = gptr(mats[p.gmat].gcA) + p.gcode;
 #pragma unroll
-        for (int t = 0; t < LA; t++) {
-            const int64_t r = min(m0 + ai(t), M - 1);
-            pa[t] = A + (OPA == 0 ? r : r * lda) + ak(t) * ksa;
+            for (int t = 0; t < LA; t++) {
+                const int64_t r = min(m0 + ai(t), M - 1);
+                pc[t] = Cd + (OPA == 0 ? r : r * lda) + ak(t) * ksa;
+            }
+        } else {
+            const SELINV_GLOBAL TA *A = gptr((const TA *)p.A);
+#pragma unroll
+            for (int t = 0; t < LA; t++) {
+                const int64_t r = min(m0 + ai(t), M - 1);
+                pa[t] = A + (OPA == 0 ? r : r * lda) + ak(t) * ksa;
+            }
         }
 #pragma unroll
         for (int t = 0; t < LB; t++) {
@@ -258,13 +274,55 @@ __device__ __forceinline__ void gemm_tile_op(const GemmProb &p, const int m0, co
 #pragma unroll
         for (int j = 0; j < TN; j++) acc[i][j] = Acc{0, 0, 0, 0};
 
+    const int nch = (K + BK - 1) / BK;
+    // GA: the source arrays of matrix gmat, and the code of every A element
+    // of the next chunk to load
+    const SELINV_GLOBAL double *gZd = nullptr;
+    const SELINV_GLOBAL TA *gZL = nullptr, *gZU = nullptr;
+    if constexpr (GA) {
+        const MatDev &Md = mats[p.gmat];
+        gZd = gptr(Md.Zd);
+        gZL = gptr((const TA *)Md.ZL);
+        gZU = gptr((const TA *)Md.ZU);
+    }
+    uint32_t code[GA ? LA : 1];
+    auto cload = [&](int c) {
+        const int k0 = c * BK;
+        if (k0 + BK <= K) {
+#pragma unroll
+            for (int t = 0; t < LA; t++) code[t] = pc[t][k0 * ksa];
+        } else {
+#pragma unroll
+            for (int t = 0; t < LA; t++) code[t] = pc[t][(int64_t)(min(k0 + ak(t), K - 1) - ak(t)) * ksa];
+        }
+    };
+    // value named by a code (array << 30 | offset; 1 Zd, 2 ZL, 3 ZU): in the
+    // mixed forms a diagonal-block entry is rounded to TA as the gather
+    // rounds it
+    auto gval = [&](uint32_t cd) -> TA {
+        const uint32_t kd = cd >> GCODE_SHIFT, off = cd & GCODE_MASK;
+        if constexpr (sizeof(TA) == sizeof(double)) {
+            const SELINV_GLOBAL TA *src = kd == 1 ? (const SELINV_GLOBAL TA *)gZd : kd == 3 ? gZU : gZL;
+            return src[off];
+        } else {
+            const double vd = gZd[kd == 1 ? off : 0];
+            const TA v = (kd == 3 ? gZU : gZL)[kd == 1 ? 0 : off];
+            return kd == 1 ? (TA)vd : v;
+        }
+    };
+
     TA ra[VA ? 1 : LA], rb[VB ? 1 : LB];
     auto gload = [&](int c) {
         const int k0 = c * BK;
         if constexpr (VA) va.load(k0, K);
         if constexpr (VB) vb.load(k0, K);
+        if constexpr (GA) {
+#pragma unroll
+            for (int t = 0; t < LA; t++) ra[t] = gval(code[t]);
+            if (c + 1 < nch) cload(c + 1);
+        }
         if (k0 + BK <= K) {
-            if constexpr (!VA) {
+            if constexpr (!VA && !GA) {
 #pragma unroll
                 for (int t = 0; t < LA; t++) ra[t] = pa[t][k0 * ksa];
             }
@@ -274,7 +332,7 @@ __device__ __forceinline__ void gemm_tile_op(const GemmProb &p, const int m0, co
             }
         } else {
             // last, partial chunk: k clamped into the operand
-            if constexpr (!VA) {
+            if constexpr (!VA && !GA) {
 #pragma unroll
                 for (int t = 0; t < LA; t++) ra[t] = pa[t][(int64_t)(min(k0 + ak(t), K - 1) - ak(t)) * ksa];
             }
@@ -377,10 +435,10 @@ __device__ __forceinline__ void gemm_tile_op(const GemmProb &p, const int m0, co
     // K == 0 (C = beta Cin): no chunk, no operand read.  Chunks whose
     // products are all zero by the operands' triangular structure are
     // skipped (p.ktri).
-    const int nch = (K + BK - 1) / BK;
     const int klo = max((p.ktri & 1) ? n0 : 0, (p.ktri & 2) ? m0 : 0);
     const int c0 = min(klo / BK, nch);
     if (c0 < nch) {
+        if constexpr (GA) cload(c0);
         gload(c0);
         sstore(c0 & 1, c0);
     }
@@ -499,6 +557,17 @@ __device__ __forceinline__ void gemm_tile(const GemmProb &p, const int m0, const
         else
             gemm_tile_op<MODE, BM, BN, TA, TC, CIN, BK, 1, 1, PUSH, TG>(p, m0, n0, sm, mats);
     }
+}
+
+// A step-3 (op(A) = G_K^T) or step-5 (op(A) = G_K) product tile with G_K
+// taken from its sources through its codes; op(B) = B, results in TA.
+template <int MODE, int BM, int BN, typename TA, int BK = ChunkK<MODE, BM>::value>
+__device__ __forceinline__ void gemm_tile_g35(const GemmProb &p, const int m0, const int n0,
+                                              Smem<MODE, BM, BN, BK> &sm, const MatDev *mats) {
+    if (p.opA == 0)
+        gemm_tile_op<MODE, BM, BN, TA, TA, false, BK, 0, 0, false, TA, true>(p, m0, n0, sm, mats);
+    else
+        gemm_tile_op<MODE, BM, BN, TA, TA, false, BK, 1, 0, false, TA, true>(p, m0, n0, sm, mats);
 }
 
 // LDS of one gather tile

@@ -34,7 +34,8 @@ EXPORTED = ["selinv_analyze", "selinv_factor", "selinv_factor_device", "selinv_r
             "selinv_set_tuning", "selinv_set_allocator", "selinv_get_many", "selinv_set_gather_code_budget",
             "selinv_batch_run_graph", "selinv_batch_tune", "selinv_batch_get_tuning", "selinv_batch_set_tuning",
             "selinv_batch_set_profiling", "selinv_batch_timings", "selinv_batch_level_stats", "selinv_batch_query",
-            "selinv_batch_last_error", "selinv_get_selected_noalloc"]
+            "selinv_batch_last_error", "selinv_get_selected_noalloc", "selinv_set_gather_form",
+            "selinv_batch_set_gather_form"]
 
 
 class SelinvError(RuntimeError):
@@ -101,6 +102,8 @@ def _load():
         "selinv_set_sweep_mode": ([vp, i32], C.c_int),
         "selinv_sweep_is_persistent": ([vp, C.c_int], i32),
         "selinv_batch_set_sweep_mode": ([vp, i32], C.c_int),
+        "selinv_set_gather_form": ([vp, i32], C.c_int),
+        "selinv_batch_set_gather_form": ([vp, i32], C.c_int),
         "selinv_tune": ([vp, C.c_int, i32, vp, P(dbl), P(dbl)], C.c_int),
         "selinv_get_tuning": ([vp, C.c_int, P(i32), i32, P(i32)], C.c_int),
         "selinv_set_tuning": ([vp, C.c_int, P(i32), i32], C.c_int),
@@ -326,6 +329,14 @@ class SelInv:
         self._check(_lib.selinv_set_sweep_mode(self._h, m), "set_sweep_mode")
         return self
 
+    # where the level sweep takes G_K from (selinv_set_gather_form)
+    GATHER_FORMS = {"auto": 0, "stored": 1, "in_products": 2}
+
+    def set_gather_form(self, form="auto"):
+        f = self.GATHER_FORMS[form] if isinstance(form, str) else int(form)
+        self._check(_lib.selinv_set_gather_form(self._h, f), "set_gather_form")
+        return self
+
     def sweep_is_persistent(self, precision="fp64") -> int:
         return int(_lib.selinv_sweep_is_persistent(self._h, _prec(precision)))
 
@@ -417,6 +428,11 @@ class Batch:
     def set_sweep_mode(self, mode="auto"):
         m = SelInv.SWEEP_MODES[mode] if isinstance(mode, str) else int(mode)
         self._check(_lib.selinv_batch_set_sweep_mode(self._b, m), "batch_set_sweep_mode")
+        return self
+
+    def set_gather_form(self, form="auto"):
+        f = SelInv.GATHER_FORMS[form] if isinstance(form, str) else int(form)
+        self._check(_lib.selinv_batch_set_gather_form(self._b, f), "batch_set_gather_form")
         return self
 
     def run(self, precision="fp64", stream=None, graph=False):

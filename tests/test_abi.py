@@ -293,23 +293,30 @@ def test_tuning_table_set_get_and_validation(si):
     s = si.SelInv(w.n, w.colptr, w.rowind, w.perm, w.max_super, w.relax, w.pad_pct)
     L = s.info["nlevels"]
     assert s.get_tuning("fp64") == []
-    table = [3, L, 1, 64, 32, 0, 0, 448]
+    table = [4, L, 1, 64, 32, 0, 0, 448]
     for d in range(L):
-        table += [32 if d % 2 else 64, 128, d % 2]
+        table += [32 if d % 2 else 64, 128, d % 2, (d // 2) % 2]
     s.set_tuning(table, "mixed_fp32")
     assert s.get_tuning("mixed_fp32") == table
     assert s.get_tuning("fp64") == []
-    # the earlier layouts are still accepted: without the side chunk (one side
-    # launch), and without the prologue flag as well (side stream kept)
-    v2 = [2] + table[1:7] + table[8:]
+    # the earlier layouts are still accepted, with a stored G on every level:
+    # three values per level; without the side chunk (one side launch); and
+    # without the prologue flag as well (side stream kept)
+    per3 = [v for d in range(L) for v in table[8 + 4 * d: 11 + 4 * d]]
+    stored = [v for d in range(L) for v in table[8 + 4 * d: 11 + 4 * d] + [0]]
+    v3 = [3] + table[1:8] + per3
+    s.set_tuning(v3, "fp64")
+    assert s.get_tuning("fp64") == table[:8] + stored
+    v2 = [2] + table[1:7] + per3
     s.set_tuning(v2, "fp64")
-    assert s.get_tuning("fp64") == table[:7] + [0] + table[8:]
-    v1 = [1] + table[1:6] + table[8:]
+    assert s.get_tuning("fp64") == table[:7] + [0] + stored
+    v1 = [1] + table[1:6] + per3
     s.set_tuning(v1, "mixed_bf16x3")
-    assert s.get_tuning("mixed_bf16x3") == table[:6] + [0, 0] + table[8:]
-    bad = [table[:-1], [4] + table[1:], table[:1] + [L + 1] + table[2:], table[:3] + [48] + table[4:],
-           table[:10] + [2] + table[11:], table[:2] + [3] + table[3:], table[:6] + [2] + table[7:],
-           table[:7] + [-1] + table[8:], table[:7] + [(1 << 20) + 1] + table[8:], v2[:-1]]
+    assert s.get_tuning("mixed_bf16x3") == table[:6] + [0, 0] + stored
+    bad = [table[:-1], [5] + table[1:], table[:1] + [L + 1] + table[2:], table[:3] + [48] + table[4:],
+           table[:10] + [2] + table[11:], table[:11] + [2] + table[12:], table[:2] + [3] + table[3:],
+           table[:6] + [2] + table[7:], table[:7] + [-1] + table[8:], table[:7] + [(1 << 20) + 1] + table[8:],
+           v2[:-1], v3 + [0]]
     for b in bad:
         with pytest.raises(si.SelinvError) as e:
             s.set_tuning(b, "mixed_fp32")
@@ -321,7 +328,7 @@ def test_tuning_table_set_get_and_validation(si):
     x = si.SelInv(w.n, w.colptr, w.rowind, w.perm, w.max_super, w.relax, w.pad_pct, symbolic="exact")
     Lx = x.info["nlevels"]
     x.set_tuning([3, Lx, 2, 0, 0, 0, 0, 0] + [0, 0, 0] * Lx)
-    x.set_tuning([3, Lx, 1, 0, 0, 0, 1, 0] + [0, 0, 0] * Lx)
+    x.set_tuning([4, Lx, 1, 0, 0, 0, 1, 0] + [0, 0, 0, 1] * Lx)
 
 
 def test_autotune_describe():
@@ -334,6 +341,22 @@ def test_autotune_describe():
     assert d["steps35_tiles"] == [32, 128] and not d["prologue_side_stream"]
     d = describe([3, 2, 1, 64, 32, 32, 0, 512, 32, 64, 0, 128, 128, 1])
     assert d["steps35_tiles"] == [32, 128] and d["prologue_side_stream"] and d["side_inversion_chunk"] == 512
+    assert d["gather_in_products_levels"] == []
+    d = describe([4, 2, 1, 64, 32, 32, 0, 512, 32, 64, 0, 1, 128, 128, 1, 0])
+    assert d["steps35_tiles"] == [32, 128] and d["step4_tiles"] == [64, 128]
+    assert d["small_per_phase_levels"] == [1] and d["gather_in_products_levels"] == [0]
+
+
+def test_gather_form_argument(si):
+    """selinv_set_gather_form takes 0..2 (host side; the runs need the device)."""
+    w = config_c0()
+    s = si.SelInv(w.n, w.colptr, w.rowind, w.perm, w.max_super, w.relax, w.pad_pct)
+    for f in ("auto", "stored", "in_products", 0, 2):
+        s.set_gather_form(f)
+    for f in (-1, 3):
+        with pytest.raises(si.SelinvError) as e:
+            s.set_gather_form(f)
+        assert e.value.status == "INVALID_ARG"
 
 
 # --------------------------------------------------------------------------

@@ -251,7 +251,7 @@ def test_c3_batch_tuned_and_profiled(si, c3_all):
     b = si.Batch(mats)
     ms_pol, ms_tun = b.tune("fp64", reps=2)
     table = b.get_tuning("fp64")
-    assert ms_tun <= ms_pol and len(table) == 8 + 3 * b.info["nlevels"]
+    assert ms_tun <= ms_pol and len(table) == 8 + 4 * b.info["nlevels"]
     b.run("fp64", graph=True)
     for k, m in enumerate(mats):
         assert np.array_equal(m.get_selected(), single["fp64"][k]), k
@@ -545,7 +545,7 @@ def test_tune_c1_keeps_parity(si, c1_pair, prec):
     ms_pol, ms_tun = s.tune(prec, reps=3)
     table = s.get_tuning(prec)
     say("c1 tune", prec, "policy ms", ms_pol, "tuned ms", ms_tun, "table", table)
-    assert ms_tun <= ms_pol and len(table) == 8 + 3 * s.info["nlevels"]
+    assert ms_tun <= ms_pol and len(table) == 8 + 4 * s.info["nlevels"]
     s.run(prec)
     compare_superset(s, o, TOL[prec])
     s.run(prec, graph=True)
@@ -555,8 +555,9 @@ def test_tune_c1_keeps_parity(si, c1_pair, prec):
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed_fp32", "mixed_bf16x3"])
 def test_forced_tables_keep_parity(si, prec):
-    """Every tile edge on every launch class, and the per-phase launches on
-    the levels of small supernodes, give the same results."""
+    """Every tile edge on every launch class, the per-phase launches on the
+    levels of small supernodes, and G_K read by the products give the same
+    results."""
     w = config_c0()
     say("c0 forced tables", prec)
     s, o = lib_and_oracle(si, w.n, w.colptr, w.rowind, w.values, w.perm, w.max_super, w.relax, w.pad_pct)
@@ -564,6 +565,10 @@ def test_forced_tables_keep_parity(si, prec):
     for edge in (32, 64, 128):
         for per_phase in (0, 1):
             s.set_tuning([2, L, 1, edge, edge, edge, per_phase] + [edge, edge, per_phase] * L, prec)
+            s.run(prec)
+            compare_superset(s, o, TOL[prec])
+            # G_K read by the products on every level that allows it
+            s.set_tuning([4, L, 1, edge, edge, edge, per_phase, 0] + [edge, edge, per_phase, 1] * L, prec)
             s.run(prec)
             compare_superset(s, o, TOL[prec])
 
@@ -800,6 +805,124 @@ def test_map_gather_split_k_whole_superset(si, split_pair, prec, sweep):
 # --------------------------------------------------------------------------
 # device memory from the allocator hook; many entries at once
 # --------------------------------------------------------------------------
+# --------------------------------------------------------------------------
+# G_K read from its sources inside the step-3/5 products (no stored G)
+# --------------------------------------------------------------------------
+def in_product_levels(s):
+    """Levels of the last run whose steps 3/5 read G_K from its sources."""
+    return [d for d in range(s.info["nlevels"]) if s.level_stats(d)["gather_fused"] == 2]
+
+
+def stored_and_in_products(s, prec, graph=False):
+    """Results with a stored G and with G_K read by the products (level sweep)."""
+    s.set_sweep_mode("levels")
+    s.set_gather_form("stored")
+    s.run(prec, graph=graph)
+    assert in_product_levels(s) == [] or graph
+    ref = s.export()
+    s.set_gather_form("in_products")
+    s.run(prec, graph=graph)
+    got = s.export()
+    s.set_gather_form("auto")
+    s.set_sweep_mode("auto")
+    return ref, got
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed_fp32", "mixed_bf16x3"])
+def test_gather_in_products_c1(si, c1_pair, prec):
+    """The products take every entry of G_K from the block that holds it: the
+    values staged are those the gather stores, so the results equal the
+    stored-G results bit for bit, and the oracle's to the bar."""
+    w, s, o = c1_pair
+    say("c1 G in products", prec)
+    ref, got = stored_and_in_products(s, prec)
+    for a, b in zip(ref, got):
+        assert np.array_equal(a, b)
+    s.set_sweep_mode("levels")
+    s.set_gather_form("in_products")
+    s.run(prec)
+    lv = in_product_levels(s)
+    assert lv and all(s.level_stats(d)["gather_tiles"] == 0 for d in lv)
+    en, ed = compare_superset(s, o, TOL[prec])
+    record("c1 G in products", prec, "err_norm", en, "err_diag", ed)
+    s.set_gather_form("auto")
+    s.set_sweep_mode("auto")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed_fp32", "mixed_bf16x3"])
+def test_gather_in_products_split_k(si, split_pair, prec):
+    """Wide levels with split step-4 products (whose reductions then push
+    nothing): bitwise equal to the stored G, and the oracle's to the bar."""
+    w, s, o = split_pair
+    say("split-K G in products", prec)
+    ref, got = stored_and_in_products(s, prec)
+    for a, b in zip(ref, got):
+        assert np.array_equal(a, b)
+    s.set_sweep_mode("levels")
+    s.set_gather_form("in_products")
+    s.run(prec)
+    assert len(in_product_levels(s)) >= 3
+    en, ed = compare_superset(s, o, TOL[prec])
+    record("split-K 32^3 G in products", prec, "err_norm", en, "err_diag", ed)
+    s.set_gather_form("auto")
+    s.set_sweep_mode("auto")
+
+
+def test_gather_in_products_graph_replay(si, c1_pair):
+    import torch
+    w, s, o = c1_pair
+    say("c1 G in products, graph")
+    ref, _ = stored_and_in_products(s, "fp64")
+    s.set_sweep_mode("levels")
+    s.set_gather_form("in_products")
+    st = torch.cuda.Stream()
+    for rep in range(3):
+        s.run("fp64", stream=st, graph=True)
+        assert np.array_equal(s.export()[2], ref[2]), rep
+        torch.cuda.synchronize()
+        s.run("fp64")
+        assert np.array_equal(s.export()[2], ref[2]), rep
+    s.set_gather_form("auto")
+    s.set_sweep_mode("auto")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed_bf16x3"])
+def test_gather_in_products_batch(si, c3_all, prec):
+    """A batch of the 8 largest C3 matrices (one code array per matrix)."""
+    ws, mats, single = c3_all
+    order = np.argsort([w.n for w in ws])[-8:]
+    say("c3 G in products", prec, [ws[k].n for k in order])
+    b = si.Batch([mats[k] for k in order]).set_sweep_mode("levels").set_gather_form("in_products")
+    b.run(prec)
+    assert any(b.level_stats(d)["gather_fused"] == 2 for d in range(b.info["nlevels"]))
+    for k in order:
+        assert np.array_equal(mats[k].get_selected(), single[prec][k]), k
+    b.run(prec, graph=True)
+    for k in order:
+        assert np.array_equal(mats[k].get_selected(), single[prec][k]), k
+    b.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed_fp32"])
+def test_gather_in_products_complex(si, z48, prec):
+    """Complex blocks (products forming the even columns only)."""
+    w, s, ref = z48
+    say("complex 48x48 G in products", prec)
+    a, b = stored_and_in_products(s, prec)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def test_gather_in_products_exact_sets(si, upwind_pair):
+    """Exact (unsymmetrized) block sets: G_K meets several ancestors."""
+    w, s, o = upwind_pair
+    say("upwind G in products")
+    for prec in ("fp64", "mixed_bf16x3"):
+        a, b = stored_and_in_products(s, prec)
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+
+
 def test_allocator_hook_nomem_and_torch_memory(si):
     import torch
     w = config_c0()
