@@ -88,8 +88,10 @@ struct SplitKRows {
     static constexpr int NT = R / 32;
     typedef TA v4 __attribute__((ext_vector_type(4), aligned(sizeof(TA))));
     typedef __bf16 v4b __attribute__((ext_vector_type(4)));
+    struct Regs {  // one chunk in flight
+        v4 reg[NT];
+    };
     const SELINV_GLOBAL TA *ptr[NT];
-    v4 reg[NT];
     __device__ __forceinline__ int row(int t) const { return (int)(threadIdx.x >> 3) + 32 * t; }
     __device__ __forceinline__ int kk() const { return 4 * (int)(threadIdx.x & 7); }
     // row r of the operand starts at base + r ld (rows clamped into [0, rows))
@@ -98,21 +100,22 @@ struct SplitKRows {
 #pragma unroll
         for (int t = 0; t < NT; t++) ptr[t] = B + (int64_t)min(r0 + row(t), rows - 1) * ld + kk();
     }
-    __device__ __forceinline__ void load(int k0, int K) {
+    __device__ __forceinline__ void load(Regs &g, int k0, int K) const {
         if (k0 + 32 <= K) {
 #pragma unroll
-            for (int t = 0; t < NT; t++) reg[t] = *(const SELINV_GLOBAL v4 *)(ptr[t] + k0);
+            for (int t = 0; t < NT; t++) g.reg[t] = *(const SELINV_GLOBAL v4 *)(ptr[t] + k0);
         } else {
             // last, partial chunk: k clamped into the operand
 #pragma unroll
             for (int t = 0; t < NT; t++)
 #pragma unroll
-                for (int e = 0; e < 4; e++) reg[t][e] = ptr[t][min(k0 + kk() + e, K - 1) - kk()];
+                for (int e = 0; e < 4; e++) g.reg[t][e] = ptr[t][min(k0 + kk() + e, K - 1) - kk()];
         }
     }
     template <int P>
-    __device__ __forceinline__ void store(__bf16 (&hi)[R][P], __bf16 (&lo)[R][P], int r0, int rows, int k0,
-                                          int K) const {
+    __device__ __forceinline__ void store(const Regs &g, __bf16 (&hi)[R][P], __bf16 (&lo)[R][P], int r0, int rows,
+                                          int k0, int K) const {
+        const v4(&reg)[NT] = g.reg;
 #pragma unroll
         for (int t = 0; t < NT; t++) {
             v4b h4, l4;
@@ -144,7 +147,9 @@ struct SplitMRows {
     int64_t ld;
     int r0, rows;
     bool full;  // all 4 rows of the quad inside the operand
-    v4 reg[KB];
+    struct Regs {  // one chunk in flight
+        v4 reg[KB];
+    };
     __device__ __forceinline__ int r4() const { return 4 * (int)(threadIdx.x % TPK); }
     __device__ __forceinline__ int kq() const { return KB * (int)(threadIdx.x / TPK); }
     // element (r, k) of the operand at base + r + k ld
@@ -155,7 +160,8 @@ struct SplitMRows {
         full = r0 + r4() + 3 < rows;
         ptr = gptr((const TA *)base) + (full ? r0 + r4() : 0) + (int64_t)kq() * ld;
     }
-    __device__ __forceinline__ void load(int k0, int K) {
+    __device__ __forceinline__ void load(Regs &g, int k0, int K) const {
+        v4(&reg)[KB] = g.reg;
         const bool kin = k0 + 32 <= K;
 #pragma unroll
         for (int e = 0; e < KB; e++) {
@@ -170,7 +176,9 @@ struct SplitMRows {
         }
     }
     template <int P>
-    __device__ __forceinline__ void store(__bf16 (&hi)[R][P], __bf16 (&lo)[R][P], int k0, int K) const {
+    __device__ __forceinline__ void store(const Regs &g, __bf16 (&hi)[R][P], __bf16 (&lo)[R][P], int k0,
+                                          int K) const {
+        const v4(&reg)[KB] = g.reg;
 #pragma unroll
         for (int q = 0; q < 4; q++) {
             vkb h, l;
@@ -223,6 +231,8 @@ __device__ __forceinline__ void gemm_tile_op(const GemmProb &p, const int m0, co
 
     // (row, k) of element t of this thread's share of an A chunk, (k, col) of B;
     // the contiguous dimension of the operand runs along consecutive threads
+    // (measured: reading an in-place G_K along k for op = N as well, which
+    // would coalesce its U-panel entries, made C4's products slower)
     auto ai = [&](int t) { return OPA == 0 ? tid % BM : tid / BK + t * (256 / BK); };
     auto ak = [&](int t) { return OPA == 0 ? tid / BM + t * (256 / BM) : tid % BK; };
     auto bj = [&](int t) { return OPB == 0 ? tid / BK + t * (256 / BK) : tid % BN; };
@@ -311,49 +321,62 @@ __device__ __forceinline__ void gemm_tile_op(const GemmProb &p, const int m0, co
         }
     };
 
-    TA ra[VA ? 1 : LA], rb[VB ? 1 : LB];
-    auto gload = [&](int c) {
+    // Register slots of the chunks loaded ahead of their LDS stage: PF = 2
+    // for the 32-wide tiles, which serve the launches that cannot fill the
+    // device, where each workgroup waits on the latency of every chunk's
+    // loads (two chunks in flight halve that wait); 1 for the wider tiles,
+    // whose launches hide it behind other workgroups (and whose registers
+    // would cost occupancy).
+    constexpr int PF = BM == 32 ? 2 : 1;
+    TA ra[PF][VA ? 1 : LA], rb[PF][VB ? 1 : LB];
+    typename VecA::Regs rva[PF];
+    typename VecB::Regs rvb[PF];
+    // chunk c into slot S
+    auto gload = [&](int c, auto S_) {
+        constexpr int S = decltype(S_)::value;
         const int k0 = c * BK;
-        if constexpr (VA) va.load(k0, K);
-        if constexpr (VB) vb.load(k0, K);
+        if constexpr (VA) va.load(rva[S], k0, K);
+        if constexpr (VB) vb.load(rvb[S], k0, K);
         if constexpr (GA) {
 #pragma unroll
-            for (int t = 0; t < LA; t++) ra[t] = gval(code[t]);
+            for (int t = 0; t < LA; t++) ra[S][t] = gval(code[t]);
             if (c + 1 < nch) cload(c + 1);
         }
         if (k0 + BK <= K) {
             if constexpr (!VA && !GA) {
 #pragma unroll
-                for (int t = 0; t < LA; t++) ra[t] = pa[t][k0 * ksa];
+                for (int t = 0; t < LA; t++) ra[S][t] = pa[t][k0 * ksa];
             }
             if constexpr (!VB) {
 #pragma unroll
-                for (int t = 0; t < LB; t++) rb[t] = pb[t][k0 * ksb];
+                for (int t = 0; t < LB; t++) rb[S][t] = pb[t][k0 * ksb];
             }
         } else {
             // last, partial chunk: k clamped into the operand
             if constexpr (!VA && !GA) {
 #pragma unroll
-                for (int t = 0; t < LA; t++) ra[t] = pa[t][(int64_t)(min(k0 + ak(t), K - 1) - ak(t)) * ksa];
+                for (int t = 0; t < LA; t++) ra[S][t] = pa[t][(int64_t)(min(k0 + ak(t), K - 1) - ak(t)) * ksa];
             }
             if constexpr (!VB) {
 #pragma unroll
-                for (int t = 0; t < LB; t++) rb[t] = pb[t][(int64_t)(min(k0 + bk(t), K - 1) - bk(t)) * ksb];
+                for (int t = 0; t < LB; t++) rb[S][t] = pb[t][(int64_t)(min(k0 + bk(t), K - 1) - bk(t)) * ksb];
             }
         }
     };
-    auto sstore = [&](int buf, int c) {
+    // chunk c from slot S into LDS buffer buf
+    auto sstore = [&](int buf, int c, auto S_) {
+        constexpr int S = decltype(S_)::value;
         const int k0 = c * BK;
         if constexpr (VA) {
             if constexpr (OPA == 1)
-                va.store(sm.ah[buf], sm.al[buf], m0, M, k0, K);
+                va.store(rva[S], sm.ah[buf], sm.al[buf], m0, M, k0, K);
             else
-                va.store(sm.ah[buf], sm.al[buf], k0, K);
+                va.store(rva[S], sm.ah[buf], sm.al[buf], k0, K);
         } else {
 #pragma unroll
         for (int t = 0; t < LA; t++) {
             const int i = ai(t), k = ak(t);
-            const T v = (m0 + i < M && k0 + k < K) ? (T)ra[t] : (T)0;
+            const T v = (m0 + i < M && k0 + k < K) ? (T)ra[S][t] : (T)0;
             if constexpr (MODE == CMP_BF16X3) {
                 const __bf16 h = (__bf16)v;
                 sm.ah[buf][i][k] = h;
@@ -365,14 +388,14 @@ __device__ __forceinline__ void gemm_tile_op(const GemmProb &p, const int m0, co
         }
         if constexpr (VB) {
             if constexpr (OPB == 0)
-                vb.store(sm.bh[buf], sm.bl[buf], n0, N, k0, K);
+                vb.store(rvb[S], sm.bh[buf], sm.bl[buf], n0, N, k0, K);
             else
-                vb.store(sm.bh[buf], sm.bl[buf], k0, K);
+                vb.store(rvb[S], sm.bh[buf], sm.bl[buf], k0, K);
         } else {
 #pragma unroll
         for (int t = 0; t < LB; t++) {
             const int j = bj(t), k = bk(t);
-            const T v = (n0 + j < N && k0 + k < K) ? (T)rb[t] : (T)0;
+            const T v = (n0 + j < N && k0 + k < K) ? (T)rb[S][t] : (T)0;
             if constexpr (MODE == CMP_BF16X3) {
                 const __bf16 h = (__bf16)v;
                 sm.bh[buf][j][k] = h;
@@ -437,19 +460,41 @@ __device__ __forceinline__ void gemm_tile_op(const GemmProb &p, const int m0, co
     // skipped (p.ktri).
     const int klo = max((p.ktri & 1) ? n0 : 0, (p.ktri & 2) ? m0 : 0);
     const int c0 = min(klo / BK, nch);
+    typedef std::integral_constant<int, 0> Slot0;
+    typedef std::integral_constant<int, PF - 1> SlotL;
     if (c0 < nch) {
         if constexpr (GA) cload(c0);
-        gload(c0);
-        sstore(c0 & 1, c0);
+        gload(c0, Slot0{});
+        if constexpr (PF == 2) {
+            if (c0 + 1 < nch) gload(c0 + 1, SlotL{});
+        }
+        sstore(c0 & 1, c0, Slot0{});
     }
     __syncthreads();
-    for (int c = c0; c < nch; c++) {
-        const int buf = c & 1;
-        const bool more = c + 1 < nch;
-        if (more) gload(c + 1);
-        compute(buf);
-        if (more) sstore(buf ^ 1, c + 1);
-        __syncthreads();
+    if constexpr (PF == 1) {
+        for (int c = c0; c < nch; c++) {
+            const int buf = c & 1;
+            const bool more = c + 1 < nch;
+            if (more) gload(c + 1, Slot0{});
+            compute(buf);
+            if (more) sstore(buf ^ 1, c + 1, Slot0{});
+            __syncthreads();
+        }
+    } else {
+        // chunk c0 + i waits in slot i & 1 from its load until its LDS stage;
+        // step c refills the slot of chunk c (staged one step earlier) with
+        // chunk c + 2 and stages chunk c + 1 (loaded one step earlier)
+        auto step = [&](int c, auto S_) {
+            constexpr int S = decltype(S_)::value;
+            if (c + 2 < nch) gload(c + 2, S_);
+            compute(c & 1);
+            if (c + 1 < nch) sstore((c + 1) & 1, c + 1, std::integral_constant<int, 1 - S>{});
+            __syncthreads();
+        };
+        for (int c = c0; c < nch; c += 2) {
+            step(c, Slot0{});
+            if (c + 1 < nch) step(c + 1, SlotL{});
+        }
     }
 
     SELINV_GLOBAL TC *__restrict__ C = gptr_w((TC *)p.C);
