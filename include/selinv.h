@@ -271,7 +271,8 @@ selinv_status selinv_set_gather_form(selinv_handle h, int32_t form);
  *     selinv_set_gather_form);
  *   - with sweep mode 0, the level sweep or the persistent sweep;
  *   - the prologue of the wide lower levels on a side stream beside the
- *     upper levels, or all of the prologue before the sweep;
+ *     upper levels (also with one part per upper level), or all of the
+ *     prologue before the sweep;
  *   - with the side stream, its tile inversions in one launch or in chunks
  *     of 5/4, 3/2, 7/4, 2, 5/2 or 3 times the compute-unit count (a launch
  *     that fills the device holds the upper levels' launches back until it
@@ -289,9 +290,13 @@ selinv_status selinv_tune(selinv_handle h, selinv_precision prec, int32_t reps, 
 /* The tuning table of `prec` as int32 values:
  *   [4, nlevels, sweep form (0: the handle's mode, 1: levels, 2: persistent),
  *    tile of the inversion rounds, of the normalisation, of the diagonal
- *    initialisation, 1 if the whole prologue runs before the sweep (no side
- *    stream), tile-inversion items per launch on the side stream (0: one
- *    launch; at most 2^20), then for every level d = 0 .. nlevels-1: tile of
+ *    initialisation, prologue placement (0: the levels from the first wide
+ *    one on a side stream beside the sweep of the levels above; 1: the whole
+ *    prologue before the sweep, no side stream; 2: as 0, and every level
+ *    above the first wide one its own part on the side stream, joined just
+ *    before the sweep reaches that level), tile-inversion items per launch
+ *    on the side stream (0: one launch; at most 2^20), then for every level
+ *    d = 0 .. nlevels-1: tile of
  *    steps 3+5, tile of step 4, 1 if the level's small supernodes use the
  *    per-phase launches, 1 if its steps 3/5 read G_K from its sources
  *    (gather form 0)],

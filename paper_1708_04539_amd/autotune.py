@@ -84,6 +84,7 @@ def describe(table: list) -> dict:
     return {"tuned": True, "sweep": {0: "handle", 1: "levels", 2: "persistent"}[table[2]],
             "prologue_tiles": {"tri": table[3], "norm": table[4], "diag_init": table[5]},
             "prologue_side_stream": not (hd >= 7 and table[6] == 1),
+            "prologue_part_per_level": hd >= 7 and table[6] == 2,
             "side_inversion_chunk": table[7] if hd == 8 else 0,
             "steps35_tiles": [p[0] for p in per], "step4_tiles": [p[1] for p in per],
             "small_per_phase_levels": [d for d, p in enumerate(per) if p[2]],

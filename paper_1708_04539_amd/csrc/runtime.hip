@@ -94,16 +94,21 @@ struct Sweep {
     GemmTile *d_tiles = nullptr;
     GatherTile *d_gt = nullptr;
     // Diagonal-block inversion, normalisation and diagonal initialisation, in
-    // two parts: pro[0] for the supernodes of the levels above `split`,
-    // pro[1] for the rest.  In an unprofiled run pro[1] goes to a side stream
-    // forked from the run's stream and joined before level `split`, so that
-    // it overlaps the sweep of the upper levels, which leave most of the
-    // device idle.  split = 0: everything in pro[0], no fork.
+    // parts by level: part i covers the supernodes of levels [pro_level[i],
+    // pro_level[i + 1]).  In an unprofiled run part 0 runs on the run's
+    // stream before the sweep and parts 1.. on a side stream forked from it,
+    // in order, each joined (ev_part[i]) before the sweep reaches its first
+    // level, so that they overlap the sweep of the levels above, which leave
+    // most of the device idle.  Two parts split at level `split` (the first
+    // wide level), or one part per level above it plus the rest (tuning), or
+    // one part (split = 0).
     struct Prologue {
         Range tri, norm, dt;
         Range tri1, tri2;  // fused items of at most 16 / 32 columns (16- / 32-wide kernel)
         std::vector<Range> tri_rounds;  // pairs (T products, X products) per doubling round
-    } pro[2];
+    };
+    std::vector<Prologue> pro;
+    std::vector<int> pro_level;
     int split = 0;
     hipStream_t side = nullptr;
     // tile-inversion items per launch on the side stream (0: one launch).  A
@@ -111,7 +116,8 @@ struct Sweep {
     // waiting for slots until it drains; cut into chunks, the side stream
     // frees slots between its launches.
     int side_chunk = 0;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t ev_fork = nullptr;
+    std::vector<hipEvent_t> ev_part;  // [i]: part i done (i >= 1)
     std::vector<Range> small, gat, g35, g4;
     // split-K step 4: per level the reduction items (red4[d].count of them,
     // red4_mn[d] the largest M N), the partial products in ws4
@@ -156,7 +162,8 @@ struct Sweep {
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (graph) (void)hipGraphDestroy(graph);
         if (ev_fork) (void)hipEventDestroy(ev_fork);
-        if (ev_join) (void)hipEventDestroy(ev_join);
+        for (auto q : ev_part)
+            if (q) (void)hipEventDestroy(q);
         if (side) (void)hipStreamDestroy(side);
         for (void *q : {(void *)d_mats, (void *)d_tri, (void *)d_probs, (void *)d_tiles, (void *)d_gt,
                         (void *)d_small, (void *)d_red, (void *)d_ws4, (void *)d_ptasks, (void *)d_psn,
@@ -178,7 +185,8 @@ struct Tuning {
     std::vector<char> no_small;     // per level: 1 = per-phase launches for its small supernodes
     std::vector<char> vg;           // per level: 1 = steps 3/5 read G_K from its sources (no stored G)
     int sweep = SWEEP_AUTO;         // SWEEP_LEVELS / SWEEP_PERSISTENT, or the handle's own mode
-    int no_fork = 0;                // 1: the whole prologue before the sweep, no side stream
+    int no_fork = 0;                // 1: the whole prologue before the sweep, no side stream;
+                                    // 2: one side-stream part per level above the split
     int side_chunk = 0;             // tile-inversion items per launch on the side stream (0: one launch)
 };
 
@@ -603,16 +611,29 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, const DevAlloc &al, in
                 S->split = d;
                 break;
             }
-        if (tn && tn->no_fork) S->split = 0;
+        if (tn && tn->no_fork == 1) S->split = 0;
         if (tn) S->side_chunk = tn->side_chunk;
+        // part of each level
+        S->pro_level.assign(1, 0);
+        if (S->split > 0) {
+            if (tn && tn->no_fork == 2)
+                for (int d = 1; d < S->split; d++) S->pro_level.push_back(d);
+            S->pro_level.push_back(S->split);
+        }
+        S->pro.resize(S->pro_level.size());
     }
-    std::vector<std::vector<char>> part(hs.size());
+    const int npro = (int)S->pro.size();
+    std::vector<int> part_of_level(depth, 0);
+    for (int d = 0; d < depth; d++)
+        for (int i = 0; i < npro; i++)
+            if (d >= S->pro_level[i]) part_of_level[d] = i;
+    std::vector<std::vector<int>> part(hs.size());
     for (size_t mi = 0; mi < hs.size(); mi++) {
         part[mi].assign(hs[mi]->P.ns, 0);
         for (int d = 0; d < hs[mi]->P.nlevels; d++)
-            for (int32_t K : hs[mi]->P.levels[d]) part[mi][K] = S->split > 0 && d >= S->split;
+            for (int32_t K : hs[mi]->P.levels[d]) part[mi][K] = part_of_level[d];
     }
-    for (int pp = 0; pp < 2; pp++) {
+    for (int pp = 0; pp < npro; pp++) {
         Sweep::Prologue &PR = S->pro[pp];
         // diagonal-block inversion: 64x64 diagonal sub-blocks, then recursive
         // doubling.  Round h joins neighbouring inverted blocks A (h x h, at o)
@@ -759,10 +780,12 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, const DevAlloc &al, in
         else
             emit_launch(probs, first, tiles, PR.dt, false, tn ? tn->dt : 0);
     }
-    if (S->split > 0) {
+    if (npro > 1) {
         HIPCHK(err, hipStreamCreateWithFlags(&S->side, hipStreamNonBlocking), "create side stream");
         HIPCHK(err, hipEventCreateWithFlags(&S->ev_fork, hipEventDisableTiming), "create event");
-        HIPCHK(err, hipEventCreateWithFlags(&S->ev_join, hipEventDisableTiming), "create event");
+        S->ev_part.assign(npro, nullptr);
+        for (int i = 1; i < npro; i++)
+            HIPCHK(err, hipEventCreateWithFlags(&S->ev_part[i], hipEventDisableTiming), "create event");
     }
     size_t first = probs.size();
     // supernode ids over the whole batch, and the product problems of each
@@ -1235,27 +1258,31 @@ hipError_t launch_sweep(const Sweep &S, hipStream_t st, std::vector<hipEvent_t> 
     auto dt_part = [&](const Sweep::Prologue &P, hipStream_t s) -> hipError_t {
         return launch_gemm(GEMM_PRO_F64, CMP_F64, P.dt.tile, S.d_probs, S.d_tiles + P.dt.off, P.dt.count, s);
     };
-    // The side part is forked after the main part, so that the main part
-    // (needed first) does not share the device with it.
-    const bool fork = S.split > 0 && ev == nullptr;
-    const int nparts = (S.split > 0 && !fork) ? 2 : 1;
+    // The side parts are forked after the main part, so that the main part
+    // (needed first) does not share the device with them.  A profiled run
+    // runs every part on the run's stream, phase by phase.
+    const int npro = (int)S.pro.size();
+    const bool fork = npro > 1 && ev == nullptr;
+    const int nmain = fork ? 1 : npro;
     mark(0);
-    for (int q = 0; q < nparts; q++)
+    for (int q = 0; q < nmain; q++)
         if ((e = tri_part(S.pro[q], st))) return e;
     mark(1);
-    for (int q = 0; q < nparts; q++)
+    for (int q = 0; q < nmain; q++)
         if ((e = norm_part(S.pro[q], st))) return e;
     mark(2);
-    for (int q = 0; q < nparts; q++)
+    for (int q = 0; q < nmain; q++)
         if ((e = dt_part(S.pro[q], st))) return e;
     mark(3);
     if (fork) {
         if ((e = hipEventRecord(S.ev_fork, st))) return e;
         if ((e = hipStreamWaitEvent(S.side, S.ev_fork, 0))) return e;
-        if ((e = tri_part(S.pro[1], S.side))) return e;
-        if ((e = norm_part(S.pro[1], S.side))) return e;
-        if ((e = dt_part(S.pro[1], S.side))) return e;
-        if ((e = hipEventRecord(S.ev_join, S.side))) return e;
+        for (int q = 1; q < npro; q++) {
+            if ((e = tri_part(S.pro[q], S.side))) return e;
+            if ((e = norm_part(S.pro[q], S.side))) return e;
+            if ((e = dt_part(S.pro[q], S.side))) return e;
+            if ((e = hipEventRecord(S.ev_part[q], S.side))) return e;
+        }
     }
     if (S.persistent) {
         PersistArgs a;
@@ -1268,13 +1295,15 @@ hipError_t launch_sweep(const Sweep &S, hipStream_t st, std::vector<hipEvent_t> 
         a.err = S.d_cnt + S.ncnt + 1;
         a.mats = S.d_mats;
         a.probs = S.d_probs;
-        if (fork && (e = hipStreamWaitEvent(st, S.ev_join, 0))) return e;
+        if (fork && (e = hipStreamWaitEvent(st, S.ev_part[npro - 1], 0))) return e;
         if ((e = launch_persist(mode, a, S.ncnt, S.grid, st))) return e;
         for (size_t d = 0; d < 4 * S.gat.size(); d++) mark(4 + d);
         return hipSuccess;
     }
     for (size_t d = 0; d < S.gat.size(); d++) {
-        if (fork && (int)d == S.split && (e = hipStreamWaitEvent(st, S.ev_join, 0))) return e;
+        if (fork)
+            for (int q = 1; q < npro; q++)
+                if (S.pro_level[q] == (int)d && (e = hipStreamWaitEvent(st, S.ev_part[q], 0))) return e;
         if ((e = launch_small(mode, S.d_mats, S.d_probs, S.d_small + S.small[d].off, S.small[d].count, st)))
             return e;
         mark(4 + 4 * d);
@@ -2293,10 +2322,11 @@ static selinv_status runner_tune(Runner &R, int prec, int32_t reps, hipStream_t 
         }
     }
     // 4. the prologue of the lower levels beside the upper levels (side
-    //    stream) or entirely before the sweep
-    {
+    //    stream), also cut into one part per upper level, or entirely before
+    //    the sweep
+    for (int nf_form : {2, 1}) {
         Tuning nf = best;
-        nf.no_fork = 1;
+        nf.no_fork = nf_form;
         R.tune[prec] = nf;
         if ((st = tune_measure(R, prec, s, reps, false, t, nullptr, err))) return st;
         if (t < t_best) {
@@ -2306,7 +2336,7 @@ static selinv_status runner_tune(Runner &R, int prec, int32_t reps, hipStream_t 
     }
     // 5. with a side stream: its tile inversions in chunks of a multiple of
     //    the compute-unit count, or in one launch
-    if (!best.no_fork) {
+    if (best.no_fork != 1) {
         R.tune[prec] = best;
         runner_drop(R, prec);
         if ((st = runner_ensure(R, prec, err))) return st;
@@ -2386,7 +2416,8 @@ static selinv_status runner_set_tuning(Runner &R, int prec, const int32_t *in, i
     const int ver = in && count > 0 ? in[0] : 0, hd = ver >= 3 ? 8 : ver == 2 ? 7 : 6, pl = ver == 4 ? 4 : 3;
     bool ok = in && ver >= 1 && ver <= 4 && count == hd + pl * L && in[1] == L && in[2] >= SWEEP_AUTO &&
               in[2] <= SWEEP_PERSISTENT && tile_ok(in[3]) && tile_ok(in[4]) && tile_ok(in[5]) &&
-              (ver == 1 || in[6] == 0 || in[6] == 1) && (ver < 3 || (in[7] >= 0 && in[7] <= (1 << 20)));
+              (ver == 1 || in[6] == 0 || in[6] == 1 || (ver == 4 && in[6] == 2)) &&
+              (ver < 3 || (in[7] >= 0 && in[7] <= (1 << 20)));
     for (int d = 0; ok && d < L; d++)
         ok = tile_ok(in[hd + pl * d]) && tile_ok(in[hd + 1 + pl * d]) &&
              (in[hd + 2 + pl * d] == 0 || in[hd + 2 + pl * d] == 1) &&

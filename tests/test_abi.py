@@ -315,13 +315,16 @@ def test_tuning_table_set_get_and_validation(si):
     assert s.get_tuning("mixed_bf16x3") == table[:6] + [0, 0] + stored
     bad = [table[:-1], [5] + table[1:], table[:1] + [L + 1] + table[2:], table[:3] + [48] + table[4:],
            table[:10] + [2] + table[11:], table[:11] + [2] + table[12:], table[:2] + [3] + table[3:],
-           table[:6] + [2] + table[7:], table[:7] + [-1] + table[8:], table[:7] + [(1 << 20) + 1] + table[8:],
-           v2[:-1], v3 + [0]]
+           table[:6] + [3] + table[7:], table[:7] + [-1] + table[8:], table[:7] + [(1 << 20) + 1] + table[8:],
+           v2[:-1], v3 + [0], v3[:6] + [2] + v3[7:]]
     for b in bad:
         with pytest.raises(si.SelinvError) as e:
             s.set_tuning(b, "mixed_fp32")
         assert e.value.status == "INVALID_ARG"
     assert s.get_tuning("mixed_fp32") == table  # unchanged by the rejected tables
+    per_level = table[:6] + [2] + table[7:]  # one prologue part per upper level
+    s.set_tuning(per_level, "mixed_fp32")
+    assert s.get_tuning("mixed_fp32") == per_level
     s.set_tuning([], "mixed_fp32")
     assert s.get_tuning("mixed_fp32") == []
     # both sweep forms for an exact analysis too
@@ -345,6 +348,8 @@ def test_autotune_describe():
     d = describe([4, 2, 1, 64, 32, 32, 0, 512, 32, 64, 0, 1, 128, 128, 1, 0])
     assert d["steps35_tiles"] == [32, 128] and d["step4_tiles"] == [64, 128]
     assert d["small_per_phase_levels"] == [1] and d["gather_in_products_levels"] == [0]
+    assert not d["prologue_part_per_level"]
+    assert describe([4, 1, 1, 0, 0, 0, 2, 0, 0, 0, 0, 0])["prologue_part_per_level"]
 
 
 def test_gather_form_argument(si):

@@ -592,6 +592,30 @@ def test_side_inversion_chunks_bitwise_c1(si, c1_pair):
     s.set_tuning([], "fp64")
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed_bf16x3"])
+def test_prologue_part_per_level_bitwise(si, c1_pair, split_pair, prec):
+    """One side-stream prologue part per upper level, each joined before its
+    level, gives bitwise the results of the prologue before the sweep,
+    eager and from the HIP graph (each part writes only its own supernodes'
+    blocks)."""
+    for w, s, o in (c1_pair, split_pair):
+        L = s.info["nlevels"]
+        say("prologue parts", w.name, prec)
+        s.set_tuning([4, L, 1, 0, 0, 0, 1, 0] + [0, 0, 0, 0] * L, prec)
+        s.run(prec)
+        ref = s.export()[2]
+        s.set_tuning([4, L, 1, 0, 0, 0, 2, 0] + [0, 0, 0, 0] * L, prec)
+        s.run(prec)
+        assert np.array_equal(s.export()[2], ref)
+        for _ in range(3):
+            s.run(prec, graph=True)
+            assert np.array_equal(s.export()[2], ref)
+        s.set_tuning([4, L, 1, 0, 0, 0, 2, 37] + [0, 0, 0, 1] * L, prec)  # chunks, G in products
+        s.run(prec, graph=True)
+        assert np.array_equal(s.export()[2], ref)
+        s.set_tuning([], prec)
+
+
 def test_tune_exact_upwind_and_cache(si, tmp_path):
     from paper_1708_04539_amd.autotune import tuned
     from workloads import config_upwind
