@@ -378,6 +378,30 @@ void add_tiles(std::vector<GemmTile> &tiles, int prob, int M, int N, int T) {
         for (int n0 = 0; n0 < N; n0 += T) tiles.push_back(GemmTile{prob, m0, n0, 0});
 }
 
+// A launch with triangular operands (GemmProb::ktri: the normalisation and
+// the diagonal initialisation) has tiles of very different k ranges (a tile
+// of output columns n0.. runs k from n0).  Longest first, dealt round robin
+// over the 8 per-XCD ranges of the list (gemm.hip, xcd_tile): every XCD gets
+// the same mix of lengths, and runs its share longest first.
+void order_by_k_length(const std::vector<GemmProb> &probs, std::vector<GemmTile> &tiles, const Range &r) {
+    bool tri = false;
+    for (int i = 0; i < r.count && !tri; i++) tri = probs[tiles[r.off + i].prob].ktri != 0;
+    if (!tri || r.count < 2) return;
+    auto len = [&](const GemmTile &t) {
+        const GemmProb &p = probs[t.prob];
+        const int klo = std::max((p.ktri & 1) ? t.n0 : 0, (p.ktri & 2) ? t.m0 : 0);
+        return std::max(p.K - klo, 0);
+    };
+    std::vector<GemmTile> sorted(tiles.begin() + r.off, tiles.begin() + r.off + r.count);
+    std::stable_sort(sorted.begin(), sorted.end(),
+                     [&](const GemmTile &a, const GemmTile &b) { return len(a) > len(b); });
+    const int n = r.count, q = n / 8, rem = n % 8;
+    for (int j = 0; j < n; j++) {
+        const int x = j % 8, i = j / 8;
+        tiles[r.off + x * q + std::min(x, rem) + i] = sorted[j];
+    }
+}
+
 // Tiles of one GEMM launch over problems [first, probs.size()).  The output
 // tile is the largest that still gives the launch about two workgroups per
 // compute unit: a workgroup runs the whole k range of its tile, so a launch
@@ -404,6 +428,7 @@ void emit_launch(const std::vector<GemmProb> &probs, size_t first, std::vector<G
     r.off = tiles.size();
     for (size_t q = first; q < probs.size(); q++) add_tiles(tiles, (int)q, probs[q].M, probs[q].N, r.tile);
     r.count = (int)(tiles.size() - r.off);
+    order_by_k_length(probs, tiles, r);
 }
 
 // As emit_launch, over the problems listed in `idx` (in that order).
