@@ -144,7 +144,9 @@ def phase_profile(s, prec, stream, reps=5):
             launches.append({"cls": "gather", "tile": 64, "level": d, "ms": float(t[4 + 4 * d]), "flops": 0.0,
                              "bytes": lev[d]["bytes_gather"], "peak_tf": bulk})
         if lev[d]["tiles35"] > 0:
-            launches.append({"cls": "gemm35", "tile": int(lev[d]["tile35"]), "level": d,
+            # gather_fused == 2: the level's products read G_K from its sources (gemm_g35)
+            cls35 = "gemm35g" if lev[d]["gather_fused"] == 2 else "gemm35"
+            launches.append({"cls": cls35, "tile": int(lev[d]["tile35"]), "level": d,
                              "ms": float(t[5 + 4 * d]), "flops": lev[d]["flops35"], "bytes": lev[d]["bytes35"],
                              "peak_tf": bulk, "max_prod_flops": lev[d]["max_prod_flops"]})
         if lev[d]["tiles4"] > 0:
@@ -157,6 +159,7 @@ def phase_profile(s, prec, stream, reps=5):
 KERNEL_SYMBOL = {
     # (class, precision, tile) -> kernel symbol as rocprofv3 prints it
     "gemm35": "selinv::gemm_v2<{mode}, {t}, {t}, {T}, {T}, 1>",
+    "gemm35g": "selinv::gemm_g35<{mode}, {t}, {t}, {T}>",
     "gemm4": "selinv::step4_gather<{mode}, {t}, {t}, {T}>",
     "gather": "selinv::gather_kernel<{T}>",
     "small": "selinv::small_kernel<{mode}>",
@@ -212,7 +215,7 @@ def largest_product(ph, prec):
     """The steps-3/5 launch of the level that holds the largest single
     supernode product: its useful rate and, for split-BF16, the rate of the
     BF16 products it issues (three per useful product)."""
-    g35 = [l for l in ph["launches"] if l["cls"] == "gemm35"]
+    g35 = [l for l in ph["launches"] if l["cls"] in ("gemm35", "gemm35g")]
     if not g35:
         return None
     l = max(g35, key=lambda x: (x["max_prod_flops"], x["flops"]))
