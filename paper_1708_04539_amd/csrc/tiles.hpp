@@ -65,11 +65,16 @@ struct ChunkK {
     static constexpr int value = (BM == 32 && MODE != CMP_BF16X3) ? 32 : Mode<MODE>::BK;
 };
 
+// Rows of FP64 chunks are padded by one element: the staging stores of the
+// k-contiguous operands (16 lanes along k, one 8-byte element each) then fall
+// on 16 distinct bank pairs, where a stride of BM + 2 elements put k and
+// k + 8 on the same pair.
 template <int MODE, int BM, int BN, int BK = ChunkK<MODE, BM>::value>
 struct Smem {
     typedef typename Mode<MODE>::T T;
-    T a[2][BK][BM + 2];
-    T b[2][BK][BN + 2];
+    static constexpr int PAD = sizeof(T) == 8 ? 1 : 2;
+    T a[2][BK][BM + PAD];
+    T b[2][BK][BN + PAD];
 };
 template <int BM, int BN, int BK>
 struct Smem<CMP_BF16X3, BM, BN, BK> {
@@ -92,7 +97,15 @@ struct SplitKRows {
         v4 reg[NT];
     };
     const SELINV_GLOBAL TA *ptr[NT];
-    __device__ __forceinline__ int row(int t) const { return (int)(threadIdx.x >> 3) + 32 * t; }
+    // Row of element t: the 8-lane groups of one 16-lane store phase take
+    // rows 4 apart (group 8p + q -> row 8p + q / 2 + 4 (q & 1)), whose 64-byte
+    // spans of the 80-byte padded rows fall on disjoint banks; consecutive
+    // rows (one group each) would overlap on four banks.
+    __device__ __forceinline__ int row(int t) const {
+        const int g = (int)(threadIdx.x >> 3), q = g & 7;
+        return (g & ~7) + (q >> 1) + 4 * (q & 1) + 32 * t;
+    }
+    static __device__ __forceinline__ int swz(int) { return 0; }  // k blocks in their own order
     __device__ __forceinline__ int kk() const { return 4 * (int)(threadIdx.x & 7); }
     // row r of the operand starts at base + r ld (rows clamped into [0, rows))
     __device__ __forceinline__ void init(const void *base, int64_t ld, int r0, int rows) {
@@ -137,6 +150,12 @@ struct SplitKRows {
 // KB = R / 32 consecutive k (4, 2 or 1) of every 32-wide chunk, loads it as KB
 // 16-byte row quads (one per k) and writes it transposed, one store of KB
 // values per row and plane.
+// The lanes of one store write rows 4 apart, which fall on only two bank
+// groups of the padded rows; row r therefore keeps its 8-wide k blocks in
+// the order kb ^ swz(r) (swz(r) = 8 ((r >> 3) & 3)), which spreads one
+// store over eight bank groups and leaves the MFMA operand reads (8
+// consecutive rows, one k block) as they were.  The readers of such a tile
+// apply the same order (gemm_tile_op).
 template <int R, typename TA>
 struct SplitMRows {
     static constexpr int KB = R / 32;
@@ -151,6 +170,7 @@ struct SplitMRows {
         v4 reg[KB];
     };
     __device__ __forceinline__ int r4() const { return 4 * (int)(threadIdx.x % TPK); }
+    static __device__ __forceinline__ int swz(int r) { return 8 * ((r >> 3) & 3); }
     __device__ __forceinline__ int kq() const { return KB * (int)(threadIdx.x / TPK); }
     // element (r, k) of the operand at base + r + k ld
     __device__ __forceinline__ void init(const void *base, int64_t ld_, int r0_, int rows_) {
@@ -189,8 +209,9 @@ struct SplitMRows {
                 h[e] = b;
                 l[e] = (__bf16)(v - (float)b);
             }
-            *(vkb *)&hi[r4() + q][kq()] = h;
-            *(vkb *)&lo[r4() + q][kq()] = l;
+            const int r = r4() + q, kp = kq() ^ swz(r);
+            *(vkb *)&hi[r][kp] = h;
+            *(vkb *)&lo[r][kp] = l;
         }
     }
 };
@@ -373,18 +394,26 @@ __device__ __forceinline__ void gemm_tile_op(const GemmProb &p, const int m0, co
             else
                 va.store(rva[S], sm.ah[buf], sm.al[buf], k0, K);
         } else {
+            // a chunk inside the operand is stored without the bound selects
+            auto put_a = [&](auto MASK_) {
+                constexpr bool MASK = decltype(MASK_)::value;
 #pragma unroll
-        for (int t = 0; t < LA; t++) {
-            const int i = ai(t), k = ak(t);
-            const T v = (m0 + i < M && k0 + k < K) ? (T)ra[S][t] : (T)0;
-            if constexpr (MODE == CMP_BF16X3) {
-                const __bf16 h = (__bf16)v;
-                sm.ah[buf][i][k] = h;
-                sm.al[buf][i][k] = (__bf16)(v - (float)h);
-            } else {
-                sm.a[buf][k][i] = v;
-            }
-        }
+                for (int t = 0; t < LA; t++) {
+                    const int i = ai(t), k = ak(t);
+                    const T v = (!MASK || (m0 + i < M && k0 + k < K)) ? (T)ra[S][t] : (T)0;
+                    if constexpr (MODE == CMP_BF16X3) {
+                        const __bf16 h = (__bf16)v;
+                        sm.ah[buf][i][k] = h;
+                        sm.al[buf][i][k] = (__bf16)(v - (float)h);
+                    } else {
+                        sm.a[buf][k][i] = v;
+                    }
+                }
+            };
+            if (m0 + BM <= M && k0 + BK <= K)
+                put_a(std::false_type{});
+            else
+                put_a(std::true_type{});
         }
         if constexpr (VB) {
             if constexpr (OPB == 0)
@@ -392,18 +421,25 @@ __device__ __forceinline__ void gemm_tile_op(const GemmProb &p, const int m0, co
             else
                 vb.store(rvb[S], sm.bh[buf], sm.bl[buf], k0, K);
         } else {
+            auto put_b = [&](auto MASK_) {
+                constexpr bool MASK = decltype(MASK_)::value;
 #pragma unroll
-        for (int t = 0; t < LB; t++) {
-            const int j = bj(t), k = bk(t);
-            const T v = (n0 + j < N && k0 + k < K) ? (T)rb[S][t] : (T)0;
-            if constexpr (MODE == CMP_BF16X3) {
-                const __bf16 h = (__bf16)v;
-                sm.bh[buf][j][k] = h;
-                sm.bl[buf][j][k] = (__bf16)(v - (float)h);
-            } else {
-                sm.b[buf][k][j] = v;
-            }
-        }
+                for (int t = 0; t < LB; t++) {
+                    const int j = bj(t), k = bk(t);
+                    const T v = (!MASK || (n0 + j < N && k0 + k < K)) ? (T)rb[S][t] : (T)0;
+                    if constexpr (MODE == CMP_BF16X3) {
+                        const __bf16 h = (__bf16)v;
+                        sm.bh[buf][j][k] = h;
+                        sm.bl[buf][j][k] = (__bf16)(v - (float)h);
+                    } else {
+                        sm.b[buf][k][j] = v;
+                    }
+                }
+            };
+            if (n0 + BN <= N && k0 + BK <= K)
+                put_b(std::false_type{});
+            else
+                put_b(std::true_type{});
         }
     };
     auto compute = [&](int buf) {
@@ -415,14 +451,16 @@ __device__ __forceinline__ void gemm_tile_op(const GemmProb &p, const int m0, co
 #pragma unroll
                 for (int i = 0; i < TM; i++) {
                     const int r = wm * WM + i * 16 + (lane & 15);
-                    ah[i] = *(const v8bf *)&sm.ah[buf][r][kb];
-                    al[i] = *(const v8bf *)&sm.al[buf][r][kb];
+                    const int kr = (VA && OPA == 0) ? kb ^ VecA::swz(r) : kb;  // SplitMRows order
+                    ah[i] = *(const v8bf *)&sm.ah[buf][r][kr];
+                    al[i] = *(const v8bf *)&sm.al[buf][r][kr];
                 }
 #pragma unroll
                 for (int j = 0; j < TN; j++) {
                     const int c = wn * WN + j * 16 + (lane & 15);
-                    bh[j] = *(const v8bf *)&sm.bh[buf][c][kb];
-                    bl[j] = *(const v8bf *)&sm.bl[buf][c][kb];
+                    const int kc = (VB && OPB == 1) ? kb ^ VecB::swz(c) : kb;
+                    bh[j] = *(const v8bf *)&sm.bh[buf][c][kc];
+                    bl[j] = *(const v8bf *)&sm.bl[buf][c][kc];
                 }
 #pragma unroll
                 for (int i = 0; i < TM; i++)
