@@ -347,7 +347,8 @@ __device__ __forceinline__ void gemm_tile_op(const GemmProb &p, const int m0, co
     // device, where each workgroup waits on the latency of every chunk's
     // loads (two chunks in flight halve that wait); 1 for the wider tiles,
     // whose launches hide it behind other workgroups (and whose registers
-    // would cost occupancy).
+    // would cost occupancy; measured: two slots on the 128-wide split-BF16
+    // steps-3/5 tile left C4 at 15.9 ms).
     constexpr int PF = BM == 32 ? 2 : 1;
     TA ra[PF][VA ? 1 : LA], rb[PF][VB ? 1 : LB];
     typename VecA::Regs rva[PF];
