@@ -45,8 +45,11 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
     return x * q + min(x, r) + i;
 }
 
+// Occupancy: four workgroups per compute unit for the 32- and 64-wide tiles
+// (their LDS allows four; at most 128 VGPRs, which the two chunks in flight
+// of the FP64 64-wide tile would otherwise exceed), two for the 128-wide ones.
 template <int MODE, int BM, int BN, typename TA, typename TC, int ROLE>
-__global__ __launch_bounds__(256) void gemm_v2(const GemmProb *__restrict__ probs,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BM == 128 ? 2 : 4))) void gemm_v2(const GemmProb *__restrict__ probs,
                                                const GemmTile *__restrict__ tiles) {
     __shared__ Smem<MODE, BM, BN> sm;
     const GemmTile tl = tiles[xcd_tile(blockIdx.x, gridDim.x)];

@@ -345,11 +345,12 @@ __device__ __forceinline__ void gemm_tile_op(const GemmProb &p, const int m0, co
     // Register slots of the chunks loaded ahead of their LDS stage: PF = 2
     // for the 32-wide tiles, which serve the launches that cannot fill the
     // device, where each workgroup waits on the latency of every chunk's
-    // loads (two chunks in flight halve that wait); 1 for the wider tiles,
-    // whose launches hide it behind other workgroups (and whose registers
-    // would cost occupancy; measured: two slots on the 128-wide split-BF16
+    // loads (two chunks in flight halve that wait), and for the FP64 64-wide
+    // products (within 128 VGPRs, see gemm.hip); 1 for the other tiles, whose
+    // launches hide it behind other workgroups (and whose registers would
+    // cost occupancy; measured: two slots on the 128-wide split-BF16
     // steps-3/5 tile left C4 at 15.9 ms).
-    constexpr int PF = BM == 32 ? 2 : 1;
+    constexpr int PF = (BM == 32 || (MODE == CMP_F64 && BM == 64 && !GA && !PUSH)) ? 2 : 1;
     TA ra[PF][VA ? 1 : LA], rb[PF][VB ? 1 : LB];
     typename VecA::Regs rva[PF];
     typename VecB::Regs rvb[PF];
