@@ -2360,7 +2360,9 @@ static selinv_status runner_tune(Runner &R, int prec, int32_t reps, hipStream_t 
         }
     }
     // 5. with a side stream: its tile inversions in chunks of a multiple of
-    //    the compute-unit count, or in one launch
+    //    the compute-unit count (from half of it, which leaves compute units
+    //    free for the upper levels' launches, to three times), or in one
+    //    launch
     if (best.no_fork != 1) {
         R.tune[prec] = best;
         runner_drop(R, prec);
@@ -2369,7 +2371,7 @@ static selinv_status runner_tune(Runner &R, int prec, int32_t reps, hipStream_t 
         HIPCHK(err, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, R.hs[0]->device),
                "device attribute");
         if (R.sweep[prec]->split > 0 && cus > 0) {
-            for (int q : {5, 6, 7, 8, 10, 12}) {
+            for (int q : {2, 3, 4, 5, 6, 7, 8, 10, 12}) {
                 Tuning ch = best;
                 ch.side_chunk = q * cus / 4;
                 R.tune[prec] = ch;
