@@ -187,3 +187,33 @@ def test_c4_columns_every_computed_entry(si, c4, prec):
     assert len(X) > 100000
     assert max(en, ed) <= TOL[prec], (en, ed)
     assert max(rr, cr) <= tol_id, (rr, cr, tol_id)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed_bf16x3"])
+def test_c4_gather_in_products_and_tuned(si, c4, prec):
+    """At full size: every level's G_K read inside the products gives the
+    stored-G results bit for bit on the sampled columns' entries, and the
+    tuner's mix of both forms keeps them within the bar."""
+    w, s, cols = c4
+    say("c4 G in products", prec)
+    idx_i = np.concatenate([i for _, i, _ in cols])
+    idx_j = np.concatenate([np.full(len(i), j) for j, i, _ in cols])
+    R = np.concatenate([ref for _, _, ref in cols])
+    D = idx_i == idx_j
+    out = {}
+    for form in ("stored", "in_products"):
+        s.set_sweep_mode("levels")
+        s.set_gather_form(form)
+        s.run(prec)
+        assert (form == "stored") == all(s.level_stats(d)["gather_fused"] != 2 for d in range(s.info["nlevels"]))
+        out[form] = s.get_many(idx_i, idx_j)
+    assert np.array_equal(out["stored"], out["in_products"])
+    s.set_gather_form("auto")
+    s.set_sweep_mode("auto")
+    s.tune(prec, reps=1)
+    s.run(prec, graph=True)
+    X = s.get_many(idx_i, idx_j)
+    en, ed = errs(X, R, D)
+    record("c4 41 columns, tuned (G stored or in the products per level)", prec, "err_norm", en, "err_diag", ed)
+    assert max(en, ed) <= TOL[prec], (en, ed)
+    s.set_tuning([], prec)
