@@ -46,6 +46,14 @@ struct MatDev {
     // three arrays, gcA[ca_off(K) + a + b c_L]), read by the step-3/5 products
     // that take G_K from its sources instead of a stored G (GemmProb::gcode)
     const uint32_t *gcA;
+    // where the rows and columns of every G_K come from, per entry of rl / ru
+    // (index rl_off(K) + a, ru_off(K) + b).  Row r: its supernode I (row_I)
+    // and the start of row r of U(I, R_U(I)) in ZU (row_up).  Column c: its
+    // supernode J (col_J), the start of column c of the diagonal block of J
+    // less first(J), so that col_diag + r addresses row r (col_diag), and the
+    // start of column c of the L panel of J (col_low)
+    const int32_t *row_I, *col_J;
+    const int64_t *row_up, *col_diag, *col_low;
 };
 
 // gather: tile of G_K rows [a0, a0+64) x columns [b0, b0+64); entries from
@@ -58,6 +66,7 @@ struct GatherTile {
     int32_t skip, cl, cu, pad;
     int64_t g_off, c_off;       // as in SnRec
     int64_t skip_lo, skip_hi;   // elements of Zd holding the skipped diagonal block
+    int64_t rl_off, ru_off;     // as in SnRec
 };
 
 // C = alpha * op(A) op(B) + beta * Cin, column-major, op = N (0) or T (1)

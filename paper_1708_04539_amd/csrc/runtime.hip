@@ -296,6 +296,9 @@ struct selinv_handle_s {
     int64_t ca_total = 0;
     uint32_t *d_gcA = nullptr;
     int ca_state = 0;
+    // row and column source records of the gather (MatDev::row_I ...)
+    int32_t *d_row_I = nullptr, *d_col_J = nullptr;
+    int64_t *d_row_up = nullptr, *d_col_diag = nullptr, *d_col_low = nullptr;
     int64_t *d_push_off = nullptr;
     PrecBufs pb[NPREC];
     Runner run;  // the handle's own sweeps (hs = {this})
@@ -617,6 +620,11 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, const DevAlloc &al, in
         m.gcL = h->d_gcL;
         m.gcU = h->d_gcU;
         m.gcA = h->d_gcA;
+        m.row_I = h->d_row_I;
+        m.row_up = h->d_row_up;
+        m.col_J = h->d_col_J;
+        m.col_diag = h->d_col_diag;
+        m.col_low = h->d_col_low;
         m.Zd = b.Zd;
         m.ZL = b.ZL;
         m.ZU = b.ZU;
@@ -1534,6 +1542,8 @@ GatherTile gather_tile_of(selinv_handle h, int32_t mi, int32_t K, int a0, int b0
     g.g_off = r.g_off;
     g.c_off = r.c_off;
     g.skip_lo = g.skip_hi = 0;
+    g.rl_off = r.rl_off;
+    g.ru_off = r.ru_off;
     if (skip >= 0) {
         g.skip_lo = h->sn[skip].off_d;
         g.skip_hi = g.skip_lo + (int64_t)h->sn[skip].s * h->sn[skip].s;
@@ -1779,6 +1789,29 @@ static selinv_status ensure_device(selinv_handle h) {
         HIPCHK(h->err, upload(h->al, &h->d_push_pos, h->push_pos), "upload push maps");
         HIPCHK(h->err, upload(h->al, &h->d_gcL, h->gcL), "upload gather codes");
         HIPCHK(h->err, upload(h->al, &h->d_gcU, h->gcU), "upload gather codes");
+        {
+            // row and column source records of the gather tiles (see MatDev)
+            std::vector<int32_t> rI(P.rl.size()), cJ(P.ru.size());
+            std::vector<int64_t> rUp(P.rl.size()), cD(P.ru.size()), cLw(P.ru.size());
+            for (size_t x = 0; x < P.rl.size(); x++) {
+                const int32_t r = P.rl[x], I = P.supof[r];
+                const SnRec &q = h->sn[I];
+                rI[x] = I;
+                rUp[x] = q.off_u + (int64_t)(r - q.f) * q.cu;
+            }
+            for (size_t y = 0; y < P.ru.size(); y++) {
+                const int32_t c = P.ru[y], J = P.supof[c];
+                const SnRec &q = h->sn[J];
+                cJ[y] = J;
+                cD[y] = q.off_d + (int64_t)(c - q.f) * q.s - q.f;
+                cLw[y] = q.off_l + (int64_t)(c - q.f) * q.cl;
+            }
+            HIPCHK(h->err, upload(h->al, &h->d_row_I, rI), "upload gather records");
+            HIPCHK(h->err, upload(h->al, &h->d_row_up, rUp), "upload gather records");
+            HIPCHK(h->err, upload(h->al, &h->d_col_J, cJ), "upload gather records");
+            HIPCHK(h->err, upload(h->al, &h->d_col_diag, cD), "upload gather records");
+            HIPCHK(h->err, upload(h->al, &h->d_col_low, cLw), "upload gather records");
+        }
     }
     return SELINV_OK;
 }
@@ -1924,7 +1957,7 @@ static selinv_status build_lu(selinv_handle h) {
             inside(w, (int64_t)cl * cu - 1, 0, w_max);
             gemm(L0 + r.off_l, cl, 0, U0 + r.off_u, cu, 1, W0 + w, cl, cl, cu, s, -1.0, 0.0);
             for (int a0 = 0; a0 < cl; a0 += 64)
-                for (int b0 = 0; b0 < cu; b0 += 64) scs.push_back(GatherTile{0, K, a0, b0, -1, cl, cu, 0, w, -1, 0, 0});
+                for (int b0 = 0; b0 < cu; b0 += 64) scs.push_back(GatherTile{0, K, a0, b0, -1, cl, cu, 0, w, -1, 0, 0, 0, 0});
             // destinations of every entry of W_K
             const int32_t *RL = P.rl.data() + P.rl_ptr[K], *RU = P.ru.data() + P.ru_ptr[K];
             for (int b2 = 0; b2 < cu && ok; b2++) {
@@ -2948,7 +2981,8 @@ void selinv_destroy(selinv_handle h) {
                     (void *)h->d_sn, (void *)h->d_supof, (void *)h->d_rl, (void *)h->d_ru, (void *)h->d_mapL,
                     (void *)h->d_mapU, (void *)h->d_lcol, (void *)h->d_urow, (void *)h->d_aloc, (void *)h->d_aloc_c,
                     (void *)h->d_kids_ptr, (void *)h->d_kids, (void *)h->d_push_off, (void *)h->d_push_pos,
-                    (void *)h->d_gcL, (void *)h->d_gcU, (void *)h->d_gcA})
+                    (void *)h->d_gcL, (void *)h->d_gcU, (void *)h->d_gcA, (void *)h->d_row_I, (void *)h->d_row_up,
+                    (void *)h->d_col_J, (void *)h->d_col_diag, (void *)h->d_col_low})
         h->al.put(q);
     delete h;
 }

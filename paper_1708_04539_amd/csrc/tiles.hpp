@@ -678,6 +678,8 @@ __device__ __forceinline__ GatherTile gather_desc(const MatDev &M, int mat, int 
     gt.g_off = sn[K].g_off;
     gt.c_off = sn[K].c_off;
     gt.skip_lo = gt.skip_hi = 0;
+    gt.rl_off = sn[K].rl_off;
+    gt.ru_off = sn[K].ru_off;
     return gt;
 }
 
@@ -764,47 +766,36 @@ __device__ __forceinline__ void gather_tile(const MatDev &M, const GatherTile &g
         gather_tile_codes<T, STORE>(M, gt, sm);
         return;
     }
-    const int K = gt.K, a0 = gt.a0, b0 = gt.b0, skip = gt.skip;
+    const int a0 = gt.a0, b0 = gt.b0, skip = gt.skip;
     T(&tileS)[64][65] = sm.tileS;
     int32_t *rowR = sm.rowR, *rowI = sm.rowI, *colJ = sm.colJ;
     int64_t *rowUp = sm.rowUp, *rowUoff = sm.rowUoff, *colDiag = sm.colDiag, *colLow = sm.colLow,
             *colLoff = sm.colLoff;
-    const SELINV_GLOBAL SnRec *sn = gptr(M.sn);
     const int32_t sk_cl = gt.cl, sk_cu = gt.cu;
-    const int64_t sk_rl_off = sn[K].rl_off, sk_ru_off = sn[K].ru_off, sk_g_off = gt.g_off;
-    const SELINV_GLOBAL int32_t *supof = gptr(M.supof);
+    const int64_t sk_g_off = gt.g_off;
     const int tid = threadIdx.x;
     const int na = min(64, sk_cl - a0), nb = min(64, sk_cu - b0);  // both >= 1
+    // the tile's row and column records: independent loads (one round trip)
     if (tid < 64) {
-        // row a0 + tid of G: its row index r of A, supernode I, and where row
-        // r of U(I, R_U(I)) starts
         const int t = min(tid, na - 1);
-        const int64_t a = sk_rl_off + a0 + t;
-        const int32_t r = gptr(M.rl)[a];
-        const int64_t uo = gptr(M.u_rowoff)[a];
-        const int32_t I = supof[r];
-        const int32_t si_f = sn[I].f, si_cu = sn[I].cu;
-        const int64_t si_off_u = sn[I].off_u;
+        const int64_t a = gt.rl_off + a0 + t;
+        const int32_t r = gptr(M.rl)[a], I = gptr(M.row_I)[a];
+        const int64_t uo = gptr(M.u_rowoff)[a], up = gptr(M.row_up)[a];
         if (tid < na) {
             rowR[tid] = r;
             rowI[tid] = I;
-            rowUp[tid] = si_off_u + (int64_t)(r - si_f) * si_cu;
+            rowUp[tid] = up;
             rowUoff[tid] = uo + b0;
         }
     } else if (tid < 128) {
-        // column b0 + t of G: supernode J of its column c, and where column c
-        // starts in the diagonal block and in the L panel of J
         const int t = min(tid - 64, nb - 1);
-        const int64_t b = sk_ru_off + b0 + t;
-        const int32_t c = gptr(M.ru)[b];
-        const int64_t lo = gptr(M.l_coloff)[b];
-        const int32_t J = supof[c];
-        const int32_t sj_f = sn[J].f, sj_s = sn[J].s, sj_cl = sn[J].cl;
-        const int64_t sj_off_d = sn[J].off_d, sj_off_l = sn[J].off_l;
+        const int64_t b = gt.ru_off + b0 + t;
+        const int32_t J = gptr(M.col_J)[b];
+        const int64_t lo = gptr(M.l_coloff)[b], cd = gptr(M.col_diag)[b], cw = gptr(M.col_low)[b];
         if (tid - 64 < nb) {
             colJ[t] = J;
-            colDiag[t] = sj_off_d + (int64_t)(c - sj_f) * sj_s - sj_f;
-            colLow[t] = sj_off_l + (int64_t)(c - sj_f) * sj_cl;
+            colDiag[t] = cd;
+            colLow[t] = cw;
             colLoff[t] = lo + a0;
         }
     }
