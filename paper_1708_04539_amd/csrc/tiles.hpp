@@ -805,68 +805,57 @@ __device__ __forceinline__ void gather_tile(const MatDev &M, const GatherTile &g
     const SELINV_GLOBAL double *Zd = gptr(M.Zd);
     const SELINV_GLOBAL int32_t *mapL = gptr(M.mapL);
     const SELINV_GLOBAL int32_t *mapU = gptr(M.mapU);
-    // Each thread owns 16 entries of the tile.  Stage 1 reads the relative
-    // positions, stage 2 the source values; a thread waits for two memory
-    // round trips per side.  Entries outside the tile or of another kind read
-    // element 0 of the array instead (every device array holds at least one
-    // element) and discard it, so that no load sits behind a branch.
+    // Each thread owns 16 entries of the tile on each side: diagonal-block and
+    // L-side sources with the threads along the rows of G (contiguous in
+    // ZL), U-side sources with the threads along its columns (contiguous in
+    // ZU).  Both sides' relative positions are read together, then both
+    // sides' values: two memory round trips.  Entries outside the tile or of
+    // another kind read element 0 of the array instead (every device array
+    // holds at least one element) and discard it, so that no load sits
+    // behind a branch.
     constexpr int PER = 64 * 64 / 256;
     {
-        // diagonal and L-side sources, threads along the rows of G (contiguous)
-        int kind[PER];
-        int32_t mi[PER];
-        T val[PER];
+        int kind[PER];  // L side (threads along a): 1 diagonal block, 2 L panel, 0 none
+        bool up[PER];   // U side (threads along b)
 #pragma unroll
         for (int t = 0; t < PER; t++) {
-            const int e = tid + 256 * t, ia = e & 63, ib = e >> 6;
+            const int e = tid + 256 * t;
+            const int ia = e & 63, ib = e >> 6;
             kind[t] = 0;
             if (ia < na && ib < nb) {
                 const int32_t I = rowI[ia], J = colJ[ib];
                 kind[t] = I == J ? (I == skip ? 0 : 1) : (I > J ? 2 : 0);
             }
+            const int ub = e & 63, ua = e >> 6;
+            up[t] = ua < na && ub < nb && rowI[ua] < colJ[ub];
         }
+        int32_t ml[PER], mu[PER];
+#pragma unroll
+        for (int t = 0; t < PER; t++) {
+            const int e = tid + 256 * t;
+            ml[t] = mapL[kind[t] == 2 ? colLoff[e >> 6] + (e & 63) : 0];
+            mu[t] = mapU[up[t] ? rowUoff[e >> 6] + (e & 63) : 0];
+        }
+        T vl[PER], vu[PER];
 #pragma unroll
         for (int t = 0; t < PER; t++) {
             const int e = tid + 256 * t, ia = e & 63, ib = e >> 6;
-            mi[t] = mapL[kind[t] == 2 ? colLoff[ib] + ia : 0];
+            if constexpr (sizeof(T) == sizeof(double)) {
+                // one load: the diagonal blocks and the L panels hold the same type
+                const int64_t i = kind[t] == 1 ? colDiag[ib] + rowR[ia] : kind[t] == 2 ? colLow[ib] + ml[t] : 0;
+                vl[t] = (kind[t] == 1 ? (const SELINV_GLOBAL T *)Zd : ZL)[i];
+            } else {
+                const double vd = Zd[kind[t] == 1 ? colDiag[ib] + rowR[ia] : 0];
+                const T v = ZL[kind[t] == 2 ? colLow[ib] + ml[t] : 0];
+                vl[t] = kind[t] == 1 ? (T)vd : v;
+            }
+            vu[t] = ZU[up[t] ? rowUp[e >> 6] + mu[t] : 0];
         }
 #pragma unroll
         for (int t = 0; t < PER; t++) {
-            const int e = tid + 256 * t, ia = e & 63, ib = e >> 6;
-            const double vd = Zd[kind[t] == 1 ? colDiag[ib] + rowR[ia] : 0];
-            const T vl = ZL[kind[t] == 2 ? colLow[ib] + mi[t] : 0];
-            val[t] = kind[t] == 1 ? (T)vd : vl;
-        }
-#pragma unroll
-        for (int t = 0; t < PER; t++) {
-            const int e = tid + 256 * t, ia = e & 63, ib = e >> 6;
-            if (kind[t]) tileS[ib][ia] = val[t];
-        }
-    }
-    {
-        // U-side sources, threads along the columns of G (contiguous in ZU)
-        bool up[PER];
-        int32_t mi[PER];
-        T val[PER];
-#pragma unroll
-        for (int t = 0; t < PER; t++) {
-            const int e = tid + 256 * t, ib = e & 63, ia = e >> 6;
-            up[t] = ia < na && ib < nb && rowI[ia] < colJ[ib];
-        }
-#pragma unroll
-        for (int t = 0; t < PER; t++) {
-            const int e = tid + 256 * t, ib = e & 63, ia = e >> 6;
-            mi[t] = mapU[up[t] ? rowUoff[ia] + ib : 0];
-        }
-#pragma unroll
-        for (int t = 0; t < PER; t++) {
-            const int e = tid + 256 * t, ia = e >> 6;
-            val[t] = ZU[up[t] ? rowUp[ia] + mi[t] : 0];
-        }
-#pragma unroll
-        for (int t = 0; t < PER; t++) {
-            const int e = tid + 256 * t, ib = e & 63, ia = e >> 6;
-            if (up[t]) tileS[ib][ia] = val[t];
+            const int e = tid + 256 * t;
+            if (kind[t]) tileS[e >> 6][e & 63] = vl[t];
+            if (up[t]) tileS[e & 63][e >> 6] = vu[t];
         }
     }
     __syncthreads();
