@@ -273,10 +273,11 @@ selinv_status selinv_set_gather_form(selinv_handle h, int32_t form);
  *   - the prologue of the wide lower levels on a side stream beside the
  *     upper levels (also with one part per upper level), or all of the
  *     prologue before the sweep;
- *   - with the side stream, its tile inversions in one launch or in chunks
- *     of 1/2, 3/4, 1, 5/4, 3/2, 7/4, 2, 5/2 or 3 times the compute-unit
- *     count (a launch that fills the device holds the upper levels' launches
- *     back until it drains).
+ *   - with the side stream, its tile inversions on one workgroup per item
+ *     or on 1/4, 1/2, 3/4, 1, 5/4, 3/2, 7/4, 2, 5/2 or 3 times the
+ *     compute-unit count of workgroups, each looping over items (a launch
+ *     that fills the device holds the upper levels' launches back until it
+ *     drains).
  * Each configuration runs reps + 1 times (the first untimed; 1 <= reps <=
  * 100) and counts its fastest run: per-launch times from eager runs with
  * events, whole-sweep comparisons from replays of the sweep's HIP graph.  When the measured choices are not faster

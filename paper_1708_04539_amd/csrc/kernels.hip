@@ -190,10 +190,8 @@ __device__ __forceinline__ void tri_fused_epilogue(TriSmem<NB> &sm, const TriIte
 }
 
 template <int NB>
-__global__ __launch_bounds__(256) void tri_base_kernel(const TriItem *__restrict__ items) {
+__device__ __forceinline__ void tri_base_item(const TriItem &it, TriSmem<NB> &sm) {
     constexpr int W = 16 * NB;
-    __shared__ TriSmem<NB> sm;
-    const TriItem it = items[blockIdx.x];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int s = it.s, o = it.j0, b = min(W, s - o);
     {
@@ -264,6 +262,19 @@ __global__ __launch_bounds__(256) void tri_base_kernel(const TriItem *__restrict
             for (int r = lane; r < o; r += 64) Linv[r + (int64_t)(o + c) * s] = 0.0;
         if (lane < b)
             for (int c = wave; c < o; c += 4) Uinv[(o + lane) + (int64_t)c * s] = 0.0;
+    }
+}
+
+// Items [0, count), item b + q gridDim.x to workgroup b: a launch with fewer
+// workgroups than items keeps at most that many resident (the side-stream
+// inversion of the leaves, beside the level chain: one 64-wide workgroup takes
+// half the LDS of a compute unit).
+template <int NB>
+__global__ __launch_bounds__(256) void tri_base_kernel(const TriItem *__restrict__ items, int count) {
+    __shared__ TriSmem<NB> sm;
+    for (int b = blockIdx.x; b < count; b += gridDim.x) {
+        tri_base_item<NB>(items[b], sm);
+        __syncthreads();  // LDS free for the next item
     }
 }
 
@@ -346,14 +357,15 @@ __global__ __launch_bounds__(256) void extract_kernel(ExtractArgs a) {
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-hipError_t launch_tri_base(const TriItem *items, int count, int nb, hipStream_t st) {
+hipError_t launch_tri_base(const TriItem *items, int count, int nb, hipStream_t st, int max_groups) {
     if (count <= 0) return hipSuccess;
+    const int grid = max_groups > 0 ? std::min(count, max_groups) : count;
     if (nb == 1)
-        hipLaunchKernelGGL(tri_base_kernel<1>, dim3(count), dim3(256), 0, st, items);
+        hipLaunchKernelGGL(tri_base_kernel<1>, dim3(grid), dim3(256), 0, st, items, count);
     else if (nb == 2)
-        hipLaunchKernelGGL(tri_base_kernel<2>, dim3(count), dim3(256), 0, st, items);
+        hipLaunchKernelGGL(tri_base_kernel<2>, dim3(grid), dim3(256), 0, st, items, count);
     else if (nb == 4)
-        hipLaunchKernelGGL(tri_base_kernel<4>, dim3(count), dim3(256), 0, st, items);
+        hipLaunchKernelGGL(tri_base_kernel<4>, dim3(grid), dim3(256), 0, st, items, count);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

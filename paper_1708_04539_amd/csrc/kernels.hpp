@@ -13,7 +13,8 @@ constexpr int TRI_MAX_S = 1024;
 // diagonal 64x64 sub-blocks of the triangular inverses, one item per sub-block
 // (TriItem.j0 = first row/column of the sub-block); nb = 1 or 2: 16- or
 // 32-wide blocks, for fused items of at most that many columns only
-hipError_t launch_tri_base(const TriItem *items, int count, int nb, hipStream_t st);
+// max_groups > 0: at most that many workgroups, each looping over items
+hipError_t launch_tri_base(const TriItem *items, int count, int nb, hipStream_t st, int max_groups = 0);
 // output tile of the grouped GEMM
 enum : int { GEMM_TILE_32 = 32, GEMM_TILE_64 = 64, GEMM_TILE_128 = 128 };
 

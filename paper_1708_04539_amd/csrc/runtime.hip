@@ -111,10 +111,10 @@ struct Sweep {
     std::vector<int> pro_level;
     int split = 0;
     hipStream_t side = nullptr;
-    // tile-inversion items per launch on the side stream (0: one launch).  A
+    // tile-inversion workgroups on the side stream (0: one per item).  A
     // launch that fills every compute unit leaves the upper levels' launches
-    // waiting for slots until it drains; cut into chunks, the side stream
-    // frees slots between its launches.
+    // waiting for slots until it drains; with fewer workgroups than items,
+    // each looping over items, the side stream keeps compute units free.
     int side_chunk = 0;
     hipEvent_t ev_fork = nullptr;
     std::vector<hipEvent_t> ev_part;  // [i]: part i done (i >= 1)
@@ -187,7 +187,7 @@ struct Tuning {
     int sweep = SWEEP_AUTO;         // SWEEP_LEVELS / SWEEP_PERSISTENT, or the handle's own mode
     int no_fork = 0;                // 1: the whole prologue before the sweep, no side stream;
                                     // 2: one side-stream part per level above the split
-    int side_chunk = 0;             // tile-inversion items per launch on the side stream (0: one launch)
+    int side_chunk = 0;             // tile-inversion workgroups on the side stream (0: one per item)
 };
 
 constexpr int NPREC = 3;
@@ -1263,13 +1263,10 @@ hipError_t launch_sweep(const Sweep &S, hipStream_t st, std::vector<hipEvent_t> 
     };
     // prologue parts: diagonal-block inversion (base blocks and doubling
     // rounds), normalisation, diagonal initialisation
+    // on the side stream, at most side_chunk inversion workgroups resident
+    // (each loops over items), so that the level chain finds free compute units
     auto tri_launch = [&](const Range &r, int nb, hipStream_t s) -> hipError_t {
-        const int chunk = (s == S.side && S.side_chunk > 0) ? S.side_chunk : r.count;
-        for (int o = 0; o < r.count; o += chunk) {
-            hipError_t e2 = launch_tri_base(S.d_tri + r.off + o, std::min(chunk, r.count - o), nb, s);
-            if (e2) return e2;
-        }
-        return hipSuccess;
+        return launch_tri_base(S.d_tri + r.off, r.count, nb, s, s == S.side ? S.side_chunk : 0);
     };
     auto tri_part = [&](const Sweep::Prologue &P, hipStream_t s) -> hipError_t {
         hipError_t e2;
@@ -1293,7 +1290,12 @@ hipError_t launch_sweep(const Sweep &S, hipStream_t st, std::vector<hipEvent_t> 
     };
     // The side parts are forked after the main part, so that the main part
     // (needed first) does not share the device with them.  A profiled run
-    // runs every part on the run's stream, phase by phase.
+    // runs every part on the run's stream, phase by phase.  The side parts
+    // are issued after the first level's launches: a graph captured from
+    // this order keeps the level chain, which is the critical path, on the
+    // queue that ran the main part, and the side branch takes the cross-queue
+    // wait of the fork (tens of microseconds when a graph branch starts on
+    // another queue).  Every side part is first needed at level 1 or later.
     const int npro = (int)S.pro.size();
     const bool fork = npro > 1 && ev == nullptr;
     const int nmain = fork ? 1 : npro;
@@ -1307,16 +1309,20 @@ hipError_t launch_sweep(const Sweep &S, hipStream_t st, std::vector<hipEvent_t> 
     for (int q = 0; q < nmain; q++)
         if ((e = dt_part(S.pro[q], st))) return e;
     mark(3);
-    if (fork) {
-        if ((e = hipEventRecord(S.ev_fork, st))) return e;
-        if ((e = hipStreamWaitEvent(S.side, S.ev_fork, 0))) return e;
+    if (fork && (e = hipEventRecord(S.ev_fork, st))) return e;
+    bool side_due = fork;
+    auto side_parts = [&]() -> hipError_t {
+        side_due = false;
+        hipError_t e2;
+        if ((e2 = hipStreamWaitEvent(S.side, S.ev_fork, 0))) return e2;
         for (int q = 1; q < npro; q++) {
-            if ((e = tri_part(S.pro[q], S.side))) return e;
-            if ((e = norm_part(S.pro[q], S.side))) return e;
-            if ((e = dt_part(S.pro[q], S.side))) return e;
-            if ((e = hipEventRecord(S.ev_part[q], S.side))) return e;
+            if ((e2 = tri_part(S.pro[q], S.side))) return e2;
+            if ((e2 = norm_part(S.pro[q], S.side))) return e2;
+            if ((e2 = dt_part(S.pro[q], S.side))) return e2;
+            if ((e2 = hipEventRecord(S.ev_part[q], S.side))) return e2;
         }
-    }
+        return hipSuccess;
+    };
     if (S.persistent) {
         PersistArgs a;
         a.tasks = S.d_ptasks;
@@ -1328,12 +1334,14 @@ hipError_t launch_sweep(const Sweep &S, hipStream_t st, std::vector<hipEvent_t> 
         a.err = S.d_cnt + S.ncnt + 1;
         a.mats = S.d_mats;
         a.probs = S.d_probs;
+        if (side_due && (e = side_parts())) return e;
         if (fork && (e = hipStreamWaitEvent(st, S.ev_part[npro - 1], 0))) return e;
         if ((e = launch_persist(mode, a, S.ncnt, S.grid, st))) return e;
         for (size_t d = 0; d < 4 * S.gat.size(); d++) mark(4 + d);
         return hipSuccess;
     }
     for (size_t d = 0; d < S.gat.size(); d++) {
+        if (side_due && d > 0 && (e = side_parts())) return e;
         if (fork)
             for (int q = 1; q < npro; q++)
                 if (S.pro_level[q] == (int)d && (e = hipStreamWaitEvent(st, S.ev_part[q], 0))) return e;
@@ -1357,6 +1365,11 @@ hipError_t launch_sweep(const Sweep &S, hipStream_t st, std::vector<hipEvent_t> 
         if ((e = launch_splitk_reduce(S.d_red + S.red4[d].off, S.red4[d].count, S.red4_mn[d], S.d_mats, st)))
             return e;
         mark(7 + 4 * d);
+    }
+    if (side_due) {  // a sweep with no level past the first: join the side parts here
+        if ((e = side_parts())) return e;
+        for (int q = 1; q < npro; q++)
+            if ((e = hipStreamWaitEvent(st, S.ev_part[q], 0))) return e;
     }
     return hipSuccess;
 }
@@ -2392,10 +2405,10 @@ static selinv_status runner_tune(Runner &R, int prec, int32_t reps, hipStream_t 
             t_best = t;
         }
     }
-    // 5. with a side stream: its tile inversions in chunks of a multiple of
-    //    the compute-unit count (from half of it, which leaves compute units
-    //    free for the upper levels' launches, to three times), or in one
-    //    launch
+    // 5. with a side stream: its tile inversions on a number of workgroups
+    //    that is a multiple of the compute-unit count (from a quarter of it,
+    //    which leaves compute units free for the upper levels' launches, to
+    //    three times), or one workgroup per item
     if (best.no_fork != 1) {
         R.tune[prec] = best;
         runner_drop(R, prec);
@@ -2404,7 +2417,7 @@ static selinv_status runner_tune(Runner &R, int prec, int32_t reps, hipStream_t 
         HIPCHK(err, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, R.hs[0]->device),
                "device attribute");
         if (R.sweep[prec]->split > 0 && cus > 0) {
-            for (int q : {2, 3, 4, 5, 6, 7, 8, 10, 12}) {
+            for (int q : {1, 2, 3, 4, 5, 6, 7, 8, 10, 12}) {
                 Tuning ch = best;
                 ch.side_chunk = q * cus / 4;
                 R.tune[prec] = ch;
