@@ -102,8 +102,11 @@ struct GemmProb {
     double alpha, beta;
 };
 
+// n1: 0, or 1 + the first column of a second output tile of the same rows
+// that the workgroup forms after the first (gemm_v2; the normalisation pairs
+// tiles of long and short triangular k ranges)
 struct GemmTile {
-    int32_t prob, m0, n0, pad;
+    int32_t prob, m0, n0, n1;
 };
 
 // triangular inversion: one 64x64 diagonal sub-block of one supernode

@@ -55,6 +55,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BM == 128 ?
     const GemmTile tl = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     // only the step-4 product accumulates into an input matrix
     gemm_tile<MODE, BM, BN, TA, TC, ROLE == 2>(probs[tl.prob], tl.m0, tl.n0, sm);
+    if (tl.n1 > 0) {
+        __syncthreads();  // LDS free for the second tile
+        gemm_tile<MODE, BM, BN, TA, TC, ROLE == 2>(probs[tl.prob], tl.m0, tl.n1 - 1, sm);
+    }
 }
 
 // Steps 3 and 5 of a level whose G_K are not stored: op(A) is read from the

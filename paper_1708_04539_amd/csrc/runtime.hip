@@ -375,33 +375,57 @@ constexpr int kSplitKMin = 512;
 constexpr double kTile128From = 192;
 
 // row-block major: the tiles of one strip of op(A) are neighbours in the
-// list (the GEMM kernel keeps neighbours on one XCD)
-void add_tiles(std::vector<GemmTile> &tiles, int prob, int M, int N, int T) {
-    for (int m0 = 0; m0 < M; m0 += T)
-        for (int n0 = 0; n0 < N; n0 += T) tiles.push_back(GemmTile{prob, m0, n0, 0});
+// list (the GEMM kernel keeps neighbours on one XCD).  pair: a product whose
+// op(B) is lower triangular (GemmProb::ktri == 1: the normalisation) pairs
+// column block j with block J - 1 - j of the same strip in one workgroup
+// (GemmTile::n1), so that every workgroup runs about s + T of k and reads the
+// strip's rows once from HBM.
+void add_tiles(std::vector<GemmTile> &tiles, int prob, int M, int N, int T, bool pair = false) {
+    const int J = (N + T - 1) / T;
+    for (int m0 = 0; m0 < M; m0 += T) {
+        if (!pair) {
+            for (int n0 = 0; n0 < N; n0 += T) tiles.push_back(GemmTile{prob, m0, n0, 0});
+            continue;
+        }
+        for (int j = 0; 2 * j < J; j++) {
+            const int j2 = J - 1 - j;
+            tiles.push_back(GemmTile{prob, m0, j * T, j2 > j ? j2 * T + 1 : 0});
+        }
+    }
 }
 
 // A launch with triangular operands (GemmProb::ktri: the normalisation and
 // the diagonal initialisation) has tiles of very different k ranges (a tile
 // of output columns n0.. runs k from n0).  Longest first, dealt round robin
 // over the 8 per-XCD ranges of the list (gemm.hip, xcd_tile): every XCD gets
-// the same mix of lengths, and runs its share longest first.
+// the same mix of lengths, and runs its share longest first.  Paired tiles
+// (GemmTile::n1) are dealt in runs of 4 list neighbours, which keeps the
+// pairs of one strip on one XCD.
 void order_by_k_length(const std::vector<GemmProb> &probs, std::vector<GemmTile> &tiles, const Range &r) {
-    bool tri = false;
-    for (int i = 0; i < r.count && !tri; i++) tri = probs[tiles[r.off + i].prob].ktri != 0;
+    bool tri = false, paired = false;
+    for (int i = 0; i < r.count; i++) {
+        tri = tri || probs[tiles[r.off + i].prob].ktri != 0;
+        paired = paired || tiles[r.off + i].n1 > 0;
+    }
     if (!tri || r.count < 2) return;
+    auto len1 = [&](const GemmProb &p, int m0, int n0) {
+        const int klo = std::max((p.ktri & 1) ? n0 : 0, (p.ktri & 2) ? m0 : 0);
+        return std::max(p.K - klo, 0);
+    };
     auto len = [&](const GemmTile &t) {
         const GemmProb &p = probs[t.prob];
-        const int klo = std::max((p.ktri & 1) ? t.n0 : 0, (p.ktri & 2) ? t.m0 : 0);
-        return std::max(p.K - klo, 0);
+        return len1(p, t.m0, t.n0) + (t.n1 > 0 ? len1(p, t.m0, t.n1 - 1) : 0);
     };
     std::vector<GemmTile> sorted(tiles.begin() + r.off, tiles.begin() + r.off + r.count);
     std::stable_sort(sorted.begin(), sorted.end(),
                      [&](const GemmTile &a, const GemmTile &b) { return len(a) > len(b); });
-    const int n = r.count, q = n / 8, rem = n % 8;
+    const int n = r.count, q = n / 8, rem = n % 8, run = paired ? 4 : 1;
+    int fill[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int x = 0;
     for (int j = 0; j < n; j++) {
-        const int x = j % 8, i = j / 8;
-        tiles[r.off + x * q + std::min(x, rem) + i] = sorted[j];
+        if (j > 0 && j % run == 0) x = (x + 1) % 8;
+        while (fill[x] >= q + (x < rem ? 1 : 0)) x = (x + 1) % 8;  // range of XCD x full
+        tiles[r.off + x * q + std::min(x, rem) + fill[x]++] = sorted[j];
     }
 }
 
@@ -413,7 +437,7 @@ void order_by_k_length(const std::vector<GemmProb> &probs, std::vector<GemmTile>
 // launches large enough to fill the device a few times over and wasting
 // little of their area.
 void emit_launch(const std::vector<GemmProb> &probs, size_t first, std::vector<GemmTile> &tiles, Range &r,
-                 bool allow128 = false, int forced = 0) {
+                 bool allow128 = false, int forced = 0, bool pair_lower = false) {
     double area = 0, t128 = 0, t64 = 0;
     for (size_t q = first; q < probs.size(); q++) {
         const double M = probs[q].M, N = probs[q].N;
@@ -429,7 +453,8 @@ void emit_launch(const std::vector<GemmProb> &probs, size_t first, std::vector<G
     else if (allow128 && t128 >= kTile128From && area / (t128 * 128 * 128) >= 0.75 * area / (t64 * 64 * 64))
         r.tile = GEMM_TILE_128;
     r.off = tiles.size();
-    for (size_t q = first; q < probs.size(); q++) add_tiles(tiles, (int)q, probs[q].M, probs[q].N, r.tile);
+    for (size_t q = first; q < probs.size(); q++)
+        add_tiles(tiles, (int)q, probs[q].M, probs[q].N, r.tile, pair_lower && probs[q].ktri == 1);
     r.count = (int)(tiles.size() - r.off);
     order_by_k_length(probs, tiles, r);
 }
@@ -794,7 +819,7 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, const DevAlloc &al, in
         // FP32 normalised panels and need a second kernel for the FP64
         // diagonal.
         if (prec != SELINV_FP64) {
-            emit_launch(probs, first, tiles, PR.norm, false, tn ? tn->norm : 0);
+            emit_launch(probs, first, tiles, PR.norm, false, tn ? tn->norm : 0, true);
             first = probs.size();
         }
         for (size_t mi = 0; mi < hs.size(); mi++) {
@@ -809,7 +834,7 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, const DevAlloc &al, in
             }
         }
         if (prec == SELINV_FP64)
-            emit_launch(probs, first, tiles, PR.norm, false, tn ? tn->norm : 0);
+            emit_launch(probs, first, tiles, PR.norm, false, tn ? tn->norm : 0, true);
         else
             emit_launch(probs, first, tiles, PR.dt, false, tn ? tn->dt : 0);
     }
