@@ -265,15 +265,30 @@ __device__ __forceinline__ void tri_base_item(const TriItem &it, TriSmem<NB> &sm
     }
 }
 
+// One item per workgroup.
+template <int NB>
+__global__ __launch_bounds__(256) void tri_base_kernel(const TriItem *__restrict__ items) {
+    __shared__ TriSmem<NB> sm;
+    tri_base_item<NB>(items[blockIdx.x], sm);
+}
+
 // Items [0, count), item b + q gridDim.x to workgroup b: a launch with fewer
 // workgroups than items keeps at most that many resident (the side-stream
 // inversion of the leaves, beside the level chain: one 64-wide workgroup takes
-// half the LDS of a compute unit).
+// half the LDS of a compute unit).  The item is a call: inlined into the
+// loop, the item's per-lane LDS addresses are hoisted out of it and held
+// across iterations, which more than triples the kernel's registers.
 template <int NB>
-__global__ __launch_bounds__(256) void tri_base_kernel(const TriItem *__restrict__ items, int count) {
+__device__ __attribute__((noinline)) void tri_base_item_call(const TriItem *__restrict__ items, int b,
+                                                             TriSmem<NB> &sm) {
+    tri_base_item<NB>(items[b], sm);
+}
+
+template <int NB>
+__global__ __launch_bounds__(256) void tri_base_loop_kernel(const TriItem *__restrict__ items, int count) {
     __shared__ TriSmem<NB> sm;
     for (int b = blockIdx.x; b < count; b += gridDim.x) {
-        tri_base_item<NB>(items[b], sm);
+        tri_base_item_call<NB>(items, b, sm);
         __syncthreads();  // LDS free for the next item
     }
 }
@@ -359,15 +374,22 @@ __global__ __launch_bounds__(256) void extract_kernel(ExtractArgs a) {
 // ---------------------------------------------------------------------------
 hipError_t launch_tri_base(const TriItem *items, int count, int nb, hipStream_t st, int max_groups) {
     if (count <= 0) return hipSuccess;
-    const int grid = max_groups > 0 ? std::min(count, max_groups) : count;
-    if (nb == 1)
-        hipLaunchKernelGGL(tri_base_kernel<1>, dim3(grid), dim3(256), 0, st, items, count);
-    else if (nb == 2)
-        hipLaunchKernelGGL(tri_base_kernel<2>, dim3(grid), dim3(256), 0, st, items, count);
-    else if (nb == 4)
-        hipLaunchKernelGGL(tri_base_kernel<4>, dim3(grid), dim3(256), 0, st, items, count);
-    else
-        return hipErrorInvalidValue;
+    if (nb != 1 && nb != 2 && nb != 4) return hipErrorInvalidValue;
+    if (max_groups > 0 && max_groups < count) {
+        const dim3 g(max_groups);
+        if (nb == 1)
+            hipLaunchKernelGGL(tri_base_loop_kernel<1>, g, dim3(256), 0, st, items, count);
+        else if (nb == 2)
+            hipLaunchKernelGGL(tri_base_loop_kernel<2>, g, dim3(256), 0, st, items, count);
+        else
+            hipLaunchKernelGGL(tri_base_loop_kernel<4>, g, dim3(256), 0, st, items, count);
+    } else if (nb == 1) {
+        hipLaunchKernelGGL(tri_base_kernel<1>, dim3(count), dim3(256), 0, st, items);
+    } else if (nb == 2) {
+        hipLaunchKernelGGL(tri_base_kernel<2>, dim3(count), dim3(256), 0, st, items);
+    } else {
+        hipLaunchKernelGGL(tri_base_kernel<4>, dim3(count), dim3(256), 0, st, items);
+    }
     return hipGetLastError();
 }
 

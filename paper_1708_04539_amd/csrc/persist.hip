@@ -407,18 +407,27 @@ __global__ __launch_bounds__(256, 4) void small_kernel(const MatDev *__restrict_
     // step 4: A^{-T}(K,K) -= A^{-T}(K,R_U) Uhat^T (FP64 accumulation)
     if (active && pg4) {
         SELINV_GLOBAL double *C = gptr_w((double *)pg4->C);
-        for (int mb = mfirst; 16 * mb < s; mb += per) {
+        // the initial A^{-T}(K,K) of all of this wavefront's row blocks in
+        // flight together (clamped addresses), then the products
+        double cin[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            const int m = min(16 * (mfirst + i * per) + li, s - 1);
+#pragma unroll
+            for (int v = 0; v < 4; v++) cin[i][v] = C[m + (int64_t)min(n0 + MF::col(lane, v), s - 1) * pg4->ldc];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            const int mb = mfirst + i * per;
+            if (16 * mb >= s) break;
             const typename MF::Acc acc = bU.tile([&](int m, int k) { return G[k][m]; }, s, cu, 16 * mb);
             const int m = 16 * mb + li;
-            double cin[4];
-#pragma unroll
-            for (int v = 0; v < 4; v++) cin[v] = C[min(m, s - 1) + (int64_t)min(n0 + MF::col(lane, v), s - 1) * pg4->ldc];
 #pragma unroll
             for (int v = 0; v < 4; v++) {
                 const int c = n0 + MF::col(lane, v);
                 if (m >= s || c >= s) continue;
                 double r = pg4->alpha * (double)acc[v];
-                r += pg4->beta * cin[v];
+                r += pg4->beta * cin[i][v];
                 C[m + (int64_t)c * pg4->ldc] = r;
             }
         }

@@ -549,37 +549,45 @@ __device__ __forceinline__ void gemm_tile_op(const GemmProb &p, const int m0, co
         return n0 + wn * WN + j * 16 + nr;
     };
     const bool has_cin = CIN && p.Cin != nullptr;
+    // The Cin loads of CR rows of 16x16 tiles in flight together (clamped
+    // addresses): every row of the wavefront's tiles up to 16 values per lane
+    // (Cin is C itself in step 4, so later loads cannot pass the stores)
+    constexpr int CR = TM * TN <= 4 ? TM : 1;
 #pragma unroll
-    for (int i = 0; i < TM; i++) {
-        // the Cin loads of one row of 16x16 tiles in flight together
-        // (clamped addresses)
-        double cin[TN][4];
+    for (int i0 = 0; i0 < TM; i0 += CR) {
+        double cin[CR][TN][4];
         if (has_cin) {
+#pragma unroll
+            for (int ii = 0; ii < CR; ii++)
+#pragma unroll
+                for (int j = 0; j < TN; j++)
+#pragma unroll
+                    for (int v = 0; v < 4; v++) {
+                        const int64_t gm = min(m0 + wm * WM + (i0 + ii) * 16 + (lane & 15), M - 1);
+                        const int64_t gn = min(row_n(j, v), N - 1);
+                        cin[ii][j][v] = (double)Cin[gm + gn * ldcin];
+                    }
+        }
+#pragma unroll
+        for (int ii = 0; ii < CR; ii++) {
+            const int i = i0 + ii;
+            const int gm = m0 + wm * WM + i * 16 + (lane & 15);
+            if (gm >= M) continue;
+            // complex blocks: the entry of the odd column that this one gives
+            const double csign = (gm & 1) ? -1.0 : 1.0;
 #pragma unroll
             for (int j = 0; j < TN; j++)
 #pragma unroll
                 for (int v = 0; v < 4; v++) {
-                    const int64_t gm = min(m0 + wm * WM + i * 16 + (lane & 15), M - 1);
-                    const int64_t gn = min(row_n(j, v), N - 1);
-                    cin[j][v] = (double)Cin[gm + gn * ldcin];
+                    const int gn = row_n(j, v);
+                    if (gn >= N) continue;
+                    double r = alpha * (double)acc[i][j][v];
+                    if (has_cin) r += beta * cin[ii][j][v];
+                    C[gm + (int64_t)gn * ldc] = (TC)r;
+                    if (p.cpx) C[(gm ^ 1) + (int64_t)gn * ldc + ldc / 2] = (TC)(csign * r);
+                    if constexpr (PUSH) acc[i][j][v] = (TC)r;  // the stored value, for the push below
                 }
         }
-        const int gm = m0 + wm * WM + i * 16 + (lane & 15);
-        if (gm >= M) continue;
-        // complex blocks: the entry of the odd column that this one gives
-        const double csign = (gm & 1) ? -1.0 : 1.0;
-#pragma unroll
-        for (int j = 0; j < TN; j++)
-#pragma unroll
-            for (int v = 0; v < 4; v++) {
-                const int gn = row_n(j, v);
-                if (gn >= N) continue;
-                double r = alpha * (double)acc[i][j][v];
-                if (has_cin) r += beta * cin[j][v];
-                C[gm + (int64_t)gn * ldc] = (TC)r;
-                if (p.cpx) C[(gm ^ 1) + (int64_t)gn * ldc + ldc / 2] = (TC)(csign * r);
-                if constexpr (PUSH) acc[i][j][v] = (TC)r;  // the stored value, for the push below
-            }
     }
     if constexpr (PUSH) {
         if (p.push_sn >= 0) {
