@@ -169,9 +169,21 @@ struct SplitMRows {
     struct Regs {  // one chunk in flight
         v4 reg[KB];
     };
-    __device__ __forceinline__ int r4() const { return 4 * (int)(threadIdx.x % TPK); }
+    // R = 128: each 16-lane store phase takes 8 row quads at two k offsets 4
+    // apart (lane bits 0-2 and 4-5: the row quad, bit 3 and 6-7: the k group),
+    // so that its 16 eight-byte stores fall on 16 distinct bank pairs; with
+    // 16 row quads at one k they met in pairs (rows 32 apart).
+    __device__ __forceinline__ int r4() const {
+        const int t = (int)threadIdx.x;
+        if constexpr (R == 128) return 4 * ((t & 7) | (((t >> 4) & 3) << 3));
+        return 4 * (t % TPK);
+    }
     static __device__ __forceinline__ int swz(int r) { return 8 * ((r >> 3) & 3); }
-    __device__ __forceinline__ int kq() const { return KB * (int)(threadIdx.x / TPK); }
+    __device__ __forceinline__ int kq() const {
+        const int t = (int)threadIdx.x;
+        if constexpr (R == 128) return KB * (((t >> 3) & 1) | ((t >> 6) << 1));
+        return KB * (t / TPK);
+    }
     // element (r, k) of the operand at base + r + k ld
     __device__ __forceinline__ void init(const void *base, int64_t ld_, int r0_, int rows_) {
         ld = ld_;
