@@ -409,7 +409,7 @@ void order_by_k_length(const std::vector<GemmProb> &probs, std::vector<GemmTile>
     }
     if (!tri || r.count < 2) return;
     auto len1 = [&](const GemmProb &p, int m0, int n0) {
-        const int klo = std::max((p.ktri & 1) ? n0 : 0, (p.ktri & 2) ? m0 : 0);
+        const int klo = std::max((p.ktri & 1) ? (p.cpx ? 2 * n0 : n0) : 0, (p.ktri & 2) ? m0 : 0);
         return std::max(p.K - klo, 0);
     };
     auto len = [&](const GemmTile &t) {
@@ -808,8 +808,14 @@ selinv_status build_sweep(std::vector<selinv_handle> &hs, const DevAlloc &al, in
                 char *Uh = (char *)b.Uh + r.off_u * e;
                 // op(B) = (L_KK)^{-1} and (U_KK)^{-T} are lower triangular: a
                 // tile of output columns n0.. needs k >= n0 only
-                add_prob(probs, h->d_lpan + r.off_l, 0, r.cl, h->d_Linv + r.off_d, 0, r.s, Lh, r.cl, nullptr, 1, r.cl,
-                         r.s, r.s, 1.0, 0.0, &X, 8, e, 1);
+                // Complex handles: Lhat = A(R_L,K) A_KK^{-1} is made of 2x2
+                // complex blocks, so its even columns are formed and the odd
+                // ones derived (op(B) = L_KK^{-1} is taken column by column;
+                // (U_KK)^{-T} as op(B) is not, so Uhat is formed whole)
+                if (add_prob(probs, h->d_lpan + r.off_l, 0, r.cl, h->d_Linv + r.off_d, 0, r.s, Lh, r.cl, nullptr, 1,
+                             r.cl, r.s, r.s, 1.0, 0.0, &X, 8, e, 1) &&
+                    h->cpx_ok)
+                    halve((int)probs.size() - 1, Lh, r.cl, r.s, e);
                 add_prob(probs, h->d_upan + r.off_u, 0, r.cu, h->d_Uinv + r.off_d, 1, r.s, Uh, r.cu, nullptr, 1, r.cu,
                          r.s, r.s, 1.0, 0.0, &X, 8, e, 1);
             }

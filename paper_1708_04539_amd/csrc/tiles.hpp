@@ -509,8 +509,8 @@ __device__ __forceinline__ void gemm_tile_op(const GemmProb &p, const int m0, co
 
     // K == 0 (C = beta Cin): no chunk, no operand read.  Chunks whose
     // products are all zero by the operands' triangular structure are
-    // skipped (p.ktri).
-    const int klo = max((p.ktri & 1) ? n0 : 0, (p.ktri & 2) ? m0 : 0);
+    // skipped (p.ktri; with p.cpx, column n of op(B) is its column 2 n).
+    const int klo = max((p.ktri & 1) ? (p.cpx ? 2 * n0 : n0) : 0, (p.ktri & 2) ? m0 : 0);
     const int c0 = min(klo / BK, nch);
     typedef std::integral_constant<int, 0> Slot0;
     typedef std::integral_constant<int, PF - 1> SlotL;
