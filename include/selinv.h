@@ -295,8 +295,9 @@ selinv_status selinv_tune(selinv_handle h, selinv_precision prec, int32_t reps, 
  *    one on a side stream beside the sweep of the levels above; 1: the whole
  *    prologue before the sweep, no side stream; 2: as 0, and every level
  *    above the first wide one its own part on the side stream, joined just
- *    before the sweep reaches that level), tile-inversion items per launch
- *    on the side stream (0: one launch; at most 2^20), then for every level
+ *    before the sweep reaches that level), tile-inversion workgroups on the
+ *    side stream, each looping over items (0: one workgroup per item; at
+ *    most 2^20), then for every level
  *    d = 0 .. nlevels-1: tile of
  *    steps 3+5, tile of step 4, 1 if the level's small supernodes use the
  *    per-phase launches, 1 if its steps 3/5 read G_K from its sources
@@ -306,7 +307,8 @@ selinv_status selinv_tune(selinv_handle h, selinv_precision prec, int32_t reps, 
  * cap < count gives SELINV_E_INVALID_ARG.  selinv_set_tuning also takes the
  * earlier layouts, all with a stored G: [3, ... as above, per level the first
  * three values] (8 + 3 nlevels values), [2, nlevels, sweep, tri, norm, dt,
- * no_fork, per level ...] (7 + 3 nlevels values, one side launch) and [1,
+ * no_fork, per level ...] (7 + 3 nlevels values, one workgroup per side
+ * inversion item) and [1,
  * nlevels, sweep, tri, norm, dt, per level ...] (6 + 3 nlevels values, side
  * stream kept). */
 selinv_status selinv_get_tuning(selinv_handle h, selinv_precision prec, int32_t *out, int32_t cap,

@@ -74,7 +74,8 @@ def tuned(s: "selinv.SelInv", precision: str = "fp64", cache_path: str | None = 
 
 
 def describe(table: list) -> dict:
-    """Readable summary of a tuning table."""
+    """Readable summary of a tuning table (side_inversion_chunk: the number of
+    workgroups of the side stream's inversion launches, 0 for one per item)."""
     if not table:
         return {"tuned": False}
     L = table[1]
