@@ -681,6 +681,7 @@ struct GatherSmem {
     T tileS[64][65];  // [b][a]
     int32_t rowR[64], rowI[64], colJ[64];
     int64_t rowUp[64], rowUoff[64], colDiag[64], colLow[64], colLoff[64];
+    uint32_t sides;  // map path: bit 0 the tile has diagonal-block or L-side entries, bit 1 U-side ones
 };
 
 // Gather tile descriptor of supernode K of matrix `mat` from its record.
@@ -796,6 +797,7 @@ __device__ __forceinline__ void gather_tile(const MatDev &M, const GatherTile &g
     const int tid = threadIdx.x;
     const int na = min(64, sk_cl - a0), nb = min(64, sk_cu - b0);  // both >= 1
     // the tile's row and column records: independent loads (one round trip)
+    if (tid == 0) sm.sides = 0;
     if (tid < 64) {
         const int t = min(tid, na - 1);
         const int64_t a = gt.rl_off + a0 + t;
@@ -837,6 +839,7 @@ __device__ __forceinline__ void gather_tile(const MatDev &M, const GatherTile &g
     {
         int kind[PER];  // L side (threads along a): 1 diagonal block, 2 L panel, 0 none
         bool up[PER];   // U side (threads along b)
+        bool anyL = false, anyU = false;
 #pragma unroll
         for (int t = 0; t < PER; t++) {
             const int e = tid + 256 * t;
@@ -848,29 +851,54 @@ __device__ __forceinline__ void gather_tile(const MatDev &M, const GatherTile &g
             }
             const int ub = e & 63, ua = e >> 6;
             up[t] = ua < na && ub < nb && rowI[ua] < colJ[ub];
+            anyL = anyL || kind[t] != 0;
+            anyU = anyU || up[t];
         }
-        int32_t ml[PER], mu[PER];
-#pragma unroll
-        for (int t = 0; t < PER; t++) {
-            const int e = tid + 256 * t;
-            ml[t] = mapL[kind[t] == 2 ? colLoff[e >> 6] + (e & 63) : 0];
-            mu[t] = mapU[up[t] ? rowUoff[e >> 6] + (e & 63) : 0];
+        // Most tiles lie on one side of the ancestors' block diagonal: the
+        // loads of a side without entries in the tile are not issued at all
+        // (uniform over the workgroup, one barrier).
+        {
+            const uint32_t mine = (__any(anyL) ? 1u : 0u) | (__any(anyU) ? 2u : 0u);
+            if ((tid & 63) == 0 && mine) atomicOr(&sm.sides, mine);
         }
+        __syncthreads();
+        const uint32_t sides = sm.sides;
         T vl[PER], vu[PER];
+        // DL / DU: the loads of that side are issued (a separate code path per
+        // combination, so that the two-sided one keeps its registers)
+        auto side_loads = [&](auto DL_, auto DU_) {
+            constexpr bool DL = decltype(DL_)::value, DU = decltype(DU_)::value;
+            int32_t ml[PER], mu[PER];
 #pragma unroll
-        for (int t = 0; t < PER; t++) {
-            const int e = tid + 256 * t, ia = e & 63, ib = e >> 6;
-            if constexpr (sizeof(T) == sizeof(double)) {
-                // one load: the diagonal blocks and the L panels hold the same type
-                const int64_t i = kind[t] == 1 ? colDiag[ib] + rowR[ia] : kind[t] == 2 ? colLow[ib] + ml[t] : 0;
-                vl[t] = (kind[t] == 1 ? (const SELINV_GLOBAL T *)Zd : ZL)[i];
-            } else {
-                const double vd = Zd[kind[t] == 1 ? colDiag[ib] + rowR[ia] : 0];
-                const T v = ZL[kind[t] == 2 ? colLow[ib] + ml[t] : 0];
-                vl[t] = kind[t] == 1 ? (T)vd : v;
+            for (int t = 0; t < PER; t++) {
+                const int e = tid + 256 * t;
+                if constexpr (DL) ml[t] = mapL[kind[t] == 2 ? colLoff[e >> 6] + (e & 63) : 0];
+                if constexpr (DU) mu[t] = mapU[up[t] ? rowUoff[e >> 6] + (e & 63) : 0];
             }
-            vu[t] = ZU[up[t] ? rowUp[e >> 6] + mu[t] : 0];
-        }
+#pragma unroll
+            for (int t = 0; t < PER; t++) {
+                const int e = tid + 256 * t, ia = e & 63, ib = e >> 6;
+                if constexpr (DL) {
+                    if constexpr (sizeof(T) == sizeof(double)) {
+                        // one load: the diagonal blocks and the L panels hold the same type
+                        const int64_t i =
+                            kind[t] == 1 ? colDiag[ib] + rowR[ia] : kind[t] == 2 ? colLow[ib] + ml[t] : 0;
+                        vl[t] = (kind[t] == 1 ? (const SELINV_GLOBAL T *)Zd : ZL)[i];
+                    } else {
+                        const double vd = Zd[kind[t] == 1 ? colDiag[ib] + rowR[ia] : 0];
+                        const T v = ZL[kind[t] == 2 ? colLow[ib] + ml[t] : 0];
+                        vl[t] = kind[t] == 1 ? (T)vd : v;
+                    }
+                }
+                if constexpr (DU) vu[t] = ZU[up[t] ? rowUp[e >> 6] + mu[t] : 0];
+            }
+        };
+        if (sides == 3)
+            side_loads(std::true_type{}, std::true_type{});
+        else if (sides == 1)
+            side_loads(std::true_type{}, std::false_type{});
+        else if (sides == 2)
+            side_loads(std::false_type{}, std::true_type{});
 #pragma unroll
         for (int t = 0; t < PER; t++) {
             const int e = tid + 256 * t;
